@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the CHYM hot path on one MI355X.
+
+Workload (default): 1000 Sherrington-Kirkpatrick +-1 instances with N = 100
+hyperspins, each run at D = 2 and at D = 3, 100 initial states x 20 pump
+values (r in [0.5, 2.0]) = 2000 replicas per (instance, D), 5000 Euler steps
+of dt = 0.01 with the linear dimensional anneal, float32 form; then sign
+readout, exact Ising energy and float64 hyperspin energy of every run.
+
+One bench step = the whole workload: reset the state to the initial
+condition (one device copy), integrate all 2000 (instance, D) tasks with the
+persistent batched kernels, score every run.  All inputs are resident in
+HBM before the timed region.
+
+Prints one JSON line (see the "metric" field); the roofline figures are for
+the dominant kernel, the persistent integrator of the D = 3 tasks, timed
+with HIP events on the stream it runs on.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spin-comp updates/s; TTS99 to Ising GS: plain FP32 vs BF16+learned stop"
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak (TFLOP/s)
+PEAK_FP32_MATRIX_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--instances", type=int, default=1000)
+    ap.add_argument("--n", type=int, default=100)
+    ap.add_argument("--dims", type=str, default="2,3")
+    ap.add_argument("--ics", type=int, default=100)
+    ap.add_argument("--pumps", type=int, default=20)
+    ap.add_argument("--euler-steps", type=int, default=5000)
+    ap.add_argument("--dt", type=float, default=0.01)
+    ap.add_argument("--precision", type=str, default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--cpu-baseline", type=int, default=1, help="0 disables the oracle timing leg")
+    ap.add_argument("--cpu-replicas", type=int, default=256)
+    return ap.parse_args()
+
+
+def build_workload(args, torch, synth, api, dev):
+    dims = [int(v) for v in args.dims.split(",")]
+    n, steps = args.n, args.euler_steps
+    R = args.ics * args.pumps
+    pumps = synth.pump_grid(args.ics, np.linspace(0.5, 2.0, args.pumps))
+    pump_d = torch.from_numpy(pumps).to(dev)
+    Js = np.stack([synth.sk_pm1(n, 1, i) for i in range(args.instances)])
+    lam = np.linalg.eigvalsh(Js.astype(np.float64))[:, -1]
+    eps = (0.5 / lam).astype(np.float32)
+    J_d = torch.from_numpy(Js).to(dev)
+    alphas = {d: torch.from_numpy(synth.anneal_schedule(steps, d)[0]).to(dev) for d in dims}
+    # one contiguous buffer for all states, and a pristine copy of the initial states
+    sizes = [n * R * d for d in dims]
+    per_inst = sum(sizes)
+    x0 = synth.initial_states_torch(args.instances * per_inst, 1, 1, seed=2308023290 + 1, device=dev).view(-1)
+    x = torch.empty_like(x0)
+    w = api.spin_words(n)
+    plans = {}
+    outs = []
+    score_tasks = []
+    for di, d in enumerate(dims):
+        tasks = []
+        for i in range(args.instances):
+            off = i * per_inst + sum(sizes[:di])
+            xv = x[off:off + sizes[di]].view(n, R, d)
+            t = dict(J=J_d[i], pump=pump_d, x=xv, alpha=alphas[d], eps=float(eps[i]), btil=1.0, eta=2e-4,
+                     dt=args.dt, steps=steps, precision=args.precision)
+            tasks.append(t)
+            o = dict(spins=torch.empty((R, w), dtype=torch.int64, device=dev),
+                     e_ising=torch.empty(R, dtype=torch.int32, device=dev),
+                     e_hs=torch.empty(R, dtype=torch.float64, device=dev),
+                     diverged=torch.empty(R, dtype=torch.uint8, device=dev))
+            outs.append((i, d, o))
+            st = dict(t)
+            st["steps"] = 0
+            st.update(o)
+            score_tasks.append(st)
+        plans[d] = api.chym_batch_create(tasks)
+    score_plan = api.chym_batch_create(score_tasks)
+    updates = sum(args.instances * n * R * d * steps for d in dims)
+    return dict(dims=dims, plans=plans, score_plan=score_plan, x=x, x0=x0, outs=outs, updates=updates, R=R,
+                Js=Js, eps=eps, pumps=pumps)
+
+
+def cpu_baseline(args, synth, wl):
+    """The FP64 oracle on a bounded sample of the same workload."""
+    import oracle
+
+    n, steps = args.n, args.euler_steps
+    rs = min(args.cpu_replicas, wl["R"])
+    J = wl["Js"][0]
+    x0 = synth.initial_states(n, rs, 3, 1, 0)
+    t0 = time.perf_counter()
+    ups = 0
+    for d in wl["dims"]:
+        al, _ = synth.anneal_schedule(steps, d)
+        oracle.ode_run(J, wl["pumps"][:rs], x0[:, :, :d], float(wl["eps"][0]), 1.0, 2e-4, args.dt, steps, al)
+        ups += n * rs * d * steps
+    sec = time.perf_counter() - t0
+    return {"value": ups / sec, "unit": "spin-component updates/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"instance 0, D in {wl['dims']}, replicas 0..{rs - 1} of {wl['R']}, {steps} steps, "
+                      f"{ups:.3e} updates in {sec:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus_requested": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_2308_02329_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = build_workload(args, torch, synth, api, dev)
+    stream = torch.cuda.current_stream()
+    dims = wl["dims"]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(dims) + 2)]
+
+    def one_step(record):
+        wl["x"].copy_(wl["x0"])
+        if record:
+            ev[0].record(stream)
+        for k, d in enumerate(dims):
+            p = wl["plans"][d]
+            p.launch_nograph() if args.no_graph else p.launch()
+            if record:
+                ev[k + 1].record(stream)
+        wl["score_plan"].launch_nograph() if args.no_graph else wl["score_plan"].launch()
+        if record:
+            ev[-1].record(stream)
+
+    for _ in range(args.warmup):
+        one_step(False)
+    torch.cuda.synchronize()
+    kern_ms = {d: 0.0 for d in dims}
+    score_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step(True)
+        torch.cuda.synchronize()
+        for k, d in enumerate(dims):
+            kern_ms[d] += ev[k].elapsed_time(ev[k + 1])
+        score_ms += ev[len(dims)].elapsed_time(ev[-1])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    value = wl["updates"] / (wall / args.steps)
+
+    # dominant kernel: persistent integrator of the largest D
+    dk = max(dims)
+    n, R = args.n, wl["R"]
+    upd_k = args.instances * n * R * dk * args.euler_steps
+    flops_k = upd_k * 2.0 * (n - 1)  # algorithmic: 2 (N-1) flops per update (dense J, zero diagonal)
+    avg_s = kern_ms[dk] / args.steps / 1e3
+    achieved = flops_k / avg_s / 1e12
+    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+            "kernel": f"k_integrate_persistent<tiles={(n + 15) // 16}, D={dk}, {args.precision}>",
+            "kernel_ms": kern_ms[dk] / args.steps}
+
+    # run statistics of the last step (not timed)
+    diverged = sum(int(o["diverged"].sum().item()) for _, _, o in wl["outs"])
+    res = {"metric": METRIC, "value": value, "unit": "spin-component updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.precision == "f32" else "bf16",
+           "data": "synthetic",
+           "config": {"workload": f"{args.instances} SK +-1 instances N={n}, D in {dims}, "
+                                  f"{args.ics} initial states x {args.pumps} pumps, {args.euler_steps} Euler steps "
+                                  f"dt={args.dt}, linear dimensional anneal, {args.precision} form",
+                      "instances": args.instances, "n": n, "dims": dims, "replicas": R,
+                      "euler_steps": args.euler_steps, "precision": args.precision,
+                      "graph": not args.no_graph},
+           "roofline": roof,
+           "integrate_ms_per_step": {str(d): kern_ms[d] / args.steps for d in dims},
+           "score_ms_per_step": score_ms / args.steps,
+           "diverged_runs": diverged}
+    if args.cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(args, synth, wl)
+    for p in list(wl["plans"].values()) + [wl["score_plan"]]:
+        p.destroy()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

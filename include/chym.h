@@ -1,0 +1,210 @@
+/*
+ * chym.h -- C ABI of libchym, a gfx950 (MI355X) library that time-integrates
+ * the coherent hyperspin machine (CHYM) of Calvanese Strinati & Conti,
+ * "Hyperscaling in the coherent hyperspin machine", arXiv 2308.02329.
+ *
+ * The method (paper, Eq. (1)-(2) and the surrounding text): N hyperspins,
+ * each a D-component vector of parametric-oscillator amplitudes, are
+ * amplified by a pump, coupled through C = J_N (x) 1_D (the same N x N matrix
+ * J_N acts on every component), limited by the nonlocal loss
+ * W = beta 1_N (x) I_D (the squared norm of each hyperspin) and by the local
+ * gain saturation of the chi(2) medium, while the coupling of component mu is
+ * scaled by the annealing weights alpha_{mu,tau} that morph the
+ * D-dimensional hypergraph back into the Ising model.  The library
+ * integrates the continuous-time limit of the round-trip map of Eq. (2)
+ * (small loss per round trip; time in photon lifetimes, pump in units of the
+ * uncoupled threshold, amplitudes rescaled) by forward Euler:
+ *
+ *   x_{p,mu} <- x_{p,mu} + dt [ (r_i - 1) x_{p,mu}
+ *                               + eps alpha_mu[k] sum_q J_pq x_{q,mu}
+ *                               - btil x_{p,mu} sum_nu x_{p,nu}^2
+ *                               - eta x_{p,mu}^3 ]
+ *
+ * (CHYM: btil = 1, eta = (kappa L)^2 / (2 beta b^2); conventional CIM with
+ * D = 1: btil = 0, eta = 1), then reads the Ising spins from the sign of the
+ * first component, and scores each run by its exact Ising energy and by the
+ * hyperspin energy of Eq. (3).
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers owned by the caller, unless a
+ *     comment says "host".  The library never allocates or frees them.
+ *   - Layouts are C-contiguous:
+ *       J       [n][n]         row p, column q (symmetric, zero diagonal for
+ *                              the Ising model; any matrix is accepted)
+ *       x       [n][r][d]      float32 amplitudes: row p, replica i, component mu
+ *       pump    [r]            float32 normalized pump r_i = h_i / h_th
+ *       alpha   [T][d]         float32 annealing weights, row k for step k
+ *       spins   [r][w]         uint64, w = ceil(n / 64); bit (p % 64) of word
+ *                              p / 64 is 1 iff sigma_p = +1, i.e. x_{p,1} >= 0
+ *                              (-0 reads +1, NaN reads -1); unused high bits 0
+ *   - stream is a hipStream_t (NULL: the default stream).  Every call is
+ *     asynchronous on that stream except where stated; the library never
+ *     synchronizes the host unless documented.
+ *   - Return value: CHYM_OK (0) or a negative CHYM_E* code.  Arguments are
+ *     validated before any device work is queued; on error nothing is
+ *     launched and chym_last_error() describes the failure.  No C++
+ *     exception crosses this interface.
+ */
+#ifndef CHYM_H
+#define CHYM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CHYM_VERSION 1
+
+/* return codes */
+#define CHYM_OK 0
+#define CHYM_EINVAL (-1)       /* invalid argument (null pointer, bad size, bad enum) */
+#define CHYM_EUNSUPPORTED (-2) /* valid but not supported (size beyond the kernels' limits) */
+#define CHYM_ENODEV (-3)       /* no gfx950 device visible */
+#define CHYM_EHIP (-4)         /* a HIP runtime call failed; see chym_last_error() */
+#define CHYM_ENOMEM (-5)       /* caller-provided workspace too small */
+
+/* storage type of the coupling matrix J */
+#define CHYM_J_I8 0  /* int8 integer couplings (e.g. +-1 / 0): contraction and Ising energy exact */
+#define CHYM_J_F32 1 /* float32 couplings (e.g. Gaussian) */
+
+/* arithmetic of the J x contraction (the state and every other step are float32) */
+#define CHYM_PREC_F32 0  /* x fed to the matrix cores as an exact sum of three bf16 terms
+                            (and J as three terms when it is not an integer matrix), float32
+                            accumulation: float32-accurate products */
+#define CHYM_PREC_BF16 1 /* x rounded to bf16 (round to nearest even) at the matrix-core
+                            input, J rounded to bf16 (exact for integer |J| <= 256),
+                            float32 accumulation and float32 state */
+
+typedef void *chym_stream_t; /* hipStream_t */
+
+/* One coupled system.  Paper: J_N and D (text after Eq. (1)); eps, btil and
+ * eta are the normalized coupling, nonlocal-loss and local-saturation
+ * coefficients of the continuous-time limit of Eq. (2). */
+typedef struct chym_problem {
+    int32_t n;        /* hyperspins N >= 1 */
+    int32_t d;        /* components per hyperspin, 1 <= D <= 4 */
+    int32_t j_dtype;  /* CHYM_J_I8 or CHYM_J_F32 */
+    int32_t reserved; /* must be 0 */
+    const void *j;    /* device [n][n] */
+    float eps;        /* coupling strength */
+    float btil;       /* nonlocal loss coefficient (1 for the CHYM, 0 for the CIM) */
+    float eta;        /* local cubic saturation coefficient */
+    float reserved_f; /* must be 0 */
+} chym_problem;
+
+/* A block of independent runs (replicas) of one problem.  Paper: pump h
+ * scanned as h = h_th (1 + delta h) and the annealing protocol alpha_{mu,tau}
+ * (text after Fig. 2 and in the statistics paragraph). */
+typedef struct chym_run {
+    int32_t r;          /* replicas >= 1 */
+    int32_t steps;      /* Euler steps taken by this call, >= 0 */
+    int32_t start_step; /* global index of the first step (row of alpha), >= 0 */
+    int32_t precision;  /* CHYM_PREC_F32 or CHYM_PREC_BF16 */
+    float dt;           /* Euler step, > 0 */
+    float reserved_f;   /* must be 0 */
+    const float *pump;  /* device [r] */
+    float *x;           /* device [n][r][d], read and overwritten in place */
+    const float *alpha; /* device [start_step + steps][d] */
+} chym_run;
+
+/* Per-run results; every pointer may be NULL (that output is skipped). */
+typedef struct chym_out {
+    uint64_t *spins;     /* [r][ceil(n/64)] sign readout of the final state */
+    int32_t *e_ising;    /* [r] exact Ising energy; CHYM_J_I8 only (else must be NULL) */
+    double *e_ising_f64; /* [r] Ising energy in float64 (exact for integer J) */
+    double *e_hs;        /* [r] hyperspin energy, Eq. (3), of the final state (float64) */
+    double *extra_frac;  /* [r] max_p sum_{mu>=2} x^2 / |x_p|^2 of the final state */
+    uint8_t *diverged;   /* [r] 1 if any final amplitude is non-finite or |x| > 1e3 */
+} chym_out;
+
+/* Library version (CHYM_VERSION). */
+int chym_version(void);
+
+/* Thread-local description of the last error returned on this thread. */
+const char *chym_last_error(void);
+
+/* Advance every replica by run->steps Euler steps of the equation above,
+ * synchronous (Jacobi) update, using alpha rows start_step .. start_step +
+ * steps - 1.  Splitting a run into calls with consecutive start_step gives
+ * bit-identical results to one call.  Sizes: 1 <= n <= 256 (n <= 192 for
+ * d = 4; n <= 128 for CHYM_J_F32 with CHYM_PREC_F32), 1 <= d <= 4, r >= 1.
+ * Larger n returns CHYM_EUNSUPPORTED. */
+int chym_integrate(const chym_problem *prob, const chym_run *run, chym_stream_t stream);
+
+/* Sign readout of x (paper: the Ising spins are read at the end of a run).
+ * spins [r][ceil(n/64)], extra_frac [r], diverged [r]; each may be NULL. */
+int chym_readout(int32_t n, int32_t d, int32_t r, const float *x, uint64_t *spins,
+                 double *extra_frac, uint8_t *diverged, chym_stream_t stream);
+
+/* Ising energy E_i = -sum_{p,q} J_pq sigma_p sigma_q of each readout (paper:
+ * the Ising Hamiltonian; Eq. (3) with D = 1).  e_i32 [r] is exact and allowed
+ * for CHYM_J_I8 only (|E| must fit int32, n <= 2048); e_f64 [r] for any J.
+ * Either may be NULL. */
+int chym_ising_energy(int32_t n, int32_t r, const void *j, int32_t j_dtype,
+                      const uint64_t *spins, int32_t *e_i32, double *e_f64,
+                      chym_stream_t stream);
+
+/* Hyperspin energy of Eq. (3), E_hs = -sum_{p,q} J_pq u_p . u_q with unit
+ * vectors u_p = x_p / |x_p| (0 for a zero hyperspin), in float64.
+ * n <= 2048, n * d <= 8192. */
+int chym_hs_energy(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dtype,
+                   const float *x, double *e_hs, chym_stream_t stream);
+
+/* Whole run: integrate run->steps steps; if 0 < ss_step < steps and e_hs_ss
+ * is not NULL, record the hyperspin energy after ss_step steps (the
+ * hyperspin steady state before annealing); then fill every non-NULL output
+ * of *out from the final state. */
+int chym_solve(const chym_problem *prob, const chym_run *run, int32_t ss_step,
+               double *e_hs_ss, const chym_out *out, chym_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Batched form: many problems (instances of different n, d, replica counts,
+ * pumps, step counts) integrated by one launch.  Paper: the statistics are
+ * gathered over N_g graphs x N_s pump values x N_r runs, all independent
+ * (statistics paragraph and Fig. 4).
+ *
+ * Tasks are grouped by kernel variant (row tiles, d, precision); each group
+ * runs as one persistent kernel whose wavefronts pop (task, 16-replica
+ * group) work items, longest first, from a counter in the workspace.  The
+ * groups run as parallel branches of one HIP graph.  After integration every
+ * task's non-NULL outputs are filled from its final state, as chym_solve does.
+ */
+typedef struct chym_task {
+    chym_problem prob;
+    chym_run run;
+    chym_out out;
+} chym_task;
+
+typedef struct chym_batch chym_batch; /* opaque plan (host object owned by the library) */
+
+/* Device workspace bytes a batch of these tasks (host array) needs. */
+int chym_batch_workspace_size(const chym_task *tasks, int32_t n_tasks, size_t *bytes);
+
+/* Validate every task (host array), write the task table and the work list
+ * into the caller's device workspace (a synchronous host-to-device copy;
+ * the workspace must stay allocated and untouched while the plan lives) and
+ * record the launch sequence as a HIP graph.  The task arrays (J, pump, x,
+ * alpha, outputs) are referenced, not copied: launches read and write them
+ * as they are at launch time. */
+int chym_batch_create(const chym_task *tasks, int32_t n_tasks, void *workspace, size_t ws_bytes,
+                      chym_batch **plan);
+
+/* Run the batch: one hipGraphLaunch on stream.  Launches of one plan must
+ * not overlap (they share the work counters). */
+int chym_batch_launch(const chym_batch *plan, chym_stream_t stream);
+
+/* Same work as chym_batch_launch, issued as plain kernel launches on stream
+ * (no graph). */
+int chym_batch_launch_nograph(const chym_batch *plan, chym_stream_t stream);
+
+/* Free the plan (host object, graph and its private streams); the caller's
+ * workspace is not touched.  Waits for the plan's outstanding launches. */
+int chym_batch_destroy(chym_batch *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHYM_H */

@@ -1,0 +1,109 @@
+"""ctypes view of libchym's C ABI (include/chym.h).  Marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libchym.so")
+
+CHYM_OK = 0
+CHYM_EINVAL = -1
+CHYM_EUNSUPPORTED = -2
+CHYM_ENODEV = -3
+CHYM_EHIP = -4
+CHYM_ENOMEM = -5
+ERROR_NAMES = {0: "CHYM_OK", -1: "CHYM_EINVAL", -2: "CHYM_EUNSUPPORTED", -3: "CHYM_ENODEV",
+               -4: "CHYM_EHIP", -5: "CHYM_ENOMEM"}
+
+CHYM_J_I8 = 0
+CHYM_J_F32 = 1
+CHYM_PREC_F32 = 0
+CHYM_PREC_BF16 = 1
+
+# every symbol include/chym.h declares
+EXPORTS = (
+    "chym_version", "chym_last_error", "chym_integrate", "chym_readout", "chym_ising_energy",
+    "chym_hs_energy", "chym_solve", "chym_batch_workspace_size", "chym_batch_create",
+    "chym_batch_launch", "chym_batch_launch_nograph", "chym_batch_destroy",
+)
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+
+
+class ChymProblem(ctypes.Structure):
+    _fields_ = [("n", _i32), ("d", _i32), ("j_dtype", _i32), ("reserved", _i32), ("j", _vp),
+                ("eps", ctypes.c_float), ("btil", ctypes.c_float), ("eta", ctypes.c_float),
+                ("reserved_f", ctypes.c_float)]
+
+
+class ChymRun(ctypes.Structure):
+    _fields_ = [("r", _i32), ("steps", _i32), ("start_step", _i32), ("precision", _i32),
+                ("dt", ctypes.c_float), ("reserved_f", ctypes.c_float), ("pump", _vp), ("x", _vp),
+                ("alpha", _vp)]
+
+
+class ChymOut(ctypes.Structure):
+    _fields_ = [("spins", _vp), ("e_ising", _vp), ("e_ising_f64", _vp), ("e_hs", _vp),
+                ("extra_frac", _vp), ("diverged", _vp)]
+
+
+class ChymError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load the in-tree libchym.so; fail loudly if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2308_02329_amd.build` "
+                          "(there is no fallback path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    lib.chym_version.restype = ctypes.c_int
+    lib.chym_last_error.restype = ctypes.c_char_p
+    lib.chym_integrate.argtypes = [P(ChymProblem), P(ChymRun), _vp]
+    lib.chym_integrate.restype = ctypes.c_int
+    lib.chym_readout.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp]
+    lib.chym_readout.restype = ctypes.c_int
+    lib.chym_ising_energy.argtypes = [_i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp]
+    lib.chym_ising_energy.restype = ctypes.c_int
+    lib.chym_hs_energy.argtypes = [_i32, _i32, _i32, _vp, _i32, _vp, _vp, _vp]
+    lib.chym_hs_energy.restype = ctypes.c_int
+    lib.chym_solve.argtypes = [P(ChymProblem), P(ChymRun), _i32, _vp, P(ChymOut), _vp]
+    lib.chym_solve.restype = ctypes.c_int
+    _load_batch(lib)
+    _lib = lib
+    return lib
+
+
+def check(rc: int, where: str):
+    if rc != CHYM_OK:
+        msg = load().chym_last_error()
+        raise ChymError(rc, where, msg.decode() if msg else "")
+
+
+class ChymTask(ctypes.Structure):
+    _fields_ = [("prob", ChymProblem), ("run", ChymRun), ("out", ChymOut)]
+
+
+def _load_batch(lib):
+    P = ctypes.POINTER
+    lib.chym_batch_workspace_size.argtypes = [P(ChymTask), _i32, P(ctypes.c_size_t)]
+    lib.chym_batch_workspace_size.restype = ctypes.c_int
+    lib.chym_batch_create.argtypes = [P(ChymTask), _i32, _vp, ctypes.c_size_t, P(_vp)]
+    lib.chym_batch_create.restype = ctypes.c_int
+    lib.chym_batch_launch.argtypes = [_vp, _vp]
+    lib.chym_batch_launch.restype = ctypes.c_int
+    lib.chym_batch_launch_nograph.argtypes = [_vp, _vp]
+    lib.chym_batch_launch_nograph.restype = ctypes.c_int
+    lib.chym_batch_destroy.argtypes = [_vp]
+    lib.chym_batch_destroy.restype = ctypes.c_int

@@ -1,0 +1,255 @@
+"""Python binding of libchym with the C ABI's names (include/chym.h).
+
+Argument marshalling only: torch tensors supply device memory and the
+current HIP stream; every step of the computation runs in the library's
+kernels.  There is no CPU fallback: if libchym.so is missing or the device is
+not gfx950 the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+from ._lib import (CHYM_J_F32, CHYM_J_I8, CHYM_PREC_BF16, CHYM_PREC_F32, ChymError, ChymOut,
+                   ChymProblem, ChymRun)
+
+__all__ = ["chym_version", "chym_last_error", "chym_integrate", "chym_readout", "chym_ising_energy",
+           "chym_hs_energy", "chym_solve", "make_problem", "make_run", "spin_words", "ChymError",
+           "CHYM_J_I8", "CHYM_J_F32", "CHYM_PREC_F32", "CHYM_PREC_BF16", "precision_code",
+           "chym_batch_workspace_size", "chym_batch_create", "chym_batch_launch", "chym_batch_launch_nograph",
+           "chym_batch_destroy", "ChymBatch"]
+
+
+def precision_code(p) -> int:
+    if isinstance(p, str):
+        return {"f32": CHYM_PREC_F32, "fp32": CHYM_PREC_F32, "bf16": CHYM_PREC_BF16}[p.lower()]
+    return int(p)
+
+
+def spin_words(n: int) -> int:
+    return (n + 63) // 64
+
+
+def _vp(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t, name, dtype, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+def _jdtype(J) -> int:
+    if J.dtype == torch.int8:
+        return CHYM_J_I8
+    if J.dtype == torch.float32:
+        return CHYM_J_F32
+    raise TypeError("J must be int8 or float32")
+
+
+def make_problem(J, d: int, eps: float, btil: float, eta: float) -> ChymProblem:
+    n = J.shape[0]
+    _need(J, "J", J.dtype, (n, n))
+    return ChymProblem(n=n, d=int(d), j_dtype=_jdtype(J), reserved=0, j=_vp(J), eps=float(eps),
+                       btil=float(btil), eta=float(eta), reserved_f=0.0)
+
+
+def make_run(n, d, pump, x, alpha, dt, steps, start_step=0, precision=CHYM_PREC_F32) -> ChymRun:
+    r = pump.shape[0]
+    _need(pump, "pump", torch.float32, (r,))
+    _need(x, "x", torch.float32, (n, r, d))
+    _need(alpha, "alpha", torch.float32)
+    if alpha.ndim != 2 or alpha.shape[1] != d or alpha.shape[0] < start_step + steps:
+        raise ValueError(f"alpha must be [>= {start_step + steps}, {d}], got {tuple(alpha.shape)}")
+    return ChymRun(r=r, steps=int(steps), start_step=int(start_step), precision=precision_code(precision),
+                   dt=float(dt), reserved_f=0.0, pump=_vp(pump), x=_vp(x), alpha=_vp(alpha))
+
+
+def chym_version() -> int:
+    return int(L.load().chym_version())
+
+
+def chym_last_error() -> str:
+    m = L.load().chym_last_error()
+    return m.decode() if m else ""
+
+
+def chym_integrate(J, pump, x, alpha, *, eps, btil, eta, dt, steps, start_step=0,
+                   precision=CHYM_PREC_F32, stream=None):
+    """Advance x [n, r, d] (float32, in place) by ``steps`` Euler steps."""
+    lib = L.load()
+    n, r, d = x.shape
+    prob = make_problem(J, d, eps, btil, eta)
+    run = make_run(n, d, pump, x, alpha, dt, steps, start_step, precision)
+    L.check(lib.chym_integrate(ctypes.byref(prob), ctypes.byref(run), _stream(stream)), "chym_integrate")
+    return x
+
+
+def chym_readout(x, spins=None, extra_frac=None, diverged=None, stream=None):
+    lib = L.load()
+    n, r, d = x.shape
+    _need(x, "x", torch.float32)
+    if spins is not None:
+        _need(spins, "spins", torch.int64, (r, spin_words(n)))
+    if extra_frac is not None:
+        _need(extra_frac, "extra_frac", torch.float64, (r,))
+    if diverged is not None:
+        _need(diverged, "diverged", torch.uint8, (r,))
+    L.check(lib.chym_readout(n, d, r, _vp(x), _vp(spins), _vp(extra_frac), _vp(diverged), _stream(stream)),
+            "chym_readout")
+
+
+def chym_ising_energy(J, spins, e_i32=None, e_f64=None, stream=None):
+    lib = L.load()
+    n = J.shape[0]
+    r = spins.shape[0]
+    _need(J, "J", J.dtype, (n, n))
+    _need(spins, "spins", torch.int64, (r, spin_words(n)))
+    if e_i32 is not None:
+        _need(e_i32, "e_i32", torch.int32, (r,))
+    if e_f64 is not None:
+        _need(e_f64, "e_f64", torch.float64, (r,))
+    L.check(lib.chym_ising_energy(n, r, _vp(J), _jdtype(J), _vp(spins), _vp(e_i32), _vp(e_f64),
+                                  _stream(stream)), "chym_ising_energy")
+
+
+def chym_hs_energy(J, x, e_hs, stream=None):
+    lib = L.load()
+    n, r, d = x.shape
+    _need(J, "J", J.dtype, (n, n))
+    _need(x, "x", torch.float32)
+    _need(e_hs, "e_hs", torch.float64, (r,))
+    L.check(lib.chym_hs_energy(n, d, r, _vp(J), _jdtype(J), _vp(x), _vp(e_hs), _stream(stream)),
+            "chym_hs_energy")
+
+
+def chym_solve(J, pump, x, alpha, *, eps, btil, eta, dt, steps, ss_step=0, start_step=0,
+               precision=CHYM_PREC_F32, stream=None, want=("spins", "e_ising", "e_hs", "e_hs_ss",
+                                                           "extra_frac", "diverged")):
+    """Whole run on x (in place).  Returns a dict of device result tensors."""
+    lib = L.load()
+    n, r, d = x.shape
+    dev = x.device
+    prob = make_problem(J, d, eps, btil, eta)
+    run = make_run(n, d, pump, x, alpha, dt, steps, start_step, precision)
+    res = {}
+    want = set(want)
+    if want & {"spins", "e_ising", "e_ising_f64"}:
+        res["spins"] = torch.empty((r, spin_words(n)), dtype=torch.int64, device=dev)
+    if "e_ising" in want and J.dtype == torch.int8:
+        res["e_ising"] = torch.empty(r, dtype=torch.int32, device=dev)
+    if "e_ising_f64" in want or ("e_ising" in want and J.dtype != torch.int8):
+        res["e_ising_f64"] = torch.empty(r, dtype=torch.float64, device=dev)
+    for k in ("e_hs", "e_hs_ss", "extra_frac"):
+        if k in want:
+            res[k] = torch.empty(r, dtype=torch.float64, device=dev)
+    if "diverged" in want:
+        res["diverged"] = torch.empty(r, dtype=torch.uint8, device=dev)
+    out = ChymOut(spins=_vp(res.get("spins")), e_ising=_vp(res.get("e_ising")),
+                  e_ising_f64=_vp(res.get("e_ising_f64")), e_hs=_vp(res.get("e_hs")),
+                  extra_frac=_vp(res.get("extra_frac")), diverged=_vp(res.get("diverged")))
+    L.check(lib.chym_solve(ctypes.byref(prob), ctypes.byref(run), int(ss_step), _vp(res.get("e_hs_ss")),
+                           ctypes.byref(out), _stream(stream)), "chym_solve")
+    return res
+
+
+# ------------------------------------------------------------------ batches
+def _task_struct(t: dict) -> L.ChymTask:
+    J, x = t["J"], t["x"]
+    n, r, d = x.shape
+    prob = make_problem(J, d, t["eps"], t["btil"], t["eta"])
+    run = make_run(n, d, t["pump"], x, t["alpha"], t["dt"], t["steps"], t.get("start_step", 0),
+                   t.get("precision", CHYM_PREC_F32))
+    w = spin_words(n)
+    checks = {"spins": (torch.int64, (r, w)), "e_ising": (torch.int32, (r,)), "e_ising_f64": (torch.float64, (r,)),
+              "e_hs": (torch.float64, (r,)), "extra_frac": (torch.float64, (r,)), "diverged": (torch.uint8, (r,))}
+    for k, (dt, shp) in checks.items():
+        if t.get(k) is not None:
+            _need(t[k], k, dt, shp)
+    out = ChymOut(spins=_vp(t.get("spins")), e_ising=_vp(t.get("e_ising")), e_ising_f64=_vp(t.get("e_ising_f64")),
+                  e_hs=_vp(t.get("e_hs")), extra_frac=_vp(t.get("extra_frac")), diverged=_vp(t.get("diverged")))
+    return L.ChymTask(prob=prob, run=run, out=out)
+
+
+class ChymBatch:
+    """A batch plan: keeps the task tensors and the workspace alive."""
+
+    def __init__(self, tasks, handle, workspace, structs):
+        self.tasks = tasks
+        self.handle = handle
+        self.workspace = workspace
+        self._structs = structs
+
+    def launch(self, stream=None):
+        chym_batch_launch(self, stream)
+
+    def launch_nograph(self, stream=None):
+        chym_batch_launch_nograph(self, stream)
+
+    def destroy(self):
+        chym_batch_destroy(self)
+
+    def __del__(self):
+        try:
+            if self.handle is not None:
+                self.destroy()
+        except Exception:
+            pass
+
+
+def chym_batch_workspace_size(tasks) -> int:
+    lib = L.load()
+    arr = (L.ChymTask * len(tasks))(*[_task_struct(t) for t in tasks])
+    nbytes = ctypes.c_size_t(0)
+    L.check(lib.chym_batch_workspace_size(arr, len(tasks), ctypes.byref(nbytes)), "chym_batch_workspace_size")
+    return int(nbytes.value)
+
+
+def chym_batch_create(tasks, device=None) -> ChymBatch:
+    """tasks: list of dicts with keys J, pump, x, alpha, eps, btil, eta, dt,
+    steps, [start_step, precision] and optional result tensors spins,
+    e_ising, e_ising_f64, e_hs, extra_frac, diverged."""
+    lib = L.load()
+    structs = [_task_struct(t) for t in tasks]
+    arr = (L.ChymTask * len(tasks))(*structs)
+    nbytes = ctypes.c_size_t(0)
+    L.check(lib.chym_batch_workspace_size(arr, len(tasks), ctypes.byref(nbytes)), "chym_batch_workspace_size")
+    dev = device if device is not None else tasks[0]["x"].device
+    ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    wsv = ws[off:off + int(nbytes.value)]
+    handle = ctypes.c_void_p()
+    L.check(lib.chym_batch_create(arr, len(tasks), ctypes.c_void_p(wsv.data_ptr()), int(nbytes.value),
+                                  ctypes.byref(handle)), "chym_batch_create")
+    return ChymBatch(list(tasks), handle, ws, arr)
+
+
+def chym_batch_launch(batch: ChymBatch, stream=None):
+    L.check(L.load().chym_batch_launch(batch.handle, _stream(stream)), "chym_batch_launch")
+
+
+def chym_batch_launch_nograph(batch: ChymBatch, stream=None):
+    L.check(L.load().chym_batch_launch_nograph(batch.handle, _stream(stream)), "chym_batch_launch_nograph")
+
+
+def chym_batch_destroy(batch: ChymBatch):
+    if batch.handle is not None and batch.handle.value:
+        h, batch.handle = batch.handle, None
+        L.check(L.load().chym_batch_destroy(h), "chym_batch_destroy")
+    batch.handle = None

@@ -1,0 +1,535 @@
+// C ABI of libchym: argument validation, device checks and dispatch.  The
+// kernels live in integrate_resident.hip and readout.hip.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "chym_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(CHYM_EHIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+// The kernels are built for gfx950 only: refuse any other device up front.
+int check_device() {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(CHYM_ENODEV, "no HIP device: %s", hipGetErrorString(e));
+    static std::mutex mu;
+    static int ok[64];  // 0 unknown, 1 gfx950, -1 other
+    if (dev < 0 || dev >= 64) return fail(CHYM_ENODEV, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(mu);
+    if (ok[dev] == 0) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+        ok[dev] = strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+    }
+    if (ok[dev] != 1) return fail(CHYM_ENODEV, "device %d is not gfx950", dev);
+    return CHYM_OK;
+}
+
+bool finite(float v) { return isfinite(v); }
+
+int validate_problem(const chym_problem *p) {
+    if (!p) return fail(CHYM_EINVAL, "problem is NULL");
+    if (p->n < 1) return fail(CHYM_EINVAL, "n = %d must be >= 1", p->n);
+    if (p->d < 1 || p->d > 4) return fail(CHYM_EINVAL, "d = %d must be in 1..4", p->d);
+    if (p->j_dtype != CHYM_J_I8 && p->j_dtype != CHYM_J_F32)
+        return fail(CHYM_EINVAL, "j_dtype = %d is not CHYM_J_I8 or CHYM_J_F32", p->j_dtype);
+    if (!p->j) return fail(CHYM_EINVAL, "J is NULL");
+    if (p->reserved != 0 || p->reserved_f != 0.0f) return fail(CHYM_EINVAL, "reserved fields must be 0");
+    if (!finite(p->eps) || !finite(p->btil) || !finite(p->eta))
+        return fail(CHYM_EINVAL, "eps, btil and eta must be finite");
+    return CHYM_OK;
+}
+
+int validate_run(const chym_run *r) {
+    if (!r) return fail(CHYM_EINVAL, "run is NULL");
+    if (r->r < 1) return fail(CHYM_EINVAL, "r = %d must be >= 1", r->r);
+    if (r->steps < 0) return fail(CHYM_EINVAL, "steps = %d must be >= 0", r->steps);
+    if (r->start_step < 0) return fail(CHYM_EINVAL, "start_step = %d must be >= 0", r->start_step);
+    if ((long long)r->start_step + r->steps > 0x7fffffffLL) return fail(CHYM_EINVAL, "start_step + steps overflows");
+    if (r->precision != CHYM_PREC_F32 && r->precision != CHYM_PREC_BF16)
+        return fail(CHYM_EINVAL, "precision = %d is not CHYM_PREC_F32 or CHYM_PREC_BF16", r->precision);
+    if (!(r->dt > 0.0f) || !finite(r->dt)) return fail(CHYM_EINVAL, "dt must be finite and > 0");
+    if (r->reserved_f != 0.0f) return fail(CHYM_EINVAL, "reserved fields must be 0");
+    if (!r->pump || !r->x || !r->alpha) return fail(CHYM_EINVAL, "pump, x and alpha must not be NULL");
+    return CHYM_OK;
+}
+
+struct Variant {
+    int tiles, xs, js;
+};
+
+Variant variant_of(const chym_problem *p, const chym_run *r) {
+    Variant v;
+    v.tiles = (p->n + 15) / 16;
+    v.xs = r->precision == CHYM_PREC_F32 ? 3 : 1;
+    v.js = (r->precision == CHYM_PREC_F32 && p->j_dtype == CHYM_J_F32) ? 3 : 1;
+    return v;
+}
+
+int default_waves_per_block() { return 4; }
+
+chym::IntegArgs make_args(const chym_problem *prob, const chym_run *run) {
+    chym::IntegArgs a;
+    a.j = prob->j;
+    a.pump = run->pump;
+    a.x = run->x;
+    a.alpha = run->alpha;
+    a.n = prob->n;
+    a.d = prob->d;
+    a.r = run->r;
+    a.steps = run->steps;
+    a.start_step = run->start_step;
+    a.j_dtype = prob->j_dtype;
+    a.eps = prob->eps;
+    a.btil = prob->btil;
+    a.eta = prob->eta;
+    a.dt = run->dt;
+    return a;
+}
+
+int check_variant(const chym_problem *prob, const chym_run *run) {
+    const Variant v = variant_of(prob, run);
+    if (v.tiles > chym::resident_tile_limit(prob->d, v.xs, v.js))
+        return fail(CHYM_EUNSUPPORTED, "n = %d with d = %d is beyond the resident integrator (<= %d rows)", prob->n,
+                    prob->d, 16 * chym::resident_tile_limit(prob->d, v.xs, v.js));
+    return CHYM_OK;
+}
+
+int integrate_impl(const chym_problem *prob, const chym_run *run, hipStream_t stream) {
+    int rc = check_variant(prob, run);
+    if (rc) return rc;
+    if (run->steps == 0) return CHYM_OK;
+    rc = check_device();
+    if (rc) return rc;
+    const Variant v = variant_of(prob, run);
+    const chym::IntegArgs a = make_args(prob, run);
+    bool supported = false;
+    hipError_t e = chym::launch_integrate(v.tiles, prob->d, v.xs, v.js, default_waves_per_block(), a, stream,
+                                          &supported);
+    if (!supported) return fail(CHYM_EUNSUPPORTED, "no integrator variant for n = %d, d = %d", prob->n, prob->d);
+    if (e != hipSuccess) return hip_fail(e, "integrate launch");
+    return CHYM_OK;
+}
+
+int validate_sizes(int32_t n, int32_t d, int32_t r) {
+    if (n < 1) return fail(CHYM_EINVAL, "n = %d must be >= 1", n);
+    if (d < 1 || d > 4) return fail(CHYM_EINVAL, "d = %d must be in 1..4", d);
+    if (r < 1) return fail(CHYM_EINVAL, "r = %d must be >= 1", r);
+    return CHYM_OK;
+}
+
+int validate_energy(int32_t n, int32_t r, const void *j, int32_t j_dtype, const uint64_t *spins, int32_t *e_i32) {
+    if (n < 1 || r < 1) return fail(CHYM_EINVAL, "n and r must be >= 1");
+    if (n > 2048) return fail(CHYM_EUNSUPPORTED, "n = %d > 2048", n);
+    if (j_dtype != CHYM_J_I8 && j_dtype != CHYM_J_F32) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
+    if (!j || !spins) return fail(CHYM_EINVAL, "J and spins must not be NULL");
+    if (e_i32 && j_dtype != CHYM_J_I8) return fail(CHYM_EINVAL, "int32 energy needs integer J (CHYM_J_I8)");
+    return CHYM_OK;
+}
+
+int validate_hs(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dtype, const float *x) {
+    int rc = validate_sizes(n, d, r);
+    if (rc) return rc;
+    if (n > 2048 || n * d > 8192) return fail(CHYM_EUNSUPPORTED, "hyperspin energy needs n <= 2048, n*d <= 8192");
+    if (j_dtype != CHYM_J_I8 && j_dtype != CHYM_J_F32) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
+    if (!j || !x) return fail(CHYM_EINVAL, "J and x must not be NULL");
+    return CHYM_OK;
+}
+
+
+// ---------------------------------------------------------------- batches
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Group {
+    Variant v;
+    int d;
+    int item_off, n_items;
+    int blocks;
+};
+
+struct BatchLayout {
+    std::vector<Group> groups;
+    std::vector<int2> items;  // (task, 16-replica group), grouped and sorted
+    size_t off_tasks, off_items, off_counters, total;
+};
+
+int validate_out(const chym_problem *prob, const chym_run *run, const chym_out *o) {
+    const bool want_energy = o->e_ising || o->e_ising_f64;
+    if (want_energy && !o->spins) return fail(CHYM_EINVAL, "Ising energies need the spins output");
+    if (want_energy) {
+        int rc = validate_energy(prob->n, run->r, prob->j, prob->j_dtype, o->spins, o->e_ising);
+        if (rc) return rc;
+    }
+    if (o->e_hs) {
+        int rc = validate_hs(prob->n, prob->d, run->r, prob->j, prob->j_dtype, run->x);
+        if (rc) return rc;
+    }
+    return CHYM_OK;
+}
+
+int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
+    if (n_tasks < 1) return fail(CHYM_EINVAL, "n_tasks = %d must be >= 1", n_tasks);
+    if (!tasks) return fail(CHYM_EINVAL, "tasks is NULL");
+    std::map<std::tuple<int, int, int, int>, std::vector<int2>> by_variant;
+    for (int t = 0; t < n_tasks; ++t) {
+        const chym_task &tk = tasks[t];
+        int rc = validate_problem(&tk.prob);
+        if (!rc) rc = validate_run(&tk.run);
+        if (!rc) rc = check_variant(&tk.prob, &tk.run);
+        if (!rc) rc = validate_out(&tk.prob, &tk.run, &tk.out);
+        if (rc) {
+            std::string m = g_err;
+            return fail(rc, "task %d: %s", t, m.c_str());
+        }
+        const Variant v = variant_of(&tk.prob, &tk.run);
+        auto &lst = by_variant[std::make_tuple(v.tiles, tk.prob.d, v.xs, v.js)];
+        if (tk.run.steps == 0) continue;
+        const int groups = (tk.run.r + 15) / 16;
+        for (int g = 0; g < groups; ++g) lst.push_back(make_int2(t, g));
+    }
+    L->groups.clear();
+    L->items.clear();
+    for (auto &kv : by_variant) {
+        auto &lst = kv.second;
+        if (lst.empty()) continue;
+        // longest first: per-item cost is proportional to the task's step count
+        std::stable_sort(lst.begin(), lst.end(), [&](const int2 &a, const int2 &b) {
+            return tasks[a.x].run.steps > tasks[b.x].run.steps;
+        });
+        Group g;
+        g.v.tiles = std::get<0>(kv.first);
+        g.d = std::get<1>(kv.first);
+        g.v.xs = std::get<2>(kv.first);
+        g.v.js = std::get<3>(kv.first);
+        g.item_off = (int)L->items.size();
+        g.n_items = (int)lst.size();
+        g.blocks = 0;
+        L->items.insert(L->items.end(), lst.begin(), lst.end());
+        L->groups.push_back(g);
+    }
+    L->off_tasks = 0;
+    L->off_items = align_up(sizeof(chym::IntegArgs) * (size_t)n_tasks);
+    L->off_counters = L->off_items + align_up(sizeof(int2) * std::max<size_t>(1, L->items.size()));
+    L->total = L->off_counters + align_up(sizeof(int) * std::max<size_t>(1, L->groups.size()));
+    return CHYM_OK;
+}
+
+constexpr int kPersistentWaves = 4;
+
+}  // namespace
+
+struct chym_batch {
+    std::vector<chym_task> tasks;
+    BatchLayout layout;
+    char *ws = nullptr;
+    int device = -1;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> events;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// Issues the batch on `main`: zero the work counters, one persistent kernel
+// per variant group (on `branches[i]` when given, forked from and joined
+// back into `main`), then the per-task scoring kernels.
+int issue_batch(const chym_batch *b, hipStream_t main, const std::vector<hipStream_t> *branches,
+                const std::vector<hipEvent_t> *events) {
+    const BatchLayout &L = b->layout;
+    const chym::IntegArgs *tasks_d = reinterpret_cast<const chym::IntegArgs *>(b->ws + L.off_tasks);
+    const int2 *items_d = reinterpret_cast<const int2 *>(b->ws + L.off_items);
+    int *counters = reinterpret_cast<int *>(b->ws + L.off_counters);
+    hipError_t e = chym::launch_zero_counters(counters, (int)L.groups.size(), main);
+    if (e != hipSuccess) return hip_fail(e, "zero counters");
+    const bool fork = branches && L.groups.size() > 1;
+    if (fork) {
+        e = hipEventRecord((*events)[0], main);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
+    for (size_t gi = 0; gi < L.groups.size(); ++gi) {
+        const Group &g = L.groups[gi];
+        hipStream_t s = fork ? (*branches)[gi] : main;
+        if (fork) {
+            e = hipStreamWaitEvent(s, (*events)[0], 0);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+        }
+        e = chym::launch_integrate_persistent(g.v.tiles, g.d, g.v.xs, g.v.js, kPersistentWaves, g.blocks, tasks_d,
+                                              items_d + g.item_off, g.n_items, counters + gi, s);
+        if (e != hipSuccess) return hip_fail(e, "persistent integrate launch");
+        if (fork) {
+            e = hipEventRecord((*events)[gi + 1], s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(main, (*events)[gi + 1], 0);
+            if (e != hipSuccess) return hip_fail(e, "join branch");
+        }
+    }
+    for (const chym_task &tk : b->tasks) {
+        const chym_out &o = tk.out;
+        const int n = tk.prob.n, d = tk.prob.d, r = tk.run.r;
+        if (o.spins || o.extra_frac || o.diverged) {
+            e = chym::launch_readout(n, d, r, tk.run.x, o.spins, o.extra_frac, o.diverged, main);
+            if (e != hipSuccess) return hip_fail(e, "readout launch");
+        }
+        if (o.e_ising || o.e_ising_f64) {
+            e = chym::launch_ising_energy(n, r, tk.prob.j, tk.prob.j_dtype, o.spins, o.e_ising, o.e_ising_f64, main);
+            if (e != hipSuccess) return hip_fail(e, "ising energy launch");
+        }
+        if (o.e_hs) {
+            e = chym::launch_hs_energy(n, d, r, tk.prob.j, tk.prob.j_dtype, tk.run.x, o.e_hs, main);
+            if (e != hipSuccess) return hip_fail(e, "hyperspin energy launch");
+        }
+    }
+    return CHYM_OK;
+}
+
+void release(chym_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (hipEvent_t ev : b->events) (void)hipEventDestroy(ev);
+    for (hipStream_t s : b->side) (void)hipStreamDestroy(s);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chym_version(void) { return CHYM_VERSION; }
+
+const char *chym_last_error(void) { return g_err.c_str(); }
+
+int chym_integrate(const chym_problem *prob, const chym_run *run, chym_stream_t stream) {
+    int rc = validate_problem(prob);
+    if (rc) return rc;
+    rc = validate_run(run);
+    if (rc) return rc;
+    return integrate_impl(prob, run, (hipStream_t)stream);
+}
+
+int chym_readout(int32_t n, int32_t d, int32_t r, const float *x, uint64_t *spins, double *extra_frac,
+                 uint8_t *diverged, chym_stream_t stream) {
+    int rc = validate_sizes(n, d, r);
+    if (rc) return rc;
+    if (!x) return fail(CHYM_EINVAL, "x is NULL");
+    if (!spins && !extra_frac && !diverged) return CHYM_OK;
+    rc = check_device();
+    if (rc) return rc;
+    hipError_t e = chym::launch_readout(n, d, r, x, spins, extra_frac, diverged, (hipStream_t)stream);
+    return e == hipSuccess ? CHYM_OK : hip_fail(e, "readout launch");
+}
+
+int chym_ising_energy(int32_t n, int32_t r, const void *j, int32_t j_dtype, const uint64_t *spins, int32_t *e_i32,
+                      double *e_f64, chym_stream_t stream) {
+    int rc = validate_energy(n, r, j, j_dtype, spins, e_i32);
+    if (rc) return rc;
+    if (!e_i32 && !e_f64) return CHYM_OK;
+    rc = check_device();
+    if (rc) return rc;
+    hipError_t e = chym::launch_ising_energy(n, r, j, j_dtype, spins, e_i32, e_f64, (hipStream_t)stream);
+    return e == hipSuccess ? CHYM_OK : hip_fail(e, "ising energy launch");
+}
+
+int chym_hs_energy(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dtype, const float *x, double *e_hs,
+                   chym_stream_t stream) {
+    int rc = validate_hs(n, d, r, j, j_dtype, x);
+    if (rc) return rc;
+    if (!e_hs) return CHYM_OK;
+    rc = check_device();
+    if (rc) return rc;
+    hipError_t e = chym::launch_hs_energy(n, d, r, j, j_dtype, x, e_hs, (hipStream_t)stream);
+    return e == hipSuccess ? CHYM_OK : hip_fail(e, "hyperspin energy launch");
+}
+
+int chym_solve(const chym_problem *prob, const chym_run *run, int32_t ss_step, double *e_hs_ss,
+               const chym_out *out, chym_stream_t stream) {
+    int rc = validate_problem(prob);
+    if (rc) return rc;
+    rc = validate_run(run);
+    if (rc) return rc;
+    if (ss_step < 0) return fail(CHYM_EINVAL, "ss_step = %d must be >= 0", ss_step);
+    const bool want_ss = e_hs_ss && ss_step > 0 && ss_step < run->steps;
+    chym_out o;
+    memset(&o, 0, sizeof o);
+    if (out) o = *out;
+    const bool want_energy = o.e_ising || o.e_ising_f64;
+    if (want_energy && !o.spins) return fail(CHYM_EINVAL, "Ising energies need the spins output");
+    if (want_energy) {
+        rc = validate_energy(prob->n, run->r, prob->j, prob->j_dtype, o.spins, o.e_ising);
+        if (rc) return rc;
+    }
+    if (want_ss || o.e_hs) {
+        rc = validate_hs(prob->n, prob->d, run->r, prob->j, prob->j_dtype, run->x);
+        if (rc) return rc;
+    }
+    const Variant v = variant_of(prob, run);
+    if (v.tiles > chym::resident_tile_limit(prob->d, v.xs, v.js))
+        return fail(CHYM_EUNSUPPORTED, "n = %d with d = %d is beyond the resident integrator", prob->n, prob->d);
+    rc = check_device();
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (want_ss) {
+        chym_run a = *run;
+        a.steps = ss_step;
+        rc = integrate_impl(prob, &a, st);
+        if (rc) return rc;
+        hipError_t e = chym::launch_hs_energy(prob->n, prob->d, run->r, prob->j, prob->j_dtype, run->x, e_hs_ss, st);
+        if (e != hipSuccess) return hip_fail(e, "hyperspin energy launch");
+        a.start_step = run->start_step + ss_step;
+        a.steps = run->steps - ss_step;
+        rc = integrate_impl(prob, &a, st);
+        if (rc) return rc;
+    } else {
+        rc = integrate_impl(prob, run, st);
+        if (rc) return rc;
+    }
+    hipError_t e;
+    if (o.spins || o.extra_frac || o.diverged) {
+        e = chym::launch_readout(prob->n, prob->d, run->r, run->x, o.spins, o.extra_frac, o.diverged, st);
+        if (e != hipSuccess) return hip_fail(e, "readout launch");
+    }
+    if (want_energy) {
+        e = chym::launch_ising_energy(prob->n, run->r, prob->j, prob->j_dtype, o.spins, o.e_ising, o.e_ising_f64, st);
+        if (e != hipSuccess) return hip_fail(e, "ising energy launch");
+    }
+    if (o.e_hs) {
+        e = chym::launch_hs_energy(prob->n, prob->d, run->r, prob->j, prob->j_dtype, run->x, o.e_hs, st);
+        if (e != hipSuccess) return hip_fail(e, "hyperspin energy launch");
+    }
+    return CHYM_OK;
+}
+
+int chym_batch_workspace_size(const chym_task *tasks, int32_t n_tasks, size_t *bytes) {
+    if (!bytes) return fail(CHYM_EINVAL, "bytes is NULL");
+    BatchLayout L;
+    int rc = plan_layout(tasks, n_tasks, &L);
+    if (rc) return rc;
+    *bytes = L.total;
+    return CHYM_OK;
+}
+
+int chym_batch_create(const chym_task *tasks, int32_t n_tasks, void *workspace, size_t ws_bytes,
+                      chym_batch **plan) {
+    if (!plan) return fail(CHYM_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    BatchLayout L;
+    int rc = plan_layout(tasks, n_tasks, &L);
+    if (rc) return rc;
+    if (!workspace) return fail(CHYM_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % kAlign) return fail(CHYM_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+    if (ws_bytes < L.total) return fail(CHYM_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+    rc = check_device();
+    if (rc) return rc;
+    chym_batch *b = new (std::nothrow) chym_batch;
+    if (!b) return fail(CHYM_ENOMEM, "out of host memory");
+    b->tasks.assign(tasks, tasks + n_tasks);
+    b->layout = L;
+    b->ws = static_cast<char *>(workspace);
+    hipError_t e = hipGetDevice(&b->device);
+    // occupancy-sized persistent grids
+    int cus = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    for (Group &g : b->layout.groups) {
+        int per_cu = 0;
+        if (e == hipSuccess) e = chym::persistent_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, kPersistentWaves, &per_cu);
+        const int need = (g.n_items + kPersistentWaves - 1) / kPersistentWaves;
+        g.blocks = std::max(1, std::min(need, std::max(1, per_cu) * cus));
+    }
+    // task table and work list
+    std::vector<chym::IntegArgs> targs(n_tasks);
+    for (int t = 0; t < n_tasks; ++t) targs[t] = make_args(&tasks[t].prob, &tasks[t].run);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->ws + L.off_tasks, targs.data(), sizeof(chym::IntegArgs) * n_tasks, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !L.items.empty())
+        e = hipMemcpy(b->ws + L.off_items, L.items.data(), sizeof(int2) * L.items.size(), hipMemcpyHostToDevice);
+    // record the launch sequence as a graph with one branch per variant group
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    const size_t ng = b->layout.groups.size();
+    for (size_t i = 0; e == hipSuccess && ng > 1 && i < ng; ++i) {
+        hipStream_t s;
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e == hipSuccess) b->side.push_back(s);
+    }
+    for (size_t i = 0; e == hipSuccess && ng > 1 && i < ng + 1; ++i) {
+        hipEvent_t ev;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) b->events.push_back(ev);
+    }
+    if (e != hipSuccess) {
+        release(b);
+        return hip_fail(e, "batch setup");
+    }
+    e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        release(b);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    rc = issue_batch(b, b->cap, &b->side, &b->events);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
+    b->graph = graph;
+    if (rc) {
+        std::string m = g_err;
+        release(b);
+        return fail(rc, "%s", m.c_str());
+    }
+    if (e2 != hipSuccess) {
+        release(b);
+        return hip_fail(e2, "hipStreamEndCapture");
+    }
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        release(b);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    *plan = b;
+    return CHYM_OK;
+}
+
+int chym_batch_launch(const chym_batch *plan, chym_stream_t stream) {
+    if (!plan || !plan->exec) return fail(CHYM_EINVAL, "plan is NULL");
+    hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    return e == hipSuccess ? CHYM_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+int chym_batch_launch_nograph(const chym_batch *plan, chym_stream_t stream) {
+    if (!plan) return fail(CHYM_EINVAL, "plan is NULL");
+    return issue_batch(plan, (hipStream_t)stream, nullptr, nullptr);
+}
+
+int chym_batch_destroy(chym_batch *plan) {
+    if (!plan) return CHYM_OK;
+    hipError_t e = hipDeviceSynchronize();
+    release(plan);
+    return e == hipSuccess ? CHYM_OK : hip_fail(e, "hipDeviceSynchronize");
+}
+
+}  // extern "C"

@@ -1,0 +1,47 @@
+// Internal declarations of libchym (gfx950).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/chym.h"
+
+namespace chym {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+// Largest row-tile count (16 rows per tile) of the register-resident
+// integrator for d components, xs state terms and js J terms (0 if none).
+int resident_tile_limit(int d, int xs, int js);
+
+// Arguments of one integration launch (one problem, one replica block).
+struct IntegArgs {
+    const void *j;
+    const float *pump;
+    float *x;
+    const float *alpha;
+    int32_t n, d, r, steps, start_step, j_dtype;
+    float eps, btil, eta, dt;
+};
+
+// Host-side launcher of the resident integrator for one (tiles, d, xs, js)
+// variant; returns hipSuccess or the launch error.
+hipError_t launch_integrate(int tiles, int d, int xs, int js, int waves_per_block,
+                            const IntegArgs &a, hipStream_t stream, bool *supported);
+bool integrate_variant_exists(int tiles, int d, int xs, int js);
+hipError_t persistent_occupancy(int tiles, int d, int xs, int js, int waves_per_block, int *blocks_per_cu);
+hipError_t launch_zero_counters(int *counters, int n, hipStream_t stream);
+// Persistent launch over a work list: items[i] = (task index, 16-replica group).
+hipError_t launch_integrate_persistent(int tiles, int d, int xs, int js, int waves_per_block, int blocks,
+                                       const IntegArgs *tasks, const int2 *items, int n_items, int *counter,
+                                       hipStream_t stream);
+
+hipError_t launch_readout(int n, int d, int r, const float *x, uint64_t *spins, double *extra,
+                          uint8_t *diverged, hipStream_t stream);
+hipError_t launch_ising_energy(int n, int r, const void *j, int j_dtype, const uint64_t *spins,
+                               int32_t *e_i32, double *e_f64, hipStream_t stream);
+hipError_t launch_hs_energy(int n, int d, int r, const void *j, int j_dtype, const float *x,
+                            double *e_hs, hipStream_t stream);
+
+}  // namespace chym

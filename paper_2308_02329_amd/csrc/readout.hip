@@ -1,0 +1,150 @@
+// Readout and scoring kernels: sign readout of the Ising spins, exact Ising
+// energy, and the float64 hyperspin energy of Eq. (3).
+#include "chym_internal.h"
+
+namespace chym {
+
+// One thread per replica.  Walks the rows of its replica once: packs the
+// spin bits (sigma_p = +1 iff x_{p,1} >= 0), and computes the largest share
+// of the extra components and the divergence flag in the same pass.
+__global__ __launch_bounds__(256) void k_readout(int n, int d, int r, const float *__restrict__ x,
+                                                 uint64_t *__restrict__ spins, double *__restrict__ extra,
+                                                 uint8_t *__restrict__ diverged) {
+    const int w = (n + 63) >> 6;
+    for (int rep = blockIdx.x * blockDim.x + threadIdx.x; rep < r; rep += gridDim.x * blockDim.x) {
+        uint64_t word = 0;
+        double m = 0.0;
+        int bad = 0;
+        for (int p = 0; p < n; ++p) {
+            const float *xp = x + ((size_t)p * r + rep) * d;
+            const float v0 = xp[0];
+            if (v0 >= 0.0f) word |= 1ull << (p & 63);
+            double tot = 0.0, ext = 0.0;
+            for (int mu = 0; mu < d; ++mu) {
+                const float v = xp[mu];
+                const double dv = (double)v;
+                tot = tot + dv * dv;
+                if (mu > 0) ext = ext + dv * dv;
+                if (!isfinite(v) || fabsf(v) > 1e3f) bad = 1;
+            }
+            if (tot > 0.0 && ext / tot > m) m = ext / tot;
+            if ((p & 63) == 63 || p == n - 1) {
+                if (spins) spins[(size_t)rep * w + (p >> 6)] = word;
+                word = 0;
+            }
+        }
+        if (extra) extra[rep] = m;
+        if (diverged) diverged[rep] = (uint8_t)bad;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int spin_of(const uint64_t *s, int p) {
+    return ((s[p >> 6] >> (p & 63)) & 1ull) ? 1 : -1;
+}
+
+// One wavefront per replica: E = -sum_q sigma_q sum_p J_pq sigma_p.  Lanes
+// own columns q (coalesced reads of each row of J); the sigma_p are uniform
+// across the wave.  Integer J: exact int32; float J: float64.
+__global__ __launch_bounds__(256) void k_ising_energy(int n, int r, const void *__restrict__ j, int j_dtype,
+                                                      const uint64_t *__restrict__ spins,
+                                                      int32_t *__restrict__ e_i32, double *__restrict__ e_f64) {
+    const int lane = threadIdx.x & 63;
+    const int rep = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (rep >= r) return;
+    const int w = (n + 63) >> 6;
+    const uint64_t *s = spins + (size_t)rep * w;
+    if (j_dtype == CHYM_J_I8) {
+        const int8_t *J = reinterpret_cast<const int8_t *>(j);
+        int acc = 0;
+        for (int q = lane; q < n; q += 64) {
+            int h = 0;
+            for (int p = 0; p < n; ++p) h += (int)J[(size_t)p * n + q] * spin_of(s, p);
+            acc += spin_of(s, q) * h;
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) {
+            if (e_i32) e_i32[rep] = -acc;
+            if (e_f64) e_f64[rep] = -(double)acc;
+        }
+    } else {
+        const float *J = reinterpret_cast<const float *>(j);
+        double acc = 0.0;
+        for (int q = lane; q < n; q += 64) {
+            double h = 0.0;
+            for (int p = 0; p < n; ++p) h += (double)J[(size_t)p * n + q] * (double)spin_of(s, p);
+            acc += (double)spin_of(s, q) * h;
+        }
+        acc = wave_sum(acc);
+        if (lane == 0 && e_f64) e_f64[rep] = -acc;
+    }
+}
+
+// One wavefront per block and per replica.  The unit vectors u_p =
+// x_p / |x_p| (0 for a zero hyperspin) are formed in float64 in LDS, then
+// E_hs = -sum_q sum_p J_pq (u_p . u_q) with lanes owning columns q.
+__global__ __launch_bounds__(64) void k_hs_energy(int n, int d, int r, const void *__restrict__ j, int j_dtype,
+                                                  const float *__restrict__ x, double *__restrict__ e_hs) {
+    extern __shared__ double u[];  // [n][d]
+    const int lane = threadIdx.x;
+    const int rep = blockIdx.x;
+    if (rep >= r) return;
+    for (int q = lane; q < n; q += 64) {
+        const float *xq = x + ((size_t)q * r + rep) * d;
+        double s = 0.0;
+        for (int mu = 0; mu < d; ++mu) {
+            const double v = (double)xq[mu];
+            s = s + v * v;
+        }
+        const double nrm = sqrt(s);
+        for (int mu = 0; mu < d; ++mu) u[q * d + mu] = nrm > 0.0 ? (double)xq[mu] / nrm : 0.0;
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int q = lane; q < n; q += 64) {
+        double h = 0.0;
+        for (int p = 0; p < n; ++p) {
+            double dot = 0.0;
+            for (int mu = 0; mu < d; ++mu) dot = dot + u[p * d + mu] * u[q * d + mu];
+            const double jv = (j_dtype == CHYM_J_I8) ? (double)reinterpret_cast<const int8_t *>(j)[(size_t)p * n + q]
+                                                     : (double)reinterpret_cast<const float *>(j)[(size_t)p * n + q];
+            h = h + jv * dot;
+        }
+        acc += h;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) e_hs[rep] = -acc;
+}
+
+hipError_t launch_readout(int n, int d, int r, const float *x, uint64_t *spins, double *extra, uint8_t *diverged,
+                          hipStream_t stream) {
+    const int block = 256;
+    int grid = (r + block - 1) / block;
+    if (grid > 65535) grid = 65535;
+    hipLaunchKernelGGL(k_readout, dim3(grid), dim3(block), 0, stream, n, d, r, x, spins, extra, diverged);
+    return hipGetLastError();
+}
+
+hipError_t launch_ising_energy(int n, int r, const void *j, int j_dtype, const uint64_t *spins, int32_t *e_i32,
+                               double *e_f64, hipStream_t stream) {
+    const int waves = 4;
+    const int grid = (r + waves - 1) / waves;
+    hipLaunchKernelGGL(k_ising_energy, dim3(grid), dim3(64 * waves), 0, stream, n, r, j, j_dtype, spins, e_i32,
+                       e_f64);
+    return hipGetLastError();
+}
+
+hipError_t launch_hs_energy(int n, int d, int r, const void *j, int j_dtype, const float *x, double *e_hs,
+                            hipStream_t stream) {
+    const size_t lds = sizeof(double) * (size_t)n * d;
+    hipLaunchKernelGGL(k_hs_energy, dim3(r), dim3(64), lds, stream, n, d, r, j, j_dtype, x, e_hs);
+    return hipGetLastError();
+}
+
+}  // namespace chym

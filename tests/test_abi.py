@@ -1,0 +1,121 @@
+"""The C-ABI library loads, exports every declared symbol, and validates its
+arguments before touching a device (CPU only: no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2308_02329_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "chym.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(chym_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_version_and_error_string():
+    lib = L.load()
+    assert lib.chym_version() == 1
+    assert isinstance(lib.chym_last_error(), bytes)
+
+
+def _prob(**kw):
+    base = dict(n=16, d=2, j_dtype=L.CHYM_J_I8, reserved=0, j=0x1000, eps=0.1, btil=1.0, eta=0.0, reserved_f=0.0)
+    base.update(kw)
+    return L.ChymProblem(**base)
+
+
+def _run(**kw):
+    base = dict(r=4, steps=10, start_step=0, precision=L.CHYM_PREC_F32, dt=0.01, reserved_f=0.0, pump=0x2000,
+                x=0x3000, alpha=0x4000)
+    base.update(kw)
+    return L.ChymRun(**base)
+
+
+@pytest.mark.parametrize("pk,rk,msg", [
+    ({"n": 0}, {}, "n = 0"), ({"d": 0}, {}, "d = 0"), ({"d": 5}, {}, "d = 5"), ({"j_dtype": 7}, {}, "j_dtype"),
+    ({"j": None}, {}, "J is NULL"), ({"reserved": 1}, {}, "reserved"), ({"eps": float("inf")}, {}, "finite"),
+    ({}, {"r": 0}, "r = 0"), ({}, {"steps": -1}, "steps"), ({}, {"start_step": -2}, "start_step"),
+    ({}, {"precision": 9}, "precision"), ({}, {"dt": 0.0}, "dt"), ({}, {"dt": float("nan")}, "dt"),
+    ({}, {"x": None}, "NULL"), ({}, {"alpha": None}, "NULL"), ({}, {"pump": None}, "NULL"),
+])
+def test_integrate_rejects_invalid_arguments(pk, rk, msg):
+    lib = L.load()
+    p, r = _prob(**pk), _run(**rk)
+    rc = lib.chym_integrate(ctypes.byref(p), ctypes.byref(r), None)
+    assert rc == L.CHYM_EINVAL
+    assert msg in lib.chym_last_error().decode()
+
+
+def test_null_structs_rejected():
+    lib = L.load()
+    assert lib.chym_integrate(None, ctypes.byref(_run()), None) == L.CHYM_EINVAL
+    assert lib.chym_integrate(ctypes.byref(_prob()), None, None) == L.CHYM_EINVAL
+
+
+def test_unsupported_size_reported_before_device():
+    lib = L.load()
+    rc = lib.chym_integrate(ctypes.byref(_prob(n=1000, d=4)), ctypes.byref(_run()), None)
+    assert rc == L.CHYM_EUNSUPPORTED
+
+
+def test_other_entry_points_validate():
+    lib = L.load()
+    assert lib.chym_readout(0, 2, 4, 0x1000, 0x2000, None, None, None) == L.CHYM_EINVAL
+    assert lib.chym_readout(16, 2, 4, None, 0x2000, None, None, None) == L.CHYM_EINVAL
+    assert lib.chym_readout(16, 2, 4, 0x1000, None, None, None, None) == L.CHYM_OK  # nothing requested
+    # int32 energy needs integer couplings
+    assert lib.chym_ising_energy(16, 4, 0x1000, L.CHYM_J_F32, 0x2000, 0x3000, None, None) == L.CHYM_EINVAL
+    assert lib.chym_ising_energy(4096, 4, 0x1000, L.CHYM_J_I8, 0x2000, 0x3000, None, None) == L.CHYM_EUNSUPPORTED
+    assert lib.chym_hs_energy(3000, 4, 2, 0x1000, L.CHYM_J_I8, 0x2000, 0x3000, None) == L.CHYM_EUNSUPPORTED
+    out = L.ChymOut(e_ising=0x5000)  # energy without spins
+    assert lib.chym_solve(ctypes.byref(_prob()), ctypes.byref(_run()), 0, None, ctypes.byref(out),
+                          None) == L.CHYM_EINVAL
+    assert lib.chym_solve(ctypes.byref(_prob()), ctypes.byref(_run()), -1, None, None, None) == L.CHYM_EINVAL
+
+
+def test_batch_validation():
+    lib = L.load()
+    tasks = (L.ChymTask * 2)(L.ChymTask(prob=_prob(), run=_run()), L.ChymTask(prob=_prob(n=0), run=_run()))
+    nbytes = ctypes.c_size_t(0)
+    assert lib.chym_batch_workspace_size(tasks, 2, ctypes.byref(nbytes)) == L.CHYM_EINVAL
+    assert "task 1" in lib.chym_last_error().decode()
+    assert lib.chym_batch_workspace_size(tasks, 1, ctypes.byref(nbytes)) == L.CHYM_OK
+    assert nbytes.value > 0
+    assert lib.chym_batch_workspace_size(tasks, 0, ctypes.byref(nbytes)) == L.CHYM_EINVAL
+    plan = ctypes.c_void_p()
+    # too small a workspace is reported before any device work
+    assert lib.chym_batch_create(tasks, 1, ctypes.c_void_p(0x10000), 16, ctypes.byref(plan)) == L.CHYM_ENOMEM
+    assert lib.chym_batch_create(tasks, 1, ctypes.c_void_p(0x10001), nbytes.value,
+                                 ctypes.byref(plan)) == L.CHYM_EINVAL
+    assert lib.chym_batch_launch(None, None) == L.CHYM_EINVAL
+    assert lib.chym_batch_destroy(None) == L.CHYM_OK
+
+
+def test_valid_call_without_device_reports_enodev():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = L.load()
+    assert lib.chym_integrate(ctypes.byref(_prob()), ctypes.byref(_run()), None) == L.CHYM_ENODEV
+
+
+def test_python_binding_has_no_fallback(tmp_path, monkeypatch):
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(L, "_lib", None)
+    with pytest.raises(ImportError):
+        L.load()
