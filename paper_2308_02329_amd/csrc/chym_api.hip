@@ -177,7 +177,10 @@ struct Group {
 struct BatchLayout {
     std::vector<Group> groups;
     std::vector<int2> items;  // (task, 16-replica group), grouped and sorted
-    size_t off_tasks, off_items, off_counters, total;
+    size_t off_tasks, off_items, off_counters, off_score, off_first, total;
+    int64_t total_replicas;
+    int max_nd;
+    bool any_readout, any_ising, any_hs;
 };
 
 int validate_out(const chym_problem *prob, const chym_run *run, const chym_out *o) {
@@ -234,10 +237,25 @@ int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
         L->items.insert(L->items.end(), lst.begin(), lst.end());
         L->groups.push_back(g);
     }
+    L->total_replicas = 0;
+    L->max_nd = 1;
+    L->any_readout = L->any_ising = L->any_hs = false;
+    for (int t = 0; t < n_tasks; ++t) {
+        const chym_out &o = tasks[t].out;
+        L->total_replicas += tasks[t].run.r;
+        L->any_readout |= (o.spins || o.extra_frac || o.diverged) != 0;
+        L->any_ising |= (o.e_ising || o.e_ising_f64) != 0;
+        if (o.e_hs) {
+            L->any_hs = true;
+            L->max_nd = std::max(L->max_nd, tasks[t].prob.n * tasks[t].prob.d);
+        }
+    }
     L->off_tasks = 0;
     L->off_items = align_up(sizeof(chym::IntegArgs) * (size_t)n_tasks);
     L->off_counters = L->off_items + align_up(sizeof(int2) * std::max<size_t>(1, L->items.size()));
-    L->total = L->off_counters + align_up(sizeof(int) * std::max<size_t>(1, L->groups.size()));
+    L->off_score = L->off_counters + align_up(sizeof(int) * std::max<size_t>(1, L->groups.size()));
+    L->off_first = L->off_score + align_up(sizeof(chym::ScoreArgs) * (size_t)n_tasks);
+    L->total = L->off_first + align_up(sizeof(int64_t) * ((size_t)n_tasks + 1));
     return CHYM_OK;
 }
 
@@ -250,6 +268,7 @@ struct chym_batch {
     BatchLayout layout;
     char *ws = nullptr;
     int device = -1;
+    int cus = 0;
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> events;
     hipStream_t cap = nullptr;
@@ -291,21 +310,11 @@ int issue_batch(const chym_batch *b, hipStream_t main, const std::vector<hipStre
             if (e != hipSuccess) return hip_fail(e, "join branch");
         }
     }
-    for (const chym_task &tk : b->tasks) {
-        const chym_out &o = tk.out;
-        const int n = tk.prob.n, d = tk.prob.d, r = tk.run.r;
-        if (o.spins || o.extra_frac || o.diverged) {
-            e = chym::launch_readout(n, d, r, tk.run.x, o.spins, o.extra_frac, o.diverged, main);
-            if (e != hipSuccess) return hip_fail(e, "readout launch");
-        }
-        if (o.e_ising || o.e_ising_f64) {
-            e = chym::launch_ising_energy(n, r, tk.prob.j, tk.prob.j_dtype, o.spins, o.e_ising, o.e_ising_f64, main);
-            if (e != hipSuccess) return hip_fail(e, "ising energy launch");
-        }
-        if (o.e_hs) {
-            e = chym::launch_hs_energy(n, d, r, tk.prob.j, tk.prob.j_dtype, tk.run.x, o.e_hs, main);
-            if (e != hipSuccess) return hip_fail(e, "hyperspin energy launch");
-        }
+    if (L.any_readout || L.any_ising || L.any_hs) {
+        e = chym::launch_score_batched(reinterpret_cast<const chym::ScoreArgs *>(b->ws + L.off_score),
+                                       reinterpret_cast<const int64_t *>(b->ws + L.off_first), (int)b->tasks.size(),
+                                       L.total_replicas, L.max_nd, L.any_readout, L.any_ising, L.any_hs, b->cus, main);
+        if (e != hipSuccess) return hip_fail(e, "batched scoring launch");
     }
     return CHYM_OK;
 }
@@ -457,6 +466,7 @@ int chym_batch_create(const chym_task *tasks, int32_t n_tasks, void *workspace, 
     // occupancy-sized persistent grids
     int cus = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    b->cus = cus;
     for (Group &g : b->layout.groups) {
         int per_cu = 0;
         if (e == hipSuccess) e = chym::persistent_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, kPersistentWaves, &per_cu);
@@ -470,6 +480,29 @@ int chym_batch_create(const chym_task *tasks, int32_t n_tasks, void *workspace, 
         e = hipMemcpy(b->ws + L.off_tasks, targs.data(), sizeof(chym::IntegArgs) * n_tasks, hipMemcpyHostToDevice);
     if (e == hipSuccess && !L.items.empty())
         e = hipMemcpy(b->ws + L.off_items, L.items.data(), sizeof(int2) * L.items.size(), hipMemcpyHostToDevice);
+    std::vector<chym::ScoreArgs> sargs(n_tasks);
+    std::vector<int64_t> first(n_tasks + 1, 0);
+    for (int t = 0; t < n_tasks; ++t) {
+        const chym_task &tk = tasks[t];
+        chym::ScoreArgs &sa = sargs[t];
+        sa.x = tk.run.x;
+        sa.j = tk.prob.j;
+        sa.spins = tk.out.spins;
+        sa.e_i32 = tk.out.e_ising;
+        sa.e_f64 = tk.out.e_ising_f64;
+        sa.e_hs = tk.out.e_hs;
+        sa.extra = tk.out.extra_frac;
+        sa.diverged = tk.out.diverged;
+        sa.n = tk.prob.n;
+        sa.d = tk.prob.d;
+        sa.r = tk.run.r;
+        sa.j_dtype = tk.prob.j_dtype;
+        first[t + 1] = first[t] + tk.run.r;
+    }
+    if (e == hipSuccess)
+        e = hipMemcpy(b->ws + L.off_score, sargs.data(), sizeof(chym::ScoreArgs) * n_tasks, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->ws + L.off_first, first.data(), sizeof(int64_t) * (n_tasks + 1), hipMemcpyHostToDevice);
     // record the launch sequence as a graph with one branch per variant group
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     const size_t ng = b->layout.groups.size();

@@ -37,6 +37,25 @@ hipError_t launch_integrate_persistent(int tiles, int d, int xs, int js, int wav
                                        const IntegArgs *tasks, const int2 *items, int n_items, int *counter,
                                        hipStream_t stream);
 
+// Per-task arguments of the batched scoring kernels.
+struct ScoreArgs {
+    const float *x;
+    const void *j;
+    uint64_t *spins;
+    int32_t *e_i32;
+    double *e_f64;
+    double *e_hs;
+    double *extra;
+    uint8_t *diverged;
+    int32_t n, d, r, j_dtype;
+};
+
+// Readout, Ising energy and hyperspin energy of every replica of every task
+// (first = replica prefix table, first[n_tasks] = total_replicas).
+hipError_t launch_score_batched(const ScoreArgs *tasks, const int64_t *first, int n_tasks, int64_t total_replicas,
+                                int max_nd, bool any_readout, bool any_ising, bool any_hs, int cus,
+                                hipStream_t stream);
+
 hipError_t launch_readout(int n, int d, int r, const float *x, uint64_t *spins, double *extra,
                           uint8_t *diverged, hipStream_t stream);
 hipError_t launch_ising_energy(int n, int r, const void *j, int j_dtype, const uint64_t *spins,

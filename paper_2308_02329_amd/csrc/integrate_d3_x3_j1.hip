@@ -1,0 +1,7 @@
+// Instantiates the register-resident integrator for d = 3, 3 state
+// term(s) and 1 coupling term(s), every supported tile count.
+#include "integrate_kernel.h"
+
+namespace chym {
+KernelPair lookup_resident_3_3_1(int tiles) { return lookup_tiles<3, 3, 1>(tiles); }
+}  // namespace chym

@@ -30,9 +30,12 @@
 // kernel, with no LDS, no barrier and no global-memory traffic per step
 // except the D annealing weights alpha[k][mu] (scalar loads).  Wavefronts
 // never wait on each other, so work is handed out per 16-replica group.
+#pragma once
+
 #include "chym_internal.h"
 
 namespace chym {
+
 
 template <int XS>
 struct XSplit {
@@ -213,7 +216,8 @@ __global__ __launch_bounds__(256) void k_integrate_persistent(const IntegArgs *_
     for (;;) {
         int it = 0;
         if (lane == 0) it = atomicAdd(counter, 1);
-        it = __shfl(it, 0, 64);
+        // wave-uniform from here on: the item and its task live in SGPRs
+        it = __builtin_amdgcn_readfirstlane(__shfl(it, 0, 64));
         if (it >= n_items) break;
         const int2 w = items[it];
         const IntegArgs a = tasks[w.x];
@@ -221,20 +225,14 @@ __global__ __launch_bounds__(256) void k_integrate_persistent(const IntegArgs *_
     }
 }
 
-// ------------------------------------------------------------------ dispatch
+
 struct KernelPair {
     void (*single)(IntegArgs);
     void (*persistent)(const IntegArgs *, const int2 *, int, int *);
 };
-typedef KernelPair KernelFn;
-
-template <int NT, int D, int XS, int JS>
-static KernelFn kernel_ptr() {
-    return KernelPair{k_integrate_resident<NT, D, XS, JS>, k_integrate_persistent<NT, D, XS, JS>};
-}
 
 // Largest row-tile count per (d, xs, js) that compiles without scratch
-// spills (state + accumulators + hoisted J fragments within 512 registers).
+// spills (state, accumulators and J fragments within 512 registers).
 constexpr int resident_max_tiles(int d, int xs, int js) {
     if (js == 3) return d == 1 ? 8 : (d <= 3 ? 6 : 5);
     if (d == 1) return 12;
@@ -243,90 +241,39 @@ constexpr int resident_max_tiles(int d, int xs, int js) {
     return 7;
 }
 
-template <int NT, int D>
-static KernelFn lookup_nt(int xs, int js) {
-    if (xs == 3 && js == 1) {
-        if constexpr (NT <= resident_max_tiles(D, 3, 1)) return kernel_ptr<NT, D, 3, 1>();
-    } else if (xs == 1 && js == 1) {
-        if constexpr (NT <= resident_max_tiles(D, 1, 1)) return kernel_ptr<NT, D, 1, 1>();
-    } else if (xs == 3 && js == 3) {
-        if constexpr (NT <= resident_max_tiles(D, 3, 3)) return kernel_ptr<NT, D, 3, 3>();
-    }
-    return KernelPair{nullptr, nullptr};
+template <int NT, int D, int XS, int JS>
+KernelPair variant_or_null() {
+    if constexpr (NT <= resident_max_tiles(D, XS, JS))
+        return KernelPair{k_integrate_resident<NT, D, XS, JS>, k_integrate_persistent<NT, D, XS, JS>};
+    else
+        return KernelPair{nullptr, nullptr};
 }
 
-template <int D>
-static KernelFn lookup_d(int tiles, int xs, int js) {
+// One translation unit per (D, XS, JS) instantiates all tile counts.
+template <int D, int XS, int JS>
+KernelPair lookup_tiles(int tiles) {
     switch (tiles) {
-        case 1: return lookup_nt<1, D>(xs, js);
-        case 2: return lookup_nt<2, D>(xs, js);
-        case 3: return lookup_nt<3, D>(xs, js);
-        case 4: return lookup_nt<4, D>(xs, js);
-        case 5: return lookup_nt<5, D>(xs, js);
-        case 6: return lookup_nt<6, D>(xs, js);
-        case 7: return lookup_nt<7, D>(xs, js);
-        case 8: return lookup_nt<8, D>(xs, js);
-        case 9: return lookup_nt<9, D>(xs, js);
-        case 10: return lookup_nt<10, D>(xs, js);
-        case 11: return lookup_nt<11, D>(xs, js);
-        case 12: return lookup_nt<12, D>(xs, js);
+        case 1: return variant_or_null<1, D, XS, JS>();
+        case 2: return variant_or_null<2, D, XS, JS>();
+        case 3: return variant_or_null<3, D, XS, JS>();
+        case 4: return variant_or_null<4, D, XS, JS>();
+        case 5: return variant_or_null<5, D, XS, JS>();
+        case 6: return variant_or_null<6, D, XS, JS>();
+        case 7: return variant_or_null<7, D, XS, JS>();
+        case 8: return variant_or_null<8, D, XS, JS>();
+        case 9: return variant_or_null<9, D, XS, JS>();
+        case 10: return variant_or_null<10, D, XS, JS>();
+        case 11: return variant_or_null<11, D, XS, JS>();
+        case 12: return variant_or_null<12, D, XS, JS>();
         default: return KernelPair{nullptr, nullptr};
     }
 }
 
-static KernelFn lookup(int tiles, int d, int xs, int js) {
-    switch (d) {
-        case 1: return lookup_d<1>(tiles, xs, js);
-        case 2: return lookup_d<2>(tiles, xs, js);
-        case 3: return lookup_d<3>(tiles, xs, js);
-        case 4: return lookup_d<4>(tiles, xs, js);
-        default: return KernelPair{nullptr, nullptr};
-    }
-}
-
-int resident_tile_limit(int d, int xs, int js) {
-    return (d >= 1 && d <= 4) ? resident_max_tiles(d, xs, js) : 0;
-}
-
-__global__ void k_zero_counters(int *c, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) c[i] = 0;
-}
-
-hipError_t launch_integrate(int tiles, int d, int xs, int js, int waves_per_block, const IntegArgs &a,
-                            hipStream_t stream, bool *supported) {
-    KernelFn fn = lookup(tiles, d, xs, js);
-    *supported = fn.single != nullptr;
-    if (!fn.single) return hipSuccess;
-    const int reps_per_block = 16 * waves_per_block;
-    const int blocks = (a.r + reps_per_block - 1) / reps_per_block;
-    hipLaunchKernelGGL(fn.single, dim3(blocks), dim3(64 * waves_per_block), 0, stream, a);
-    return hipGetLastError();
-}
-
-bool integrate_variant_exists(int tiles, int d, int xs, int js) { return lookup(tiles, d, xs, js).single != nullptr; }
-
-hipError_t persistent_occupancy(int tiles, int d, int xs, int js, int waves_per_block, int *blocks_per_cu) {
-    KernelFn fn = lookup(tiles, d, xs, js);
-    *blocks_per_cu = 0;
-    if (!fn.persistent) return hipErrorInvalidDeviceFunction;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn.persistent, 64 * waves_per_block, 0);
-}
-
-hipError_t launch_zero_counters(int *counters, int n, hipStream_t stream) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_counters, dim3((n + 255) / 256), dim3(256), 0, stream, counters, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_integrate_persistent(int tiles, int d, int xs, int js, int waves_per_block, int blocks,
-                                       const IntegArgs *tasks, const int2 *items, int n_items, int *counter,
-                                       hipStream_t stream) {
-    KernelFn fn = lookup(tiles, d, xs, js);
-    if (!fn.persistent) return hipErrorInvalidDeviceFunction;
-    hipLaunchKernelGGL(fn.persistent, dim3(blocks), dim3(64 * waves_per_block), 0, stream, tasks, items, n_items,
-                       counter);
-    return hipGetLastError();
-}
+#define CHYM_DECLARE_LOOKUP(D, XS, JS) KernelPair lookup_resident_##D##_##XS##_##JS(int tiles);
+CHYM_DECLARE_LOOKUP(1, 3, 1) CHYM_DECLARE_LOOKUP(1, 1, 1) CHYM_DECLARE_LOOKUP(1, 3, 3)
+CHYM_DECLARE_LOOKUP(2, 3, 1) CHYM_DECLARE_LOOKUP(2, 1, 1) CHYM_DECLARE_LOOKUP(2, 3, 3)
+CHYM_DECLARE_LOOKUP(3, 3, 1) CHYM_DECLARE_LOOKUP(3, 1, 1) CHYM_DECLARE_LOOKUP(3, 3, 3)
+CHYM_DECLARE_LOOKUP(4, 3, 1) CHYM_DECLARE_LOOKUP(4, 1, 1) CHYM_DECLARE_LOOKUP(4, 3, 3)
+#undef CHYM_DECLARE_LOOKUP
 
 }  // namespace chym

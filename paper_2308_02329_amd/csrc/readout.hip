@@ -1,17 +1,18 @@
 // Readout and scoring kernels: sign readout of the Ising spins, exact Ising
 // energy, and the float64 hyperspin energy of Eq. (3).
+#include <algorithm>
+
 #include "chym_internal.h"
 
 namespace chym {
 
-// One thread per replica.  Walks the rows of its replica once: packs the
+// Readout of one replica by one thread.  Walks the rows once: packs the
 // spin bits (sigma_p = +1 iff x_{p,1} >= 0), and computes the largest share
 // of the extra components and the divergence flag in the same pass.
-__global__ __launch_bounds__(256) void k_readout(int n, int d, int r, const float *__restrict__ x,
-                                                 uint64_t *__restrict__ spins, double *__restrict__ extra,
-                                                 uint8_t *__restrict__ diverged) {
+__device__ void readout_one(int n, int d, int r, int rep, const float *__restrict__ x, uint64_t *__restrict__ spins,
+                            double *__restrict__ extra, uint8_t *__restrict__ diverged) {
     const int w = (n + 63) >> 6;
-    for (int rep = blockIdx.x * blockDim.x + threadIdx.x; rep < r; rep += gridDim.x * blockDim.x) {
+    {
         uint64_t word = 0;
         double m = 0.0;
         int bad = 0;
@@ -38,6 +39,13 @@ __global__ __launch_bounds__(256) void k_readout(int n, int d, int r, const floa
     }
 }
 
+__global__ __launch_bounds__(256) void k_readout(int n, int d, int r, const float *__restrict__ x,
+                                                 uint64_t *__restrict__ spins, double *__restrict__ extra,
+                                                 uint8_t *__restrict__ diverged) {
+    for (int rep = blockIdx.x * blockDim.x + threadIdx.x; rep < r; rep += gridDim.x * blockDim.x)
+        readout_one(n, d, r, rep, x, spins, extra, diverged);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -49,15 +57,13 @@ __device__ __forceinline__ int spin_of(const uint64_t *s, int p) {
     return ((s[p >> 6] >> (p & 63)) & 1ull) ? 1 : -1;
 }
 
-// One wavefront per replica: E = -sum_q sigma_q sum_p J_pq sigma_p.  Lanes
-// own columns q (coalesced reads of each row of J); the sigma_p are uniform
-// across the wave.  Integer J: exact int32; float J: float64.
-__global__ __launch_bounds__(256) void k_ising_energy(int n, int r, const void *__restrict__ j, int j_dtype,
-                                                      const uint64_t *__restrict__ spins,
-                                                      int32_t *__restrict__ e_i32, double *__restrict__ e_f64) {
+// Ising energy of one replica by one wavefront:
+// E = -sum_q sigma_q sum_p J_pq sigma_p.  Lanes own columns q (coalesced
+// reads of each row of J); the sigma_p are uniform across the wave.  Integer
+// J: exact int32; float J: float64.
+__device__ void ising_one(int n, int rep, const void *__restrict__ j, int j_dtype, const uint64_t *__restrict__ spins,
+                          int32_t *__restrict__ e_i32, double *__restrict__ e_f64) {
     const int lane = threadIdx.x & 63;
-    const int rep = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (rep >= r) return;
     const int w = (n + 63) >> 6;
     const uint64_t *s = spins + (size_t)rep * w;
     if (j_dtype == CHYM_J_I8) {
@@ -86,15 +92,21 @@ __global__ __launch_bounds__(256) void k_ising_energy(int n, int r, const void *
     }
 }
 
-// One wavefront per block and per replica.  The unit vectors u_p =
-// x_p / |x_p| (0 for a zero hyperspin) are formed in float64 in LDS, then
-// E_hs = -sum_q sum_p J_pq (u_p . u_q) with lanes owning columns q.
-__global__ __launch_bounds__(64) void k_hs_energy(int n, int d, int r, const void *__restrict__ j, int j_dtype,
-                                                  const float *__restrict__ x, double *__restrict__ e_hs) {
-    extern __shared__ double u[];  // [n][d]
-    const int lane = threadIdx.x;
-    const int rep = blockIdx.x;
+__global__ __launch_bounds__(256) void k_ising_energy(int n, int r, const void *__restrict__ j, int j_dtype,
+                                                      const uint64_t *__restrict__ spins,
+                                                      int32_t *__restrict__ e_i32, double *__restrict__ e_f64) {
+    const int rep = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (rep >= r) return;
+    ising_one(n, rep, j, j_dtype, spins, e_i32, e_f64);
+}
+
+// Hyperspin energy of one replica by one wavefront, u = its private LDS
+// area [n][d].  The unit vectors u_p = x_p / |x_p| (0 for a zero hyperspin)
+// are formed in float64, then E_hs = -sum_q sum_p J_pq (u_p . u_q) with
+// lanes owning columns q.
+__device__ void hs_one(int n, int d, int r, int rep, const void *__restrict__ j, int j_dtype,
+                       const float *__restrict__ x, double *__restrict__ e_hs, double *u) {
+    const int lane = threadIdx.x & 63;
     for (int q = lane; q < n; q += 64) {
         const float *xq = x + ((size_t)q * r + rep) * d;
         double s = 0.0;
@@ -105,7 +117,9 @@ __global__ __launch_bounds__(64) void k_hs_energy(int n, int d, int r, const voi
         const double nrm = sqrt(s);
         for (int mu = 0; mu < d; ++mu) u[q * d + mu] = nrm > 0.0 ? (double)xq[mu] / nrm : 0.0;
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     double acc = 0.0;
     for (int q = lane; q < n; q += 64) {
         double h = 0.0;
@@ -120,6 +134,66 @@ __global__ __launch_bounds__(64) void k_hs_energy(int n, int d, int r, const voi
     }
     acc = wave_sum(acc);
     if (lane == 0) e_hs[rep] = -acc;
+}
+
+__global__ __launch_bounds__(64) void k_hs_energy(int n, int d, int r, const void *__restrict__ j, int j_dtype,
+                                                  const float *__restrict__ x, double *__restrict__ e_hs) {
+    extern __shared__ double u[];  // [n][d]
+    const int rep = blockIdx.x;
+    if (rep >= r) return;
+    hs_one(n, d, r, rep, j, j_dtype, x, e_hs, u);
+}
+
+// ------------------------------------------------------- batched scoring
+// Global replica index g of a batch maps to (task, replica) through the
+// prefix table first[t] = sum of r over tasks < t (first[n_tasks] = total).
+__device__ __forceinline__ int task_of(const int64_t *__restrict__ first, int n_tasks, int64_t g) {
+    int lo = 0, hi = n_tasks - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_readout_batched(const ScoreArgs *__restrict__ t, const int64_t *__restrict__ first,
+                                                         int n_tasks) {
+    const int64_t total = first[n_tasks];
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int k = task_of(first, n_tasks, g);
+        const ScoreArgs &a = t[k];
+        if (!a.spins && !a.extra && !a.diverged) continue;
+        readout_one(a.n, a.d, a.r, (int)(g - first[k]), a.x, a.spins, a.extra, a.diverged);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ising_batched(const ScoreArgs *__restrict__ t, const int64_t *__restrict__ first,
+                                                       int n_tasks) {
+    const int64_t total = first[n_tasks];
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g < total; g += waves) {
+        const int k = __builtin_amdgcn_readfirstlane(task_of(first, n_tasks, g));
+        const ScoreArgs &a = t[k];
+        if (!a.e_i32 && !a.e_f64) continue;
+        ising_one(a.n, (int)(g - first[k]), a.j, a.j_dtype, a.spins, a.e_i32, a.e_f64);
+    }
+}
+
+// LDS: one [max n*d] float64 area per wavefront.
+__global__ __launch_bounds__(256) void k_hs_batched(const ScoreArgs *__restrict__ t, const int64_t *__restrict__ first,
+                                                    int n_tasks, int max_nd) {
+    extern __shared__ double u_all[];
+    double *u = u_all + (size_t)(threadIdx.x >> 6) * max_nd;
+    const int64_t total = first[n_tasks];
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g < total; g += waves) {
+        const int k = __builtin_amdgcn_readfirstlane(task_of(first, n_tasks, g));
+        const ScoreArgs &a = t[k];
+        if (!a.e_hs) continue;
+        hs_one(a.n, a.d, a.r, (int)(g - first[k]), a.j, a.j_dtype, a.x, a.e_hs, u);
+        __builtin_amdgcn_wave_barrier();  // u is rewritten by the next replica
+    }
 }
 
 hipError_t launch_readout(int n, int d, int r, const float *x, uint64_t *spins, double *extra, uint8_t *diverged,
@@ -145,6 +219,34 @@ hipError_t launch_hs_energy(int n, int d, int r, const void *j, int j_dtype, con
     const size_t lds = sizeof(double) * (size_t)n * d;
     hipLaunchKernelGGL(k_hs_energy, dim3(r), dim3(64), lds, stream, n, d, r, j, j_dtype, x, e_hs);
     return hipGetLastError();
+}
+
+hipError_t launch_score_batched(const ScoreArgs *tasks, const int64_t *first, int n_tasks, int64_t total_replicas,
+                                int max_nd, bool any_readout, bool any_ising, bool any_hs, int cus,
+                                hipStream_t stream) {
+    if (total_replicas <= 0) return hipSuccess;
+    const int grid_cap = 16 * (cus > 0 ? cus : 256);
+    if (any_readout) {
+        int grid = (int)std::min<int64_t>((total_replicas + 255) / 256, grid_cap);
+        hipLaunchKernelGGL(k_readout_batched, dim3(grid), dim3(256), 0, stream, tasks, first, n_tasks);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (any_ising) {
+        int grid = (int)std::min<int64_t>((total_replicas + 3) / 4, grid_cap);
+        hipLaunchKernelGGL(k_ising_batched, dim3(grid), dim3(256), 0, stream, tasks, first, n_tasks);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (any_hs) {
+        const int waves = max_nd <= 2048 ? 4 : 1;
+        const size_t lds = sizeof(double) * (size_t)max_nd * waves;
+        int grid = (int)std::min<int64_t>((total_replicas + waves - 1) / waves, grid_cap);
+        hipLaunchKernelGGL(k_hs_batched, dim3(grid), dim3(64 * waves), lds, stream, tasks, first, n_tasks, max_nd);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace chym
