@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--dt", type=float, default=0.01)
     ap.add_argument("--precision", type=str, default="f32", choices=["f32", "bf16"])
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--autotune", type=int, default=1, help="time the launch plans of each variant first")
+    ap.add_argument("--plan-cache", type=str, default="", help="load plans from this file instead of tuning")
     ap.add_argument("--cpu-baseline", type=int, default=1, help="0 disables the oracle timing leg")
     ap.add_argument("--cpu-replicas", type=int, default=256)
     return ap.parse_args()
@@ -129,6 +131,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    plans = {}
+    if args.plan_cache:
+        api.chym_plan_load(args.plan_cache)
+    elif args.autotune:
+        for d in [int(v) for v in args.dims.split(",")]:
+            best, cands = api.chym_plan_autotune(args.n, d, args.precision, torch.int8, steps=400)
+            plans[str(d)] = {"chosen": best, "candidates": cands}
     wl = build_workload(args, torch, synth, api, dev)
     stream = torch.cuda.current_stream()
     dims = wl["dims"]
@@ -191,7 +200,9 @@ def main():
            "roofline": roof,
            "integrate_ms_per_step": {str(d): kern_ms[d] / args.steps for d in dims},
            "score_ms_per_step": score_ms / args.steps,
-           "diverged_runs": diverged}
+           "diverged_runs": diverged,
+           "plans": {str(d): api.chym_plan_get(args.n, d, args.precision, torch.int8) for d in dims},
+           "autotune": plans}
     if args.cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args, synth, wl)
     for p in list(wl["plans"].values()) + [wl["score_plan"]]:

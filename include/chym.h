@@ -203,6 +203,67 @@ int chym_batch_launch_nograph(const chym_batch *plan, chym_stream_t stream);
  * workspace is not touched.  Waits for the plan's outstanding launches. */
 int chym_batch_destroy(chym_batch *plan);
 
+/* ------------------------------------------------------------------------
+ * Launch plans and the autotuner.  A plan entry picks, for one kernel
+ * variant (n rounded up to 16-row tiles, d, precision, J storage), how the
+ * batched path runs it:
+ *   CHYM_KERNEL_REGJ  each wavefront gathers J into its own registers and
+ *                     takes work items of 16 replicas (one wavefront per
+ *                     SIMD when the state is large);
+ *   CHYM_KERNEL_LDSJ  a block of `waves` wavefronts stages J once in LDS and
+ *                     takes work items of 16 * waves replicas, leaving
+ *                     registers for two wavefronts per SIMD.
+ * The table is process-wide and starts empty (CHYM_KERNEL_REGJ, 4 waves per
+ * block, for every variant).  Plans change speed only, never results.
+ */
+#define CHYM_KERNEL_AUTO 0
+#define CHYM_KERNEL_REGJ 1
+#define CHYM_KERNEL_LDSJ 2
+
+typedef struct chym_plan_entry {
+    int32_t n;         /* problem size the entry applies to (any n with the same 16-row tile count) */
+    int32_t d;
+    int32_t precision; /* CHYM_PREC_* */
+    int32_t j_dtype;   /* CHYM_J_* */
+    int32_t kernel;    /* CHYM_KERNEL_REGJ or CHYM_KERNEL_LDSJ (CHYM_KERNEL_AUTO: remove the entry) */
+    int32_t waves;     /* wavefronts per block, 1..4 */
+    float ms;          /* autotune: measured time of the probe run of this entry (informational) */
+    float reserved;    /* must be 0 */
+} chym_plan_entry;
+
+/* Install (or, with CHYM_KERNEL_AUTO, remove) a plan entry. */
+int chym_plan_set(const chym_plan_entry *entry);
+
+/* The entry the batched path will use for this problem shape (the default
+ * when none was set). */
+int chym_plan_get(int32_t n, int32_t d, int32_t precision, int32_t j_dtype, chym_plan_entry *entry);
+
+/* Device workspace bytes chym_plan_autotune needs for `replicas` replicas. */
+int chym_plan_autotune_workspace_size(int32_t n, int32_t d, int32_t replicas, int32_t steps, size_t *bytes);
+
+/* Times every candidate plan for this problem shape on a synthetic problem
+ * (+-1 or Gaussian J, `replicas` replicas, `steps` Euler steps) built in the
+ * caller's workspace, installs the fastest, and returns it in *best.  The
+ * candidates and their times are written to cand[0 .. *n_cand-1] when cand
+ * is not NULL (capacity max_cand).  Synchronizes the host with the device. */
+int chym_plan_autotune(int32_t n, int32_t d, int32_t precision, int32_t j_dtype, int32_t replicas, int32_t steps,
+                       void *workspace, size_t ws_bytes, chym_plan_entry *best, chym_plan_entry *cand,
+                       int32_t max_cand, int32_t *n_cand, chym_stream_t stream);
+
+/* The three-term bf16 split that the float32 form feeds to the matrix
+ * cores, exposed for verification: for each of the n floats of x (device),
+ * hi[i], mid[i], lo[i] (device, bf16 bit patterns) satisfy
+ * hi = round-to-nearest-even bf16 of x and hi + mid + lo == x exactly when
+ * |x| >= 2^-100 (the residual terms are then normal floats; below that they
+ * may be flushed to zero, an error of at most 2^-8 |x|).  n must be a
+ * multiple of 8; hi, mid and lo 16-byte aligned. */
+int chym_split3_bf16(const float *x, int64_t n, uint16_t *hi, uint16_t *mid, uint16_t *lo, chym_stream_t stream);
+
+/* Write the plan table to / merge it from a text file (one entry per line:
+ * tiles d precision j_dtype kernel waves ms). */
+int chym_plan_save(const char *path);
+int chym_plan_load(const char *path);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,8 +25,14 @@ CHYM_PREC_BF16 = 1
 EXPORTS = (
     "chym_version", "chym_last_error", "chym_integrate", "chym_readout", "chym_ising_energy",
     "chym_hs_energy", "chym_solve", "chym_batch_workspace_size", "chym_batch_create",
-    "chym_batch_launch", "chym_batch_launch_nograph", "chym_batch_destroy",
+    "chym_batch_launch", "chym_batch_launch_nograph", "chym_batch_destroy", "chym_plan_set", "chym_plan_get",
+    "chym_plan_autotune_workspace_size", "chym_plan_autotune", "chym_split3_bf16", "chym_plan_save",
+    "chym_plan_load",
 )
+
+CHYM_KERNEL_AUTO = 0
+CHYM_KERNEL_REGJ = 1
+CHYM_KERNEL_LDSJ = 2
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -81,6 +87,7 @@ def load():
     lib.chym_solve.argtypes = [P(ChymProblem), P(ChymRun), _i32, _vp, P(ChymOut), _vp]
     lib.chym_solve.restype = ctypes.c_int
     _load_batch(lib)
+    _load_plan(lib)
     _lib = lib
     return lib
 
@@ -107,3 +114,23 @@ def _load_batch(lib):
     lib.chym_batch_launch_nograph.restype = ctypes.c_int
     lib.chym_batch_destroy.argtypes = [_vp]
     lib.chym_batch_destroy.restype = ctypes.c_int
+
+
+class ChymPlanEntry(ctypes.Structure):
+    _fields_ = [("n", _i32), ("d", _i32), ("precision", _i32), ("j_dtype", _i32), ("kernel", _i32),
+                ("waves", _i32), ("ms", ctypes.c_float), ("reserved", ctypes.c_float)]
+
+
+def _load_plan(lib):
+    P = ctypes.POINTER
+    lib.chym_plan_set.argtypes = [P(ChymPlanEntry)]
+    lib.chym_plan_get.argtypes = [_i32, _i32, _i32, _i32, P(ChymPlanEntry)]
+    lib.chym_plan_autotune_workspace_size.argtypes = [_i32, _i32, _i32, _i32, P(ctypes.c_size_t)]
+    lib.chym_plan_autotune.argtypes = [_i32, _i32, _i32, _i32, _i32, _i32, _vp, ctypes.c_size_t, P(ChymPlanEntry),
+                                       P(ChymPlanEntry), _i32, P(_i32), _vp]
+    lib.chym_split3_bf16.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
+    lib.chym_plan_save.argtypes = [ctypes.c_char_p]
+    lib.chym_plan_load.argtypes = [ctypes.c_char_p]
+    for f in ("chym_plan_set", "chym_plan_get", "chym_plan_autotune_workspace_size", "chym_plan_autotune",
+              "chym_split3_bf16", "chym_plan_save", "chym_plan_load"):
+        getattr(lib, f).restype = ctypes.c_int

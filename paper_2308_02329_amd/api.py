@@ -12,14 +12,16 @@ import ctypes
 import torch
 
 from . import _lib as L
-from ._lib import (CHYM_J_F32, CHYM_J_I8, CHYM_PREC_BF16, CHYM_PREC_F32, ChymError, ChymOut,
-                   ChymProblem, ChymRun)
+from ._lib import (CHYM_J_F32, CHYM_J_I8, CHYM_KERNEL_AUTO, CHYM_KERNEL_LDSJ, CHYM_KERNEL_REGJ,
+                   CHYM_PREC_BF16, CHYM_PREC_F32, ChymError, ChymOut, ChymPlanEntry, ChymProblem, ChymRun)
 
 __all__ = ["chym_version", "chym_last_error", "chym_integrate", "chym_readout", "chym_ising_energy",
            "chym_hs_energy", "chym_solve", "make_problem", "make_run", "spin_words", "ChymError",
            "CHYM_J_I8", "CHYM_J_F32", "CHYM_PREC_F32", "CHYM_PREC_BF16", "precision_code",
            "chym_batch_workspace_size", "chym_batch_create", "chym_batch_launch", "chym_batch_launch_nograph",
-           "chym_batch_destroy", "ChymBatch"]
+           "chym_batch_destroy", "ChymBatch", "chym_plan_set", "chym_plan_get", "chym_plan_autotune",
+           "chym_plan_save", "chym_plan_load", "chym_split3_bf16", "CHYM_KERNEL_REGJ", "CHYM_KERNEL_LDSJ",
+           "CHYM_KERNEL_AUTO"]
 
 
 def precision_code(p) -> int:
@@ -253,3 +255,66 @@ def chym_batch_destroy(batch: ChymBatch):
         h, batch.handle = batch.handle, None
         L.check(L.load().chym_batch_destroy(h), "chym_batch_destroy")
     batch.handle = None
+
+
+# ------------------------------------------------------------------ plans
+def _entry_dict(e: ChymPlanEntry) -> dict:
+    return dict(n=e.n, d=e.d, precision=e.precision, j_dtype=e.j_dtype, kernel=e.kernel, waves=e.waves, ms=e.ms)
+
+
+def _jcode(j_dtype) -> int:
+    if isinstance(j_dtype, torch.dtype):
+        return CHYM_J_I8 if j_dtype == torch.int8 else CHYM_J_F32
+    return int(j_dtype)
+
+
+def chym_plan_set(n, d, precision, j_dtype, kernel, waves=4):
+    e = ChymPlanEntry(n=n, d=d, precision=precision_code(precision), j_dtype=_jcode(j_dtype), kernel=int(kernel),
+                      waves=int(waves), ms=0.0, reserved=0.0)
+    L.check(L.load().chym_plan_set(ctypes.byref(e)), "chym_plan_set")
+
+
+def chym_plan_get(n, d, precision, j_dtype) -> dict:
+    e = ChymPlanEntry()
+    L.check(L.load().chym_plan_get(n, d, precision_code(precision), _jcode(j_dtype), ctypes.byref(e)),
+            "chym_plan_get")
+    return _entry_dict(e)
+
+
+def chym_plan_autotune(n, d, precision, j_dtype, replicas=None, steps=200, device=None, stream=None):
+    """Time the candidate plans on a synthetic problem and install the best.
+    Returns (best, candidates) as dicts."""
+    lib = L.load()
+    dev = torch.device("cuda") if device is None else torch.device(device)
+    if replicas is None:
+        cus = torch.cuda.get_device_properties(dev).multi_processor_count
+        replicas = cus * 4 * 2 * 16 * 2  # two rounds of two wavefronts per SIMD
+    nbytes = ctypes.c_size_t(0)
+    L.check(lib.chym_plan_autotune_workspace_size(n, d, replicas, steps, ctypes.byref(nbytes)),
+            "chym_plan_autotune_workspace_size")
+    ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    best = ChymPlanEntry()
+    cands = (ChymPlanEntry * 8)()
+    nc = ctypes.c_int32(0)
+    L.check(lib.chym_plan_autotune(n, d, precision_code(precision), _jcode(j_dtype), replicas, steps,
+                                   ctypes.c_void_p(ws.data_ptr() + off), int(nbytes.value), ctypes.byref(best), cands,
+                                   8, ctypes.byref(nc), _stream(stream)), "chym_plan_autotune")
+    return _entry_dict(best), [_entry_dict(cands[i]) for i in range(nc.value)]
+
+
+def chym_plan_save(path):
+    L.check(L.load().chym_plan_save(str(path).encode()), "chym_plan_save")
+
+
+def chym_plan_load(path):
+    L.check(L.load().chym_plan_load(str(path).encode()), "chym_plan_load")
+
+
+def chym_split3_bf16(x):
+    """(hi, mid, lo) bf16 bit patterns (int16 tensors) of the float32 form's split."""
+    n = x.numel()
+    _need(x, "x", torch.float32)
+    hi, mid, lo = (torch.empty(n, dtype=torch.int16, device=x.device) for _ in range(3))
+    L.check(L.load().chym_split3_bf16(_vp(x), n, _vp(hi), _vp(mid), _vp(lo), _stream(None)), "chym_split3_bf16")
+    return hi, mid, lo

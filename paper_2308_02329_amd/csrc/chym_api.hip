@@ -163,6 +163,50 @@ int validate_hs(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dtype,
 }
 
 
+// ---------------------------------------------------------------- plans
+typedef std::tuple<int, int, int, int> VariantKey;  // (tiles, d, xs, js)
+
+struct PlanValue {
+    int kind;   // chym::kKernelRegJ / kKernelLdsJ
+    int waves;  // wavefronts per block
+    float ms;
+};
+
+std::mutex g_plan_mu;
+std::map<VariantKey, PlanValue> g_plan;
+
+constexpr int kDefaultWaves = 4;
+constexpr int kPersistentWaves = 4;
+
+VariantKey key_of(const Variant &v, int d) { return std::make_tuple(v.tiles, d, v.xs, v.js); }
+
+PlanValue plan_for(const VariantKey &k) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plan.find(k);
+    if (it != g_plan.end()) return it->second;
+    return PlanValue{chym::kKernelRegJ, kDefaultWaves, 0.0f};
+}
+
+Variant variant_of_shape(int n, int precision, int j_dtype) {
+    Variant v;
+    v.tiles = (n + 15) / 16;
+    v.xs = precision == CHYM_PREC_F32 ? 3 : 1;
+    v.js = (precision == CHYM_PREC_F32 && j_dtype == CHYM_J_F32) ? 3 : 1;
+    return v;
+}
+
+int validate_shape(int32_t n, int32_t d, int32_t precision, int32_t j_dtype) {
+    if (n < 1) return fail(CHYM_EINVAL, "n = %d must be >= 1", n);
+    if (d < 1 || d > 4) return fail(CHYM_EINVAL, "d = %d must be in 1..4", d);
+    if (precision != CHYM_PREC_F32 && precision != CHYM_PREC_BF16)
+        return fail(CHYM_EINVAL, "precision = %d is not CHYM_PREC_F32 or CHYM_PREC_BF16", precision);
+    if (j_dtype != CHYM_J_I8 && j_dtype != CHYM_J_F32) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
+    const Variant v = variant_of_shape(n, precision, j_dtype);
+    if (v.tiles > chym::resident_tile_limit(d, v.xs, v.js))
+        return fail(CHYM_EUNSUPPORTED, "n = %d with d = %d is beyond the resident integrator", n, d);
+    return CHYM_OK;
+}
+
 // ---------------------------------------------------------------- batches
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -170,13 +214,14 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Group {
     Variant v;
     int d;
+    int kind, waves;  // launch plan of this variant
     int item_off, n_items;
     int blocks;
 };
 
 struct BatchLayout {
     std::vector<Group> groups;
-    std::vector<int2> items;  // (task, 16-replica group), grouped and sorted
+    std::vector<int2> items;  // (task, replica slab), grouped and sorted
     size_t off_tasks, off_items, off_counters, off_score, off_first, total;
     int64_t total_replicas;
     int max_nd;
@@ -212,10 +257,13 @@ int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
             return fail(rc, "task %d: %s", t, m.c_str());
         }
         const Variant v = variant_of(&tk.prob, &tk.run);
-        auto &lst = by_variant[std::make_tuple(v.tiles, tk.prob.d, v.xs, v.js)];
+        const VariantKey key = key_of(v, tk.prob.d);
+        auto &lst = by_variant[key];
         if (tk.run.steps == 0) continue;
-        const int groups = (tk.run.r + 15) / 16;
-        for (int g = 0; g < groups; ++g) lst.push_back(make_int2(t, g));
+        const PlanValue pv = plan_for(key);
+        const int slab = pv.kind == chym::kKernelLdsJ ? 16 * pv.waves : 16;
+        const int slabs = (tk.run.r + slab - 1) / slab;
+        for (int g = 0; g < slabs; ++g) lst.push_back(make_int2(t, g));
     }
     L->groups.clear();
     L->items.clear();
@@ -231,6 +279,9 @@ int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
         g.d = std::get<1>(kv.first);
         g.v.xs = std::get<2>(kv.first);
         g.v.js = std::get<3>(kv.first);
+        const PlanValue pv = plan_for(kv.first);
+        g.kind = pv.kind;
+        g.waves = pv.kind == chym::kKernelLdsJ ? pv.waves : kPersistentWaves;
         g.item_off = (int)L->items.size();
         g.n_items = (int)lst.size();
         g.blocks = 0;
@@ -258,8 +309,6 @@ int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
     L->total = L->off_first + align_up(sizeof(int64_t) * ((size_t)n_tasks + 1));
     return CHYM_OK;
 }
-
-constexpr int kPersistentWaves = 4;
 
 }  // namespace
 
@@ -301,7 +350,7 @@ int issue_batch(const chym_batch *b, hipStream_t main, const std::vector<hipStre
             e = hipStreamWaitEvent(s, (*events)[0], 0);
             if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
         }
-        e = chym::launch_integrate_persistent(g.v.tiles, g.d, g.v.xs, g.v.js, kPersistentWaves, g.blocks, tasks_d,
+        e = chym::launch_integrate_persistent(g.v.tiles, g.d, g.v.xs, g.v.js, g.kind, g.waves, g.blocks, tasks_d,
                                               items_d + g.item_off, g.n_items, counters + gi, s);
         if (e != hipSuccess) return hip_fail(e, "persistent integrate launch");
         if (fork) {
@@ -469,8 +518,8 @@ int chym_batch_create(const chym_task *tasks, int32_t n_tasks, void *workspace, 
     b->cus = cus;
     for (Group &g : b->layout.groups) {
         int per_cu = 0;
-        if (e == hipSuccess) e = chym::persistent_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, kPersistentWaves, &per_cu);
-        const int need = (g.n_items + kPersistentWaves - 1) / kPersistentWaves;
+        if (e == hipSuccess) e = chym::persistent_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, g.kind, g.waves, &per_cu);
+        const int need = g.kind == chym::kKernelLdsJ ? g.n_items : (g.n_items + g.waves - 1) / g.waves;
         g.blocks = std::max(1, std::min(need, std::max(1, per_cu) * cus));
     }
     // task table and work list
@@ -563,6 +612,227 @@ int chym_batch_destroy(chym_batch *plan) {
     hipError_t e = hipDeviceSynchronize();
     release(plan);
     return e == hipSuccess ? CHYM_OK : hip_fail(e, "hipDeviceSynchronize");
+}
+
+// ------------------------------------------------------------------ plans
+int chym_plan_set(const chym_plan_entry *e) {
+    if (!e) return fail(CHYM_EINVAL, "entry is NULL");
+    int rc = validate_shape(e->n, e->d, e->precision, e->j_dtype);
+    if (rc) return rc;
+    if (e->reserved != 0.0f) return fail(CHYM_EINVAL, "reserved fields must be 0");
+    const VariantKey k = key_of(variant_of_shape(e->n, e->precision, e->j_dtype), e->d);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (e->kernel == CHYM_KERNEL_AUTO) {
+        g_plan.erase(k);
+        return CHYM_OK;
+    }
+    if (e->kernel != CHYM_KERNEL_REGJ && e->kernel != CHYM_KERNEL_LDSJ)
+        return fail(CHYM_EINVAL, "kernel = %d is not a CHYM_KERNEL_* value", e->kernel);
+    if (e->waves < 1 || e->waves > 4) return fail(CHYM_EINVAL, "waves = %d must be in 1..4", e->waves);
+    g_plan[k] = PlanValue{e->kernel == CHYM_KERNEL_LDSJ ? chym::kKernelLdsJ : chym::kKernelRegJ, e->waves, e->ms};
+    return CHYM_OK;
+}
+
+int chym_plan_get(int32_t n, int32_t d, int32_t precision, int32_t j_dtype, chym_plan_entry *e) {
+    if (!e) return fail(CHYM_EINVAL, "entry is NULL");
+    int rc = validate_shape(n, d, precision, j_dtype);
+    if (rc) return rc;
+    const PlanValue pv = plan_for(key_of(variant_of_shape(n, precision, j_dtype), d));
+    e->n = n;
+    e->d = d;
+    e->precision = precision;
+    e->j_dtype = j_dtype;
+    e->kernel = pv.kind == chym::kKernelLdsJ ? CHYM_KERNEL_LDSJ : CHYM_KERNEL_REGJ;
+    e->waves = pv.waves;
+    e->ms = pv.ms;
+    e->reserved = 0.0f;
+    return CHYM_OK;
+}
+
+namespace {
+struct ProbeLayout {
+    size_t off_j, off_pump, off_x, off_alpha, off_batch, total, batch_bytes;
+};
+
+ProbeLayout probe_layout(int n, int d, int r, int steps) {
+    ProbeLayout L;
+    L.off_j = 0;
+    L.off_pump = align_up((size_t)n * n * 4);
+    L.off_x = L.off_pump + align_up((size_t)r * 4);
+    L.off_alpha = L.off_x + align_up((size_t)n * r * d * 4);
+    L.off_batch = L.off_alpha + align_up((size_t)steps * d * 4);
+    // batch workspace of one task: its work list is largest with 16-replica items
+    L.batch_bytes = align_up(sizeof(chym::IntegArgs)) + align_up(sizeof(int2) * (size_t)((r + 15) / 16)) +
+                    align_up(sizeof(int)) + align_up(sizeof(chym::ScoreArgs)) + align_up(2 * sizeof(int64_t));
+    L.total = L.off_batch + L.batch_bytes;
+    return L;
+}
+}  // namespace
+
+int chym_plan_autotune_workspace_size(int32_t n, int32_t d, int32_t replicas, int32_t steps, size_t *bytes) {
+    if (!bytes) return fail(CHYM_EINVAL, "bytes is NULL");
+    if (n < 1 || d < 1 || d > 4 || replicas < 1 || steps < 1) return fail(CHYM_EINVAL, "bad probe shape");
+    *bytes = probe_layout(n, d, replicas, steps).total;
+    return CHYM_OK;
+}
+
+int chym_plan_autotune(int32_t n, int32_t d, int32_t precision, int32_t j_dtype, int32_t replicas, int32_t steps,
+                       void *workspace, size_t ws_bytes, chym_plan_entry *best, chym_plan_entry *cand,
+                       int32_t max_cand, int32_t *n_cand, chym_stream_t stream) {
+    int rc = validate_shape(n, d, precision, j_dtype);
+    if (rc) return rc;
+    if (replicas < 1 || steps < 1) return fail(CHYM_EINVAL, "replicas and steps must be >= 1");
+    if (!workspace || !best) return fail(CHYM_EINVAL, "workspace and best must not be NULL");
+    if ((uintptr_t)workspace % kAlign) return fail(CHYM_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+    const ProbeLayout L = probe_layout(n, d, replicas, steps);
+    if (ws_bytes < L.total) return fail(CHYM_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+    rc = check_device();
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = static_cast<char *>(workspace);
+    hipError_t e = chym::launch_fill_probe(ws + L.off_j, j_dtype, n, reinterpret_cast<float *>(ws + L.off_pump),
+                                           replicas, reinterpret_cast<float *>(ws + L.off_alpha), steps * d, st);
+    if (e != hipSuccess) return hip_fail(e, "probe fill");
+    chym_task task;
+    memset(&task, 0, sizeof task);
+    task.prob.n = n;
+    task.prob.d = d;
+    task.prob.j_dtype = j_dtype;
+    task.prob.j = ws + L.off_j;
+    task.prob.eps = 0.05f;
+    task.prob.btil = 1.0f;
+    task.prob.eta = 2e-4f;
+    task.run.r = replicas;
+    task.run.steps = steps;
+    task.run.precision = precision;
+    task.run.dt = 0.01f;
+    task.run.pump = reinterpret_cast<const float *>(ws + L.off_pump);
+    task.run.x = reinterpret_cast<float *>(ws + L.off_x);
+    task.run.alpha = reinterpret_cast<const float *>(ws + L.off_alpha);
+    const VariantKey key = key_of(variant_of_shape(n, precision, j_dtype), d);
+    PlanValue saved;
+    bool had;
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        auto it = g_plan.find(key);
+        had = it != g_plan.end();
+        if (had) saved = it->second;
+    }
+    const PlanValue cands[] = {{chym::kKernelRegJ, 4, 0.f}, {chym::kKernelLdsJ, 2, 0.f}, {chym::kKernelLdsJ, 4, 0.f}};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    int best_i = -1;
+    float best_ms = 0.0f;
+    int count = 0;
+    rc = CHYM_OK;
+    for (int ci = 0; ci < 3 && rc == CHYM_OK; ++ci) {
+        {
+            std::lock_guard<std::mutex> lk(g_plan_mu);
+            g_plan[key] = cands[ci];
+        }
+        chym_batch *plan = nullptr;
+        rc = chym_batch_create(&task, 1, ws + L.off_batch, L.batch_bytes, &plan);
+        if (rc) break;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && rc == CHYM_OK; ++rep) {  // warm-up, then timed
+            e = chym::launch_fill_state(task.run.x, (size_t)n * replicas * d, st);
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            if (e == hipSuccess) rc = chym_batch_launch_nograph(plan, st);
+            if (e == hipSuccess && rc == CHYM_OK) e = hipEventRecord(e1, st);
+            if (e == hipSuccess && rc == CHYM_OK) e = hipEventSynchronize(e1);
+            if (e == hipSuccess && rc == CHYM_OK) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) rc = hip_fail(e, "autotune timing");
+        }
+        chym_batch_destroy(plan);
+        if (rc) break;
+        if (cand && count < max_cand) {
+            chym_plan_entry &c = cand[count];
+            c.n = n;
+            c.d = d;
+            c.precision = precision;
+            c.j_dtype = j_dtype;
+            c.kernel = cands[ci].kind == chym::kKernelLdsJ ? CHYM_KERNEL_LDSJ : CHYM_KERNEL_REGJ;
+            c.waves = cands[ci].waves;
+            c.ms = ms;
+            c.reserved = 0.0f;
+        }
+        ++count;
+        if (best_i < 0 || ms < best_ms) {
+            best_i = ci;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        if (rc != CHYM_OK || best_i < 0) {
+            if (had) g_plan[key] = saved;
+            else g_plan.erase(key);
+        } else {
+            PlanValue pv = cands[best_i];
+            pv.ms = best_ms;
+            g_plan[key] = pv;
+        }
+    }
+    if (n_cand) *n_cand = std::min(count, max_cand);
+    if (rc) return rc;
+    return chym_plan_get(n, d, precision, j_dtype, best);
+}
+
+int chym_split3_bf16(const float *x, int64_t n, uint16_t *hi, uint16_t *mid, uint16_t *lo, chym_stream_t stream) {
+    if (n < 0 || n % 8) return fail(CHYM_EINVAL, "n = %lld must be a non-negative multiple of 8", (long long)n);
+    if (!x || !hi || !mid || !lo) return fail(CHYM_EINVAL, "pointers must not be NULL");
+    if ((uintptr_t)hi % 16 || (uintptr_t)mid % 16 || (uintptr_t)lo % 16)
+        return fail(CHYM_EINVAL, "hi, mid and lo must be 16-byte aligned");
+    if (n == 0) return CHYM_OK;
+    int rc = check_device();
+    if (rc) return rc;
+    hipError_t e = chym::launch_split3(x, n, hi, mid, lo, (hipStream_t)stream);
+    return e == hipSuccess ? CHYM_OK : hip_fail(e, "split launch");
+}
+
+int chym_plan_save(const char *path) {
+    if (!path) return fail(CHYM_EINVAL, "path is NULL");
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(CHYM_EINVAL, "cannot open %s for writing", path);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    fprintf(f, "# libchym plan table: tiles d xs js kernel waves ms\n");
+    for (const auto &kv : g_plan)
+        fprintf(f, "%d %d %d %d %d %d %.4f\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                std::get<3>(kv.first), kv.second.kind == chym::kKernelLdsJ ? CHYM_KERNEL_LDSJ : CHYM_KERNEL_REGJ,
+                kv.second.waves, kv.second.ms);
+    fclose(f);
+    return CHYM_OK;
+}
+
+int chym_plan_load(const char *path) {
+    if (!path) return fail(CHYM_EINVAL, "path is NULL");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(CHYM_EINVAL, "cannot open %s", path);
+    char line[256];
+    std::vector<std::pair<VariantKey, PlanValue>> got;
+    int lineno = 0;
+    while (fgets(line, sizeof line, f)) {
+        ++lineno;
+        if (line[0] == '#' || line[0] == '\n') continue;
+        int t, d, xs, js, kernel, waves;
+        float ms;
+        if (sscanf(line, "%d %d %d %d %d %d %f", &t, &d, &xs, &js, &kernel, &waves, &ms) != 7 || t < 1 || d < 1 ||
+            d > 4 || (xs != 1 && xs != 3) || (js != 1 && js != 3) ||
+            (kernel != CHYM_KERNEL_REGJ && kernel != CHYM_KERNEL_LDSJ) || waves < 1 || waves > 4) {
+            fclose(f);
+            return fail(CHYM_EINVAL, "%s:%d: malformed plan entry", path, lineno);
+        }
+        got.push_back({std::make_tuple(t, d, xs, js),
+                       PlanValue{kernel == CHYM_KERNEL_LDSJ ? chym::kKernelLdsJ : chym::kKernelRegJ, waves, ms}});
+    }
+    fclose(f);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (auto &kv : got) g_plan[kv.first] = kv.second;
+    return CHYM_OK;
 }
 
 }  // extern "C"

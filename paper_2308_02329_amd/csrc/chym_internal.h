@@ -30,10 +30,20 @@ struct IntegArgs {
 hipError_t launch_integrate(int tiles, int d, int xs, int js, int waves_per_block,
                             const IntegArgs &a, hipStream_t stream, bool *supported);
 bool integrate_variant_exists(int tiles, int d, int xs, int js);
-hipError_t persistent_occupancy(int tiles, int d, int xs, int js, int waves_per_block, int *blocks_per_cu);
+// Persistent kernel kinds: J gathered into each wavefront's registers, work
+// items of 16 replicas; or J staged in LDS per block, work items of
+// 16 * waves_per_block replicas.
+constexpr int kKernelRegJ = 0;
+constexpr int kKernelLdsJ = 1;
+hipError_t persistent_occupancy(int tiles, int d, int xs, int js, int kind, int waves_per_block, int *blocks_per_cu);
 hipError_t launch_zero_counters(int *counters, int n, hipStream_t stream);
-// Persistent launch over a work list: items[i] = (task index, 16-replica group).
-hipError_t launch_integrate_persistent(int tiles, int d, int xs, int js, int waves_per_block, int blocks,
+// Synthetic timing problem for the autotuner.
+hipError_t launch_fill_probe(void *j, int j_dtype, int n, float *pump, int r, float *alpha, int na,
+                             hipStream_t stream);
+hipError_t launch_fill_state(float *x, size_t nx, hipStream_t stream);
+hipError_t launch_split3(const float *x, int64_t n, uint16_t *hi, uint16_t *mid, uint16_t *lo, hipStream_t stream);
+// Persistent launch over a work list: items[i] = (task index, replica slab).
+hipError_t launch_integrate_persistent(int tiles, int d, int xs, int js, int kind, int waves_per_block, int blocks,
                                        const IntegArgs *tasks, const int2 *items, int n_items, int *counter,
                                        hipStream_t stream);
 

@@ -3,5 +3,5 @@
 #include "integrate_kernel.h"
 
 namespace chym {
-KernelPair lookup_resident_1_1_1(int tiles) { return lookup_tiles<1, 1, 1>(tiles); }
+KernelSet lookup_resident_1_1_1(int tiles) { return lookup_tiles<1, 1, 1>(tiles); }
 }  // namespace chym

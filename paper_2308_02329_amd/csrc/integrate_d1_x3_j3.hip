@@ -3,5 +3,5 @@
 #include "integrate_kernel.h"
 
 namespace chym {
-KernelPair lookup_resident_1_3_3(int tiles) { return lookup_tiles<1, 3, 3>(tiles); }
+KernelSet lookup_resident_1_3_3(int tiles) { return lookup_tiles<1, 3, 3>(tiles); }
 }  // namespace chym

@@ -3,5 +3,5 @@
 #include "integrate_kernel.h"
 
 namespace chym {
-KernelPair lookup_resident_2_1_1(int tiles) { return lookup_tiles<2, 1, 1>(tiles); }
+KernelSet lookup_resident_2_1_1(int tiles) { return lookup_tiles<2, 1, 1>(tiles); }
 }  // namespace chym

@@ -3,5 +3,5 @@
 #include "integrate_kernel.h"
 
 namespace chym {
-KernelPair lookup_resident_3_3_3(int tiles) { return lookup_tiles<3, 3, 3>(tiles); }
+KernelSet lookup_resident_3_3_3(int tiles) { return lookup_tiles<3, 3, 3>(tiles); }
 }  // namespace chym

@@ -13,29 +13,36 @@
 // operand and the state as the B operand.  The order in which the 32 values
 // of a K-chunk are summed is free, so chunk c is defined as the rows a lane
 // already holds in row tiles 2c and 2c+1: the B operand is built from the
-// lane's own registers with no LDS round trip and no shuffle, and J is
-// gathered once per work item into registers in the matching (permuted)
-// order as A fragments.
+// lane's own registers with no LDS round trip and no shuffle, and J is laid
+// out in the matching (permuted) order as A fragments, either gathered once
+// per work item into registers (one wavefront per work item) or staged once
+// per work item into LDS and shared by the wavefronts of a block (which
+// frees the registers for a second wavefront per SIMD, so that one wave's
+// matrix-core work overlaps the other's vector work).
 //
 // Float32 form: x is fed as the exact sum x = hi + mid + lo of three bf16
 // terms (each residual of a round-to-nearest bf16 has at most 16, then 8,
 // significant bits), so every product J_pq x_q is formed exactly and summed
 // in float32.  An integer J is exact in bf16; a float J is split the same
 // way and the six leading cross terms are kept (error ~2^-24 relative).
-// BF16 form: one bf16 term each.
+// BF16 form: one bf16 term each.  The split works on pairs of values: one
+// packed conversion rounds two values, and each residual x - hi is formed by
+// a bf16 dot product against (-1, 0) or (0, -1) accumulated onto x, which is
+// exact because the residual is representable.
 //
 // The Euler update (pump gain, coupling with the annealing weight, nonlocal
 // loss, local saturation) is fused after the contraction and works on the
 // accumulator registers in place; the whole step loop runs inside the
-// kernel, with no LDS, no barrier and no global-memory traffic per step
-// except the D annealing weights alpha[k][mu] (scalar loads).  Wavefronts
-// never wait on each other, so work is handed out per 16-replica group.
+// kernel, with no barrier and no global-memory traffic per step except the
+// D annealing weights alpha[k][mu] (scalar loads).
 #pragma once
 
 #include "chym_internal.h"
 
 namespace chym {
 
+typedef __attribute__((ext_vector_type(2))) float f32x2;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 
 template <int XS>
 struct XSplit {
@@ -44,6 +51,59 @@ struct XSplit {
 
 __device__ __forceinline__ float bf_to_f(__bf16 h) { return (float)h; }
 
+__device__ __forceinline__ bf16x2 pack_rne(float a, float b) { return __builtin_convertvector((f32x2){a, b}, bf16x2); }
+
+// The packed bf16 constants (-1, 0) and (0, -1), forced into VGPRs.  Left to
+// the compiler, (-1, 0) is encoded as the inline constant -1.0, which the
+// dot instruction reads as the float32 bit pattern, i.e. as (0, -1): the
+// residual would subtract the wrong half.  An empty asm with a VGPR operand
+// hides the value so it always travels in a register.
+struct NegPair {
+    bf16x2 lo, hi;
+};
+__device__ __forceinline__ NegPair neg_pair() {
+    uint32_t lo = 0x0000BF80u, hi = 0xBF800000u;
+    asm("" : "+v"(lo));
+    asm("" : "+v"(hi));
+    return NegPair{__builtin_bit_cast(bf16x2, lo), __builtin_bit_cast(bf16x2, hi)};
+}
+
+// a - (float)h.x and b - (float)h.y, exact when representable.
+__device__ __forceinline__ float resid_lo(bf16x2 h, float a, const NegPair &k) {
+    return __builtin_amdgcn_fdot2_f32_bf16(h, k.lo, a, false);
+}
+__device__ __forceinline__ float resid_hi(bf16x2 h, float b, const NegPair &k) {
+    return __builtin_amdgcn_fdot2_f32_bf16(h, k.hi, b, false);
+}
+
+__device__ __forceinline__ bf16x8 join4(bf16x2 p0, bf16x2 p1, bf16x2 p2, bf16x2 p3) {
+    typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+    const bf16x4 lo = __builtin_shufflevector(p0, p1, 0, 1, 2, 3);
+    const bf16x4 hi = __builtin_shufflevector(p2, p3, 0, 1, 2, 3);
+    return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+// Splits 8 floats (4 pairs) into XS bf16 terms whose sum is exact.
+template <int XS>
+__device__ __forceinline__ void split8(const float (&v)[8], XSplit<XS> &out, const NegPair &k) {
+    bf16x2 t[XS][4];
+#pragma unroll
+    for (int pr = 0; pr < 4; ++pr) {
+        const float a = v[2 * pr], b = v[2 * pr + 1];
+        const bf16x2 h = pack_rne(a, b);
+        t[0][pr] = h;
+        if constexpr (XS == 3) {
+            const float ra = resid_lo(h, a, k), rb = resid_hi(h, b, k);
+            const bf16x2 m = pack_rne(ra, rb);
+            const float sa = resid_lo(m, ra, k), sb = resid_hi(m, rb, k);
+            t[1][pr] = m;
+            t[2][pr] = pack_rne(sa, sb);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < XS; ++k) out.t[k] = join4(t[k][0], t[k][1], t[k][2], t[k][3]);
+}
+
 // Loads one coupling value as float (0 outside the n x n matrix).
 __device__ __forceinline__ float j_at(const IntegArgs &a, int p, int q) {
     if (p >= a.n || q >= a.n) return 0.0f;
@@ -51,10 +111,48 @@ __device__ __forceinline__ float j_at(const IntegArgs &a, int p, int q) {
                                     : reinterpret_cast<const float *>(a.j)[(size_t)p * a.n + q];
 }
 
+// A fragment (I, c) for lane (i, g): slot s holds
+// J[16 I + i][32 c + 16 (s >> 2) + 4 g + (s & 3)], split into JS bf16 terms.
+template <int JS>
+__device__ __forceinline__ void j_fragment(const IntegArgs &a, int I, int c, int lane, bf16x8 (&f)[JS]) {
+    const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const float v = j_at(a, 16 * I + i, 32 * c + 16 * (s >> 2) + 4 * g + (s & 3));
+        if constexpr (JS == 1) {
+            f[0][s] = (__bf16)v;
+        } else {
+            const __bf16 h = (__bf16)v;
+            const float r1 = v - bf_to_f(h);
+            const __bf16 m = (__bf16)r1;
+            const float r2 = r1 - bf_to_f(m);
+            f[0][s] = h;
+            f[1][s] = m;
+            f[2][s] = (__bf16)r2;
+        }
+    }
+}
+
+// Stages all A fragments of J into LDS, layout [JS][NT][NC][64 lanes].
+template <int NT, int JS>
+__device__ __forceinline__ void stage_j(const IntegArgs &a, bf16x8 *jl) {
+    constexpr int NC = (NT + 1) / 2;
+    for (int idx = threadIdx.x; idx < NT * NC * 64; idx += blockDim.x) {
+        const int lane = idx & 63;
+        const int c = (idx >> 6) % NC;
+        const int I = (idx >> 6) / NC;
+        bf16x8 f[JS];
+        j_fragment<JS>(a, I, c, lane, f);
+#pragma unroll
+        for (int t = 0; t < JS; ++t) jl[t * NT * NC * 64 + idx] = f[t];
+    }
+}
+
 // Integrates the 16 replicas rep0 .. rep0+15 of problem a for a.steps steps.
-// Called by one whole wavefront; uses no LDS and no barrier.
-template <int NT, int D, int XS, int JS>
-__device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0) {
+// Called by one whole wavefront.  JLDS: J fragments are read from the
+// block's LDS copy every step; otherwise they are gathered into registers.
+template <int NT, int D, int XS, int JS, bool JLDS>
+__device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0, const bf16x8 *jl) {
     constexpr int NC = (NT + 1) / 2;
     const int n = a.n;
     const int r = a.r;
@@ -64,28 +162,18 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0) {
     const int rep = rep0 + jcol;
     const bool valid = rep < r;
 
-    // ---- J as MFMA A fragments, held in registers for the whole run ----
-    // fragment (I, c), lane (i, g), slot s: J[16 I + i][32 c + 16 (s >> 2) + 4 g + (s & 3)]
-    bf16x8 jf[JS][NT][NC];
+    bf16x8 jr[JLDS ? 1 : JS][JLDS ? 1 : NT][JLDS ? 1 : NC];
+    if constexpr (!JLDS) {
 #pragma unroll
-    for (int I = 0; I < NT; ++I)
+        for (int I = 0; I < NT; ++I)
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
+            for (int c = 0; c < NC; ++c) {
+                bf16x8 f[JS];
+                j_fragment<JS>(a, I, c, lane, f);
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const float v = j_at(a, 16 * I + jcol, 32 * c + 16 * (s >> 2) + 4 * g + (s & 3));
-                if constexpr (JS == 1) {
-                    jf[0][I][c][s] = (__bf16)v;
-                } else {
-                    const __bf16 h = (__bf16)v;
-                    const float r1 = v - bf_to_f(h);
-                    const __bf16 m = (__bf16)r1;
-                    const float r2 = r1 - bf_to_f(m);
-                    jf[0][I][c][s] = h;
-                    jf[1][I][c][s] = m;
-                    jf[2][I][c][s] = (__bf16)r2;
-                }
+                for (int t = 0; t < JS; ++t) jr[t][I][c] = f[t];
             }
+    }
 
     // ---- load the state (zero for padded rows and replicas) ----
     float x[NT][D][4];
@@ -100,11 +188,17 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0) {
         }
 
     const float base = valid ? fmaf(a.dt, a.pump[rep] - 1.0f, 1.0f) : 0.0f;  // 1 + dt (r_i - 1)
+    const NegPair negk = neg_pair();
     const float nbd = -(a.dt * a.btil);
     const float ned = -(a.dt * a.eta);
     const float dte = a.dt * a.eps;
 
     for (int k = 0; k < a.steps; ++k) {
+        if constexpr (JLDS) {
+            // keep the J fragments in LDS: reload them every step instead of
+            // letting them be hoisted into registers
+            asm volatile("" ::: "memory");
+        }
         const float *al = a.alpha + (size_t)(a.start_step + k) * D;
         float ga[D];
 #pragma unroll
@@ -121,25 +215,25 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0) {
             // B operands of chunk c straight from the lane's own registers
             XSplit<XS> bx[D];
 #pragma unroll
-            for (int mu = 0; mu < D; ++mu)
+            for (int mu = 0; mu < D; ++mu) {
+                float v8[8];
 #pragma unroll
                 for (int s = 0; s < 8; ++s) {
                     const int tile = 2 * c + (s >> 2);
-                    const float v = (tile < NT) ? x[tile < NT ? tile : 0][mu][s & 3] : 0.0f;
-                    if constexpr (XS == 1) {
-                        bx[mu].t[0][s] = (__bf16)v;
-                    } else {
-                        const __bf16 h = (__bf16)v;
-                        const float r1 = v - bf_to_f(h);
-                        const __bf16 m = (__bf16)r1;
-                        const float r2 = r1 - bf_to_f(m);
-                        bx[mu].t[0][s] = h;
-                        bx[mu].t[1][s] = m;
-                        bx[mu].t[2][s] = (__bf16)r2;
-                    }
+                    v8[s] = (tile < NT) ? x[tile < NT ? tile : 0][mu][s & 3] : 0.0f;
                 }
+                split8<XS>(v8, bx[mu], negk);
+            }
 #pragma unroll
-            for (int I = 0; I < NT; ++I)
+            for (int I = 0; I < NT; ++I) {
+                bf16x8 af[JS];
+#pragma unroll
+                for (int t = 0; t < JS; ++t) {
+                    if constexpr (JLDS)
+                        af[t] = jl[((t * NT + I) * NC + c) * 64 + lane];
+                    else
+                        af[t] = jr[JLDS ? 0 : t][JLDS ? 0 : I][JLDS ? 0 : c];
+                }
 #pragma unroll
                 for (int mu = 0; mu < D; ++mu) {
                     f32x4 cacc = acc[I][mu];
@@ -147,17 +241,23 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0) {
                         // smallest terms first
 #pragma unroll
                         for (int t = XS - 1; t >= 0; --t)
-                            cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(jf[0][I][c], bx[mu].t[t], cacc, 0, 0, 0);
+                            cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bx[mu].t[t], cacc, 0, 0, 0);
                     } else {
-                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(jf[2][I][c], bx[mu].t[0], cacc, 0, 0, 0);
-                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(jf[1][I][c], bx[mu].t[1], cacc, 0, 0, 0);
-                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(jf[0][I][c], bx[mu].t[2], cacc, 0, 0, 0);
-                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(jf[1][I][c], bx[mu].t[0], cacc, 0, 0, 0);
-                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(jf[0][I][c], bx[mu].t[1], cacc, 0, 0, 0);
-                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(jf[0][I][c], bx[mu].t[0], cacc, 0, 0, 0);
+                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2], bx[mu].t[0], cacc, 0, 0, 0);
+                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1], bx[mu].t[1], cacc, 0, 0, 0);
+                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bx[mu].t[2], cacc, 0, 0, 0);
+                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1], bx[mu].t[0], cacc, 0, 0, 0);
+                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bx[mu].t[1], cacc, 0, 0, 0);
+                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bx[mu].t[0], cacc, 0, 0, 0);
                     }
                     acc[I][mu] = cacc;
                 }
+            }
+            if constexpr (JLDS) {
+                // one chunk's operands live at a time (register budget of
+                // two wavefronts per SIMD)
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
 
         // ---- fused Euler update on the accumulator tiles ----
@@ -201,7 +301,7 @@ __global__ __launch_bounds__(256) void k_integrate_resident(IntegArgs a) {
     const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int rep0 = wave * 16;
     if (rep0 >= a.r) return;
-    integrate_group<NT, D, XS, JS>(a, rep0);
+    integrate_group<NT, D, XS, JS, false>(a, rep0, nullptr);
 }
 
 // Many problems of one variant: a persistent grid whose wavefronts pop work
@@ -221,14 +321,48 @@ __global__ __launch_bounds__(256) void k_integrate_persistent(const IntegArgs *_
         if (it >= n_items) break;
         const int2 w = items[it];
         const IntegArgs a = tasks[w.x];
-        integrate_group<NT, D, XS, JS>(a, w.y * 16);
+        integrate_group<NT, D, XS, JS, false>(a, w.y * 16, nullptr);
     }
 }
 
+// Same, with J shared through LDS: a block of W wavefronts pops work items
+// (problem, slab of 16 W replicas), stages the problem's J fragments once,
+// and each wavefront integrates its 16 replicas reading J from LDS, which
+// leaves room for two wavefronts per SIMD.
+template <int NT, int D, int XS, int JS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void k_integrate_persistent_lds(const IntegArgs *__restrict__ tasks, const int2 *__restrict__ items, int n_items,
+                                int *__restrict__ counter) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    bf16x8 *jl = reinterpret_cast<bf16x8 *>(smem);
+    __shared__ int s_item;
+    const int waves = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6;
+    for (;;) {
+        __syncthreads();  // the previous item's LDS reads are done
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        if (it >= n_items) break;
+        const int2 w = items[it];
+        const IntegArgs a = tasks[w.x];
+        stage_j<NT, JS>(a, jl);
+        __syncthreads();
+        const int rep0 = (w.y * waves + wave) * 16;
+        if (rep0 < a.r) integrate_group<NT, D, XS, JS, true>(a, rep0, jl);
+    }
+}
 
-struct KernelPair {
+template <int NT, int JS>
+constexpr size_t lds_j_bytes() {
+    return (size_t)JS * NT * ((NT + 1) / 2) * 64 * sizeof(bf16x8);
+}
+
+struct KernelSet {
     void (*single)(IntegArgs);
     void (*persistent)(const IntegArgs *, const int2 *, int, int *);
+    void (*persistent_lds)(const IntegArgs *, const int2 *, int, int *);
+    size_t lds_bytes;
 };
 
 // Largest row-tile count per (d, xs, js) that compiles without scratch
@@ -242,16 +376,17 @@ constexpr int resident_max_tiles(int d, int xs, int js) {
 }
 
 template <int NT, int D, int XS, int JS>
-KernelPair variant_or_null() {
+KernelSet variant_or_null() {
     if constexpr (NT <= resident_max_tiles(D, XS, JS))
-        return KernelPair{k_integrate_resident<NT, D, XS, JS>, k_integrate_persistent<NT, D, XS, JS>};
+        return KernelSet{k_integrate_resident<NT, D, XS, JS>, k_integrate_persistent<NT, D, XS, JS>,
+                         k_integrate_persistent_lds<NT, D, XS, JS>, lds_j_bytes<NT, JS>()};
     else
-        return KernelPair{nullptr, nullptr};
+        return KernelSet{nullptr, nullptr, nullptr, 0};
 }
 
 // One translation unit per (D, XS, JS) instantiates all tile counts.
 template <int D, int XS, int JS>
-KernelPair lookup_tiles(int tiles) {
+KernelSet lookup_tiles(int tiles) {
     switch (tiles) {
         case 1: return variant_or_null<1, D, XS, JS>();
         case 2: return variant_or_null<2, D, XS, JS>();
@@ -265,11 +400,11 @@ KernelPair lookup_tiles(int tiles) {
         case 10: return variant_or_null<10, D, XS, JS>();
         case 11: return variant_or_null<11, D, XS, JS>();
         case 12: return variant_or_null<12, D, XS, JS>();
-        default: return KernelPair{nullptr, nullptr};
+        default: return KernelSet{nullptr, nullptr, nullptr, 0};
     }
 }
 
-#define CHYM_DECLARE_LOOKUP(D, XS, JS) KernelPair lookup_resident_##D##_##XS##_##JS(int tiles);
+#define CHYM_DECLARE_LOOKUP(D, XS, JS) KernelSet lookup_resident_##D##_##XS##_##JS(int tiles);
 CHYM_DECLARE_LOOKUP(1, 3, 1) CHYM_DECLARE_LOOKUP(1, 1, 1) CHYM_DECLARE_LOOKUP(1, 3, 3)
 CHYM_DECLARE_LOOKUP(2, 3, 1) CHYM_DECLARE_LOOKUP(2, 1, 1) CHYM_DECLARE_LOOKUP(2, 3, 3)
 CHYM_DECLARE_LOOKUP(3, 3, 1) CHYM_DECLARE_LOOKUP(3, 1, 1) CHYM_DECLARE_LOOKUP(3, 3, 3)

@@ -119,3 +119,34 @@ def test_python_binding_has_no_fallback(tmp_path, monkeypatch):
     monkeypatch.setattr(L, "_lib", None)
     with pytest.raises(ImportError):
         L.load()
+
+
+def test_plan_table_validation_and_file_roundtrip(tmp_path):
+    lib = L.load()
+    e = L.ChymPlanEntry(n=100, d=3, precision=L.CHYM_PREC_F32, j_dtype=L.CHYM_J_I8, kernel=L.CHYM_KERNEL_LDSJ,
+                        waves=2, ms=0.0, reserved=0.0)
+    assert lib.chym_plan_set(ctypes.byref(e)) == L.CHYM_OK
+    got = L.ChymPlanEntry()
+    assert lib.chym_plan_get(112, 3, L.CHYM_PREC_F32, L.CHYM_J_I8, ctypes.byref(got)) == L.CHYM_OK  # same tiles
+    assert (got.kernel, got.waves) == (L.CHYM_KERNEL_LDSJ, 2)
+    path = str(tmp_path / "plan.txt").encode()
+    assert lib.chym_plan_save(path) == L.CHYM_OK
+    e.kernel = L.CHYM_KERNEL_AUTO
+    assert lib.chym_plan_set(ctypes.byref(e)) == L.CHYM_OK
+    assert lib.chym_plan_get(100, 3, L.CHYM_PREC_F32, L.CHYM_J_I8, ctypes.byref(got)) == L.CHYM_OK
+    assert got.kernel == L.CHYM_KERNEL_REGJ  # default
+    assert lib.chym_plan_load(path) == L.CHYM_OK
+    assert lib.chym_plan_get(100, 3, L.CHYM_PREC_F32, L.CHYM_J_I8, ctypes.byref(got)) == L.CHYM_OK
+    assert got.kernel == L.CHYM_KERNEL_LDSJ
+    e.kernel = L.CHYM_KERNEL_AUTO
+    lib.chym_plan_set(ctypes.byref(e))
+    bad = tmp_path / "bad.txt"
+    bad.write_text("7 3 3 1 9 2 0.0\n")
+    assert lib.chym_plan_load(str(bad).encode()) == L.CHYM_EINVAL
+    for kw in ({"kernel": 7}, {"waves": 0}, {"waves": 5}, {"d": 0}, {"n": 0}, {"n": 4000}):
+        e2 = L.ChymPlanEntry(n=100, d=3, precision=0, j_dtype=0, kernel=L.CHYM_KERNEL_REGJ, waves=2)
+        for k, v in kw.items():
+            setattr(e2, k, v)
+        assert lib.chym_plan_set(ctypes.byref(e2)) in (L.CHYM_EINVAL, L.CHYM_EUNSUPPORTED)
+    assert lib.chym_split3_bf16(None, 8, None, None, None, None) == L.CHYM_EINVAL
+    assert lib.chym_split3_bf16(0x1000, 7, 0x2000, 0x3000, 0x4000, None) == L.CHYM_EINVAL

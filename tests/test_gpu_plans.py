@@ -1,0 +1,85 @@
+"""GPU checks of the float32 form's exact split and of the launch plans."""
+import numpy as np
+import pytest
+
+from paper_2308_02329_amd import api
+
+torch = pytest.importorskip("torch")
+from gpu_helpers import Case, to_dev  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16_rne_bits(x32: np.ndarray) -> np.ndarray:
+    """Round-to-nearest-even float32 -> bf16 bit patterns (finite inputs)."""
+    b = x32.view(np.uint32).astype(np.uint64)
+    rounding = ((b >> 16) & 1) + 0x7FFF
+    return ((b + rounding) >> 16).astype(np.uint16)
+
+
+def bits_to_f64(h: np.ndarray) -> np.ndarray:
+    return (h.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def test_split3_is_exact_and_rne():
+    """hi + mid + lo == x exactly and hi = RNE(x) while the residual terms
+    stay normal floats (|x| >= 2^-100); below that the smallest terms may be
+    flushed to zero, bounded by 2^-8 |x|."""
+    g = np.random.default_rng(0)
+    mags = 10.0 ** g.uniform(-37, 30, 1 << 16)
+    x = (g.choice([-1.0, 1.0], mags.size) * mags).astype(np.float32)
+    x[:8] = [0.0, -0.0, 1.0, -1.0, 3.0e-3, 1.0 + 2 ** -23, -(1.0 + 2 ** -8), 65504.0]
+    # values sitting exactly on bf16 rounding ties, at O(1) and at small magnitude
+    k = np.arange(1, 1025, dtype=np.uint32)
+    ties = np.concatenate([((0x3F80 + k) << 16 | 0x8000), ((0x0C00 + k) << 16 | 0x8000)]).view(np.float32)
+    x = np.concatenate([x, ties, -ties]).astype(np.float32)
+    x = x[: x.size // 8 * 8]
+    hi, mid, lo = api.chym_split3_bf16(to_dev(x))
+    hi, mid, lo = (t.cpu().numpy().view(np.uint16) for t in (hi, mid, lo))
+    np.testing.assert_array_equal(hi, bf16_rne_bits(x))
+    total = bits_to_f64(hi) + bits_to_f64(mid) + bits_to_f64(lo)
+    x64 = x.astype(np.float64)
+    big = np.abs(x64) >= 2.0 ** -100
+    assert big.sum() > 60000
+    assert np.array_equal(total[big], x64[big])
+    assert np.all(np.abs(total[~big] - x64[~big]) <= 2.0 ** -8 * np.abs(x64[~big]) + 2.0 ** -126)
+
+
+@pytest.mark.parametrize("n,d,prec", [(100, 2, "f32"), (100, 3, "bf16"), (40, 4, "f32"), (150, 1, "f32")])
+@pytest.mark.parametrize("waves", [2, 4])
+def test_lds_plan_matches_register_plan_bit_exact(n, d, prec, waves):
+    specs = [(n, d, 70, 150), (n, d, 33, 120), (n, d, 16, 150)]
+    cases = [Case(nn, dd, r, s, key=(30, i)) for i, (nn, dd, r, s) in enumerate(specs)]
+
+    def run():
+        tasks = []
+        for c, (_, _, r, s) in zip(cases, specs):
+            Jd, pump, x, alpha = c.gpu_inputs()
+            tasks.append(dict(J=Jd, pump=pump, x=x, alpha=alpha, steps=s, precision=prec, **c.params()))
+        b = api.chym_batch_create(tasks)
+        b.launch()
+        torch.cuda.synchronize()
+        b.destroy()
+        return [t["x"].cpu().numpy() for t in tasks]
+
+    api.chym_plan_set(n, d, prec, torch.int8, api.CHYM_KERNEL_REGJ, 4)
+    ref = run()
+    api.chym_plan_set(n, d, prec, torch.int8, api.CHYM_KERNEL_LDSJ, waves)
+    assert api.chym_plan_get(n, d, prec, torch.int8)["kernel"] == api.CHYM_KERNEL_LDSJ
+    got = run()
+    api.chym_plan_set(n, d, prec, torch.int8, api.CHYM_KERNEL_AUTO, 4)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+
+
+def test_autotune_installs_a_candidate(tmp_path):
+    best, cands = api.chym_plan_autotune(48, 2, "f32", torch.int8, replicas=4096, steps=50)
+    assert len(cands) == 3 and all(c["ms"] > 0 for c in cands)
+    assert best["ms"] == min(c["ms"] for c in cands)
+    assert api.chym_plan_get(48, 2, "f32", torch.int8)["kernel"] == best["kernel"]
+    path = tmp_path / "plans.txt"
+    api.chym_plan_save(path)
+    api.chym_plan_set(48, 2, "f32", torch.int8, api.CHYM_KERNEL_AUTO)
+    api.chym_plan_load(path)
+    assert api.chym_plan_get(48, 2, "f32", torch.int8)["kernel"] == best["kernel"]
+    api.chym_plan_set(48, 2, "f32", torch.int8, api.CHYM_KERNEL_AUTO)
