@@ -212,20 +212,23 @@ int chym_batch_destroy(chym_batch *plan);
  *                     SIMD when the state is large);
  *   CHYM_KERNEL_LDSJ  a block of `waves` wavefronts stages J once in LDS and
  *                     takes work items of 16 * waves replicas, leaving
- *                     registers for two wavefronts per SIMD.
+ *                     registers for two wavefronts per SIMD;
+ *   CHYM_KERNEL_LDSJ1 the same with one wavefront per SIMD (the whole
+ *                     register file for each wave).
  * The table is process-wide and starts empty (CHYM_KERNEL_REGJ, 4 waves per
  * block, for every variant).  Plans change speed only, never results.
  */
 #define CHYM_KERNEL_AUTO 0
 #define CHYM_KERNEL_REGJ 1
 #define CHYM_KERNEL_LDSJ 2
+#define CHYM_KERNEL_LDSJ1 3
 
 typedef struct chym_plan_entry {
     int32_t n;         /* problem size the entry applies to (any n with the same 16-row tile count) */
     int32_t d;
     int32_t precision; /* CHYM_PREC_* */
     int32_t j_dtype;   /* CHYM_J_* */
-    int32_t kernel;    /* CHYM_KERNEL_REGJ or CHYM_KERNEL_LDSJ (CHYM_KERNEL_AUTO: remove the entry) */
+    int32_t kernel;    /* CHYM_KERNEL_REGJ, _LDSJ or _LDSJ1 (CHYM_KERNEL_AUTO: remove the entry) */
     int32_t waves;     /* wavefronts per block, 1..4 */
     float ms;          /* autotune: measured time of the probe run of this entry (informational) */
     float reserved;    /* must be 0 */

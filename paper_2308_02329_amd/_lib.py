@@ -33,6 +33,7 @@ EXPORTS = (
 CHYM_KERNEL_AUTO = 0
 CHYM_KERNEL_REGJ = 1
 CHYM_KERNEL_LDSJ = 2
+CHYM_KERNEL_LDSJ1 = 3
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32

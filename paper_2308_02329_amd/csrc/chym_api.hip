@@ -167,7 +167,7 @@ int validate_hs(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dtype,
 typedef std::tuple<int, int, int, int> VariantKey;  // (tiles, d, xs, js)
 
 struct PlanValue {
-    int kind;   // chym::kKernelRegJ / kKernelLdsJ
+    int kind;   // chym::kKernelRegJ / kKernelLdsJ / kKernelLdsJ1
     int waves;  // wavefronts per block
     float ms;
 };
@@ -185,6 +185,13 @@ PlanValue plan_for(const VariantKey &k) {
     auto it = g_plan.find(k);
     if (it != g_plan.end()) return it->second;
     return PlanValue{chym::kKernelRegJ, kDefaultWaves, 0.0f};
+}
+
+int kind_of_code(int code) {
+    return code == CHYM_KERNEL_LDSJ ? chym::kKernelLdsJ : code == CHYM_KERNEL_LDSJ1 ? chym::kKernelLdsJ1 : chym::kKernelRegJ;
+}
+int code_of_kind(int kind) {
+    return kind == chym::kKernelLdsJ ? CHYM_KERNEL_LDSJ : kind == chym::kKernelLdsJ1 ? CHYM_KERNEL_LDSJ1 : CHYM_KERNEL_REGJ;
 }
 
 Variant variant_of_shape(int n, int precision, int j_dtype) {
@@ -261,7 +268,7 @@ int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
         auto &lst = by_variant[key];
         if (tk.run.steps == 0) continue;
         const PlanValue pv = plan_for(key);
-        const int slab = pv.kind == chym::kKernelLdsJ ? 16 * pv.waves : 16;
+        const int slab = pv.kind != chym::kKernelRegJ ? 16 * pv.waves : 16;
         const int slabs = (tk.run.r + slab - 1) / slab;
         for (int g = 0; g < slabs; ++g) lst.push_back(make_int2(t, g));
     }
@@ -281,7 +288,7 @@ int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
         g.v.js = std::get<3>(kv.first);
         const PlanValue pv = plan_for(kv.first);
         g.kind = pv.kind;
-        g.waves = pv.kind == chym::kKernelLdsJ ? pv.waves : kPersistentWaves;
+        g.waves = pv.kind != chym::kKernelRegJ ? pv.waves : kPersistentWaves;
         g.item_off = (int)L->items.size();
         g.n_items = (int)lst.size();
         g.blocks = 0;
@@ -519,7 +526,7 @@ int chym_batch_create(const chym_task *tasks, int32_t n_tasks, void *workspace, 
     for (Group &g : b->layout.groups) {
         int per_cu = 0;
         if (e == hipSuccess) e = chym::persistent_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, g.kind, g.waves, &per_cu);
-        const int need = g.kind == chym::kKernelLdsJ ? g.n_items : (g.n_items + g.waves - 1) / g.waves;
+        const int need = g.kind != chym::kKernelRegJ ? g.n_items : (g.n_items + g.waves - 1) / g.waves;
         g.blocks = std::max(1, std::min(need, std::max(1, per_cu) * cus));
     }
     // task table and work list
@@ -626,10 +633,10 @@ int chym_plan_set(const chym_plan_entry *e) {
         g_plan.erase(k);
         return CHYM_OK;
     }
-    if (e->kernel != CHYM_KERNEL_REGJ && e->kernel != CHYM_KERNEL_LDSJ)
+    if (e->kernel != CHYM_KERNEL_REGJ && e->kernel != CHYM_KERNEL_LDSJ && e->kernel != CHYM_KERNEL_LDSJ1)
         return fail(CHYM_EINVAL, "kernel = %d is not a CHYM_KERNEL_* value", e->kernel);
     if (e->waves < 1 || e->waves > 4) return fail(CHYM_EINVAL, "waves = %d must be in 1..4", e->waves);
-    g_plan[k] = PlanValue{e->kernel == CHYM_KERNEL_LDSJ ? chym::kKernelLdsJ : chym::kKernelRegJ, e->waves, e->ms};
+    g_plan[k] = PlanValue{kind_of_code(e->kernel), e->waves, e->ms};
     return CHYM_OK;
 }
 
@@ -642,7 +649,7 @@ int chym_plan_get(int32_t n, int32_t d, int32_t precision, int32_t j_dtype, chym
     e->d = d;
     e->precision = precision;
     e->j_dtype = j_dtype;
-    e->kernel = pv.kind == chym::kKernelLdsJ ? CHYM_KERNEL_LDSJ : CHYM_KERNEL_REGJ;
+    e->kernel = code_of_kind(pv.kind);
     e->waves = pv.waves;
     e->ms = pv.ms;
     e->reserved = 0.0f;
@@ -718,7 +725,11 @@ int chym_plan_autotune(int32_t n, int32_t d, int32_t precision, int32_t j_dtype,
         had = it != g_plan.end();
         if (had) saved = it->second;
     }
-    const PlanValue cands[] = {{chym::kKernelRegJ, 4, 0.f}, {chym::kKernelLdsJ, 2, 0.f}, {chym::kKernelLdsJ, 4, 0.f}};
+    const PlanValue cands[] = {{chym::kKernelRegJ, 4, 0.f},
+                               {chym::kKernelLdsJ, 2, 0.f},
+                               {chym::kKernelLdsJ, 4, 0.f},
+                               {chym::kKernelLdsJ1, 4, 0.f}};
+    constexpr int kCands = sizeof(cands) / sizeof(cands[0]);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -727,7 +738,7 @@ int chym_plan_autotune(int32_t n, int32_t d, int32_t precision, int32_t j_dtype,
     float best_ms = 0.0f;
     int count = 0;
     rc = CHYM_OK;
-    for (int ci = 0; ci < 3 && rc == CHYM_OK; ++ci) {
+    for (int ci = 0; ci < kCands && rc == CHYM_OK; ++ci) {
         {
             std::lock_guard<std::mutex> lk(g_plan_mu);
             g_plan[key] = cands[ci];
@@ -753,7 +764,7 @@ int chym_plan_autotune(int32_t n, int32_t d, int32_t precision, int32_t j_dtype,
             c.d = d;
             c.precision = precision;
             c.j_dtype = j_dtype;
-            c.kernel = cands[ci].kind == chym::kKernelLdsJ ? CHYM_KERNEL_LDSJ : CHYM_KERNEL_REGJ;
+            c.kernel = code_of_kind(cands[ci].kind);
             c.waves = cands[ci].waves;
             c.ms = ms;
             c.reserved = 0.0f;
@@ -802,7 +813,7 @@ int chym_plan_save(const char *path) {
     fprintf(f, "# libchym plan table: tiles d xs js kernel waves ms\n");
     for (const auto &kv : g_plan)
         fprintf(f, "%d %d %d %d %d %d %.4f\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                std::get<3>(kv.first), kv.second.kind == chym::kKernelLdsJ ? CHYM_KERNEL_LDSJ : CHYM_KERNEL_REGJ,
+                std::get<3>(kv.first), code_of_kind(kv.second.kind),
                 kv.second.waves, kv.second.ms);
     fclose(f);
     return CHYM_OK;
@@ -822,12 +833,12 @@ int chym_plan_load(const char *path) {
         float ms;
         if (sscanf(line, "%d %d %d %d %d %d %f", &t, &d, &xs, &js, &kernel, &waves, &ms) != 7 || t < 1 || d < 1 ||
             d > 4 || (xs != 1 && xs != 3) || (js != 1 && js != 3) ||
-            (kernel != CHYM_KERNEL_REGJ && kernel != CHYM_KERNEL_LDSJ) || waves < 1 || waves > 4) {
+            (kernel != CHYM_KERNEL_REGJ && kernel != CHYM_KERNEL_LDSJ && kernel != CHYM_KERNEL_LDSJ1) || waves < 1 ||
+            waves > 4) {
             fclose(f);
             return fail(CHYM_EINVAL, "%s:%d: malformed plan entry", path, lineno);
         }
-        got.push_back({std::make_tuple(t, d, xs, js),
-                       PlanValue{kernel == CHYM_KERNEL_LDSJ ? chym::kKernelLdsJ : chym::kKernelRegJ, waves, ms}});
+        got.push_back({std::make_tuple(t, d, xs, js), PlanValue{kind_of_code(kernel), waves, ms}});
     }
     fclose(f);
     std::lock_guard<std::mutex> lk(g_plan_mu);

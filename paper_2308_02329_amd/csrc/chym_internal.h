@@ -34,7 +34,8 @@ bool integrate_variant_exists(int tiles, int d, int xs, int js);
 // items of 16 replicas; or J staged in LDS per block, work items of
 // 16 * waves_per_block replicas.
 constexpr int kKernelRegJ = 0;
-constexpr int kKernelLdsJ = 1;
+constexpr int kKernelLdsJ = 1;   // two wavefronts per SIMD
+constexpr int kKernelLdsJ1 = 2;  // one wavefront per SIMD
 hipError_t persistent_occupancy(int tiles, int d, int xs, int js, int kind, int waves_per_block, int *blocks_per_cu);
 hipError_t launch_zero_counters(int *counters, int n, hipStream_t stream);
 // Synthetic timing problem for the autotuner.

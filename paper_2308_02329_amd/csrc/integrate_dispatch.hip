@@ -13,7 +13,7 @@ static KernelFn lookup(int tiles, int d, int xs, int js) {
     CHYM_PICK(3, 3, 1) CHYM_PICK(3, 1, 1) CHYM_PICK(3, 3, 3)
     CHYM_PICK(4, 3, 1) CHYM_PICK(4, 1, 1) CHYM_PICK(4, 3, 3)
 #undef CHYM_PICK
-    return KernelSet{nullptr, nullptr, nullptr, 0};
+    return KernelSet{nullptr, nullptr, nullptr, nullptr, 0};
 }
 
 int resident_tile_limit(int d, int xs, int js) {
@@ -105,9 +105,13 @@ hipError_t launch_integrate(int tiles, int d, int xs, int js, int waves_per_bloc
 
 bool integrate_variant_exists(int tiles, int d, int xs, int js) { return lookup(tiles, d, xs, js).single != nullptr; }
 
-static hipError_t prepare_lds(const KernelFn &fn) {
+static void (*lds_kernel(const KernelFn &fn, int kind))(const IntegArgs *, const int2 *, int, int *) {
+    return kind == kKernelLdsJ1 ? fn.persistent_lds1 : fn.persistent_lds;
+}
+
+static hipError_t prepare_lds(const KernelFn &fn, int kind) {
     if (fn.lds_bytes <= 64 * 1024) return hipSuccess;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(fn.persistent_lds),
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(lds_kernel(fn, kind)),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)fn.lds_bytes);
 }
 
@@ -115,10 +119,10 @@ hipError_t persistent_occupancy(int tiles, int d, int xs, int js, int kind, int 
     KernelFn fn = lookup(tiles, d, xs, js);
     *blocks_per_cu = 0;
     if (!fn.persistent) return hipErrorInvalidDeviceFunction;
-    if (kind == kKernelLdsJ) {
-        hipError_t e = prepare_lds(fn);
+    if (kind == kKernelLdsJ || kind == kKernelLdsJ1) {
+        hipError_t e = prepare_lds(fn, kind);
         if (e != hipSuccess) return e;
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn.persistent_lds, 64 * waves_per_block,
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, lds_kernel(fn, kind), 64 * waves_per_block,
                                                             fn.lds_bytes);
     }
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn.persistent, 64 * waves_per_block, 0);
@@ -135,11 +139,11 @@ hipError_t launch_integrate_persistent(int tiles, int d, int xs, int js, int kin
                                        hipStream_t stream) {
     KernelFn fn = lookup(tiles, d, xs, js);
     if (!fn.persistent) return hipErrorInvalidDeviceFunction;
-    if (kind == kKernelLdsJ) {
-        hipError_t e = prepare_lds(fn);
+    if (kind == kKernelLdsJ || kind == kKernelLdsJ1) {
+        hipError_t e = prepare_lds(fn, kind);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(fn.persistent_lds, dim3(blocks), dim3(64 * waves_per_block), fn.lds_bytes, stream, tasks,
-                           items, n_items, counter);
+        hipLaunchKernelGGL(lds_kernel(fn, kind), dim3(blocks), dim3(64 * waves_per_block), fn.lds_bytes, stream,
+                           tasks, items, n_items, counter);
     } else {
         hipLaunchKernelGGL(fn.persistent, dim3(blocks), dim3(64 * waves_per_block), 0, stream, tasks, items, n_items,
                            counter);

@@ -194,92 +194,93 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0, co
     const float dte = a.dt * a.eps;
 
     for (int k = 0; k < a.steps; ++k) {
-        if constexpr (JLDS) {
-            // keep the J fragments in LDS: reload them every step instead of
-            // letting them be hoisted into registers
-            asm volatile("" ::: "memory");
-        }
-        const float *al = a.alpha + (size_t)(a.start_step + k) * D;
-        float ga[D];
-#pragma unroll
-        for (int mu = 0; mu < D; ++mu) ga[mu] = dte * al[mu];
-
-        f32x4 acc[NT][D];
-#pragma unroll
-        for (int I = 0; I < NT; ++I)
-#pragma unroll
-            for (int mu = 0; mu < D; ++mu) acc[I][mu] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            // B operands of chunk c straight from the lane's own registers
-            XSplit<XS> bx[D];
-#pragma unroll
-            for (int mu = 0; mu < D; ++mu) {
-                float v8[8];
-#pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    const int tile = 2 * c + (s >> 2);
-                    v8[s] = (tile < NT) ? x[tile < NT ? tile : 0][mu][s & 3] : 0.0f;
-                }
-                split8<XS>(v8, bx[mu], negk);
-            }
-#pragma unroll
-            for (int I = 0; I < NT; ++I) {
-                bf16x8 af[JS];
-#pragma unroll
-                for (int t = 0; t < JS; ++t) {
-                    if constexpr (JLDS)
-                        af[t] = jl[((t * NT + I) * NC + c) * 64 + lane];
-                    else
-                        af[t] = jr[JLDS ? 0 : t][JLDS ? 0 : I][JLDS ? 0 : c];
-                }
-#pragma unroll
-                for (int mu = 0; mu < D; ++mu) {
-                    f32x4 cacc = acc[I][mu];
-                    if constexpr (JS == 1) {
-                        // smallest terms first
-#pragma unroll
-                        for (int t = XS - 1; t >= 0; --t)
-                            cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bx[mu].t[t], cacc, 0, 0, 0);
-                    } else {
-                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2], bx[mu].t[0], cacc, 0, 0, 0);
-                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1], bx[mu].t[1], cacc, 0, 0, 0);
-                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bx[mu].t[2], cacc, 0, 0, 0);
-                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1], bx[mu].t[0], cacc, 0, 0, 0);
-                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bx[mu].t[1], cacc, 0, 0, 0);
-                        cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bx[mu].t[0], cacc, 0, 0, 0);
-                    }
-                    acc[I][mu] = cacc;
-                }
-            }
             if constexpr (JLDS) {
-                // one chunk's operands live at a time (register budget of
-                // two wavefronts per SIMD)
-                __builtin_amdgcn_sched_barrier(0);
+                // keep the J fragments in LDS: reload them every step instead of
+                // letting them be hoisted into registers
+                asm volatile("" ::: "memory");
             }
-        }
+            const float *al = a.alpha + (size_t)(a.start_step + k) * D;
+            float ga[D];
+#pragma unroll
+            for (int mu = 0; mu < D; ++mu) ga[mu] = dte * al[mu];
 
-        // ---- fused Euler update on the accumulator tiles ----
-        // x <- x (1 + dt (r-1) - dt btil S - dt eta x^2) + dt eps alpha_mu G
+            // The update is x <- y + dt eps alpha_mu G with the local part
+            // y = x (1 + dt (r-1) - dt btil S - dt eta x^2).  y is formed tile by
+            // tile just before the tile's state is split into matrix-core
+            // operands; the split then consumes x in place, and y becomes the new
+            // state with one multiply-add once G is complete.
+            float y[NT][D][4];
+            f32x4 acc[NT][D];
 #pragma unroll
-        for (int I = 0; I < NT; ++I)
+            for (int I = 0; I < NT; ++I)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                float x2[D];
+                for (int mu = 0; mu < D; ++mu) acc[I][mu] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
 #pragma unroll
-                for (int mu = 0; mu < D; ++mu) x2[mu] = x[I][mu][v] * x[I][mu][v];
-                float S = x2[0];
+            for (int c = 0; c < NC; ++c) {
 #pragma unroll
-                for (int mu = 1; mu < D; ++mu) S = S + x2[mu];
-                const float cc = fmaf(nbd, S, base);
+                for (int h = 0; h < 2; ++h) {
+                    const int I = 2 * c + h;
+                    if (I < NT) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            float x2[D];
+#pragma unroll
+                            for (int mu = 0; mu < D; ++mu) x2[mu] = x[I][mu][v] * x[I][mu][v];
+                            float S = x2[0];
+#pragma unroll
+                            for (int mu = 1; mu < D; ++mu) S = S + x2[mu];
+                            const float cc = fmaf(nbd, S, base);
+#pragma unroll
+                            for (int mu = 0; mu < D; ++mu) y[I][mu][v] = x[I][mu][v] * fmaf(ned, x2[mu], cc);
+                        }
+                    }
+                }
+                // B operands of chunk c straight from the lane's own registers
+                XSplit<XS> bx[D];
 #pragma unroll
                 for (int mu = 0; mu < D; ++mu) {
-                    const float t = fmaf(ned, x2[mu], cc);
-                    const float y = x[I][mu][v] * t;
-                    x[I][mu][v] = fmaf(ga[mu], acc[I][mu][v], y);
+                    float v8[8];
+#pragma unroll
+                    for (int s = 0; s < 8; ++s) {
+                        const int tile = 2 * c + (s >> 2);
+                        v8[s] = (tile < NT) ? x[tile < NT ? tile : 0][mu][s & 3] : 0.0f;
+                    }
+                    split8<XS>(v8, bx[mu], negk);
                 }
+                bf16x8 af[JS][NT];
+#pragma unroll
+                for (int I = 0; I < NT; ++I)
+#pragma unroll
+                    for (int t = 0; t < JS; ++t) {
+                        if constexpr (JLDS)
+                            af[t][I] = jl[((t * NT + I) * NC + c) * 64 + lane];
+                        else
+                            af[t][I] = jr[JLDS ? 0 : t][JLDS ? 0 : I][JLDS ? 0 : c];
+                    }
+                // term pairs (J term, state term), smallest first; consecutive
+                // instructions write different accumulators
+                constexpr int NP = JS == 1 ? XS : 6;
+                constexpr int pj[6] = {JS == 1 ? 0 : 2, JS == 1 ? 0 : 1, 0, JS == 1 ? 0 : 1, 0, 0};
+                constexpr int px[6] = {JS == 1 ? XS - 1 : 0, JS == 1 ? (XS > 1 ? XS - 2 : 0) : 1,
+                                       JS == 1 ? 0 : 2, 0, 1, 0};
+#pragma unroll
+                for (int q = 0; q < NP; ++q)
+#pragma unroll
+                    for (int I = 0; I < NT; ++I)
+#pragma unroll
+                        for (int mu = 0; mu < D; ++mu)
+                            acc[I][mu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[pj[q]][I], bx[mu].t[px[q]],
+                                                                                acc[I][mu], 0, 0, 0);
+    
             }
+
+#pragma unroll
+            for (int I = 0; I < NT; ++I)
+#pragma unroll
+                for (int mu = 0; mu < D; ++mu)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) x[I][mu][v] = fmaf(ga[mu], acc[I][mu][v], y[I][mu][v]);
     }
 
     // ---- store ----
@@ -327,10 +328,12 @@ __global__ __launch_bounds__(256) void k_integrate_persistent(const IntegArgs *_
 
 // Same, with J shared through LDS: a block of W wavefronts pops work items
 // (problem, slab of 16 W replicas), stages the problem's J fragments once,
-// and each wavefront integrates its 16 replicas reading J from LDS, which
-// leaves room for two wavefronts per SIMD.
-template <int NT, int D, int XS, int JS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+// and each wavefront integrates its 16 replicas reading J from LDS.  WPE
+// wavefronts per SIMD: 2 caps each at 256 registers so that one wave's
+// matrix-core work can overlap the other's vector work; 1 leaves the full
+// register file to a single wave.
+template <int NT, int D, int XS, int JS, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_integrate_persistent_lds(const IntegArgs *__restrict__ tasks, const int2 *__restrict__ items, int n_items,
                                 int *__restrict__ counter) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -361,7 +364,8 @@ constexpr size_t lds_j_bytes() {
 struct KernelSet {
     void (*single)(IntegArgs);
     void (*persistent)(const IntegArgs *, const int2 *, int, int *);
-    void (*persistent_lds)(const IntegArgs *, const int2 *, int, int *);
+    void (*persistent_lds)(const IntegArgs *, const int2 *, int, int *);   // two wavefronts per SIMD
+    void (*persistent_lds1)(const IntegArgs *, const int2 *, int, int *);  // one wavefront per SIMD
     size_t lds_bytes;
 };
 
@@ -379,9 +383,10 @@ template <int NT, int D, int XS, int JS>
 KernelSet variant_or_null() {
     if constexpr (NT <= resident_max_tiles(D, XS, JS))
         return KernelSet{k_integrate_resident<NT, D, XS, JS>, k_integrate_persistent<NT, D, XS, JS>,
-                         k_integrate_persistent_lds<NT, D, XS, JS>, lds_j_bytes<NT, JS>()};
+                         k_integrate_persistent_lds<NT, D, XS, JS, 2>, k_integrate_persistent_lds<NT, D, XS, JS, 1>,
+                         lds_j_bytes<NT, JS>()};
     else
-        return KernelSet{nullptr, nullptr, nullptr, 0};
+        return KernelSet{nullptr, nullptr, nullptr, nullptr, 0};
 }
 
 // One translation unit per (D, XS, JS) instantiates all tile counts.
@@ -400,7 +405,7 @@ KernelSet lookup_tiles(int tiles) {
         case 10: return variant_or_null<10, D, XS, JS>();
         case 11: return variant_or_null<11, D, XS, JS>();
         case 12: return variant_or_null<12, D, XS, JS>();
-        default: return KernelSet{nullptr, nullptr, nullptr, 0};
+        default: return KernelSet{nullptr, nullptr, nullptr, nullptr, 0};
     }
 }
 

@@ -46,8 +46,8 @@ def test_split3_is_exact_and_rne():
 
 
 @pytest.mark.parametrize("n,d,prec", [(100, 2, "f32"), (100, 3, "bf16"), (40, 4, "f32"), (150, 1, "f32")])
-@pytest.mark.parametrize("waves", [2, 4])
-def test_lds_plan_matches_register_plan_bit_exact(n, d, prec, waves):
+@pytest.mark.parametrize("kernel,waves", [(2, 2), (2, 4), (3, 4), (3, 1)])
+def test_lds_plan_matches_register_plan_bit_exact(n, d, prec, kernel, waves):
     specs = [(n, d, 70, 150), (n, d, 33, 120), (n, d, 16, 150)]
     cases = [Case(nn, dd, r, s, key=(30, i)) for i, (nn, dd, r, s) in enumerate(specs)]
 
@@ -64,8 +64,8 @@ def test_lds_plan_matches_register_plan_bit_exact(n, d, prec, waves):
 
     api.chym_plan_set(n, d, prec, torch.int8, api.CHYM_KERNEL_REGJ, 4)
     ref = run()
-    api.chym_plan_set(n, d, prec, torch.int8, api.CHYM_KERNEL_LDSJ, waves)
-    assert api.chym_plan_get(n, d, prec, torch.int8)["kernel"] == api.CHYM_KERNEL_LDSJ
+    api.chym_plan_set(n, d, prec, torch.int8, kernel, waves)
+    assert api.chym_plan_get(n, d, prec, torch.int8)["kernel"] == kernel
     got = run()
     api.chym_plan_set(n, d, prec, torch.int8, api.CHYM_KERNEL_AUTO, 4)
     for a, b in zip(ref, got):
@@ -74,7 +74,7 @@ def test_lds_plan_matches_register_plan_bit_exact(n, d, prec, waves):
 
 def test_autotune_installs_a_candidate(tmp_path):
     best, cands = api.chym_plan_autotune(48, 2, "f32", torch.int8, replicas=4096, steps=50)
-    assert len(cands) == 3 and all(c["ms"] > 0 for c in cands)
+    assert len(cands) == 4 and all(c["ms"] > 0 for c in cands)
     assert best["ms"] == min(c["ms"] for c in cands)
     assert api.chym_plan_get(48, 2, "f32", torch.int8)["kernel"] == best["kernel"]
     path = tmp_path / "plans.txt"
