@@ -128,10 +128,26 @@ const char *chym_last_error(void);
 /* Advance every replica by run->steps Euler steps of the equation above,
  * synchronous (Jacobi) update, using alpha rows start_step .. start_step +
  * steps - 1.  Splitting a run into calls with consecutive start_step gives
- * bit-identical results to one call.  Sizes: 1 <= n <= 256 (n <= 192 for
- * d = 4; n <= 128 for CHYM_J_F32 with CHYM_PREC_F32), 1 <= d <= 4, r >= 1.
- * Larger n returns CHYM_EUNSUPPORTED. */
+ * bit-identical results to one call.
+ *
+ * Two integrators, chosen by size, give identical results for the same
+ * problem: a register-resident one (no workspace) up to n = 192 (d = 1),
+ * 144/160 (d = 2, float32/bf16 form), 128 (d = 3), 112 (d = 4), or less
+ * for float J in the float32 form; and a streamed-J one for larger n, up to
+ * n = 1024, which needs a caller workspace (chym_integrate_ws) and requires
+ * the bf16 operand of 16 replicas, ceil(n/32) * d * terms KiB, to fit in
+ * 160 KiB of LDS (terms = 1 in the bf16 form, 3 in the float32 form).
+ * chym_integrate returns CHYM_EUNSUPPORTED where a workspace is needed. */
 int chym_integrate(const chym_problem *prob, const chym_run *run, chym_stream_t stream);
+
+/* Device workspace bytes chym_integrate_ws / chym_solve_ws need for this
+ * problem (0 when the register-resident integrator applies). */
+int chym_integrate_workspace_size(const chym_problem *prob, const chym_run *run, size_t *bytes);
+
+/* chym_integrate with a caller workspace (256-byte aligned) for the staged
+ * coupling matrix of the streamed-J integrator. */
+int chym_integrate_ws(const chym_problem *prob, const chym_run *run, void *workspace, size_t ws_bytes,
+                      chym_stream_t stream);
 
 /* Sign readout of x (paper: the Ising spins are read at the end of a run).
  * spins [r][ceil(n/64)], extra_frac [r], diverged [r]; each may be NULL. */
@@ -158,6 +174,10 @@ int chym_hs_energy(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dty
  * of *out from the final state. */
 int chym_solve(const chym_problem *prob, const chym_run *run, int32_t ss_step,
                double *e_hs_ss, const chym_out *out, chym_stream_t stream);
+
+/* chym_solve with a caller workspace (see chym_integrate_ws). */
+int chym_solve_ws(const chym_problem *prob, const chym_run *run, int32_t ss_step, double *e_hs_ss,
+                  const chym_out *out, void *workspace, size_t ws_bytes, chym_stream_t stream);
 
 /* ------------------------------------------------------------------------
  * Batched form: many problems (instances of different n, d, replica counts,

@@ -27,7 +27,7 @@ EXPORTS = (
     "chym_hs_energy", "chym_solve", "chym_batch_workspace_size", "chym_batch_create",
     "chym_batch_launch", "chym_batch_launch_nograph", "chym_batch_destroy", "chym_plan_set", "chym_plan_get",
     "chym_plan_autotune_workspace_size", "chym_plan_autotune", "chym_split3_bf16", "chym_plan_save",
-    "chym_plan_load",
+    "chym_plan_load", "chym_integrate_workspace_size", "chym_integrate_ws", "chym_solve_ws",
 )
 
 CHYM_KERNEL_AUTO = 0
@@ -87,6 +87,12 @@ def load():
     lib.chym_hs_energy.restype = ctypes.c_int
     lib.chym_solve.argtypes = [P(ChymProblem), P(ChymRun), _i32, _vp, P(ChymOut), _vp]
     lib.chym_solve.restype = ctypes.c_int
+    lib.chym_solve_ws.argtypes = [P(ChymProblem), P(ChymRun), _i32, _vp, P(ChymOut), _vp, ctypes.c_size_t, _vp]
+    lib.chym_solve_ws.restype = ctypes.c_int
+    lib.chym_integrate_workspace_size.argtypes = [P(ChymProblem), P(ChymRun), P(ctypes.c_size_t)]
+    lib.chym_integrate_workspace_size.restype = ctypes.c_int
+    lib.chym_integrate_ws.argtypes = [P(ChymProblem), P(ChymRun), _vp, ctypes.c_size_t, _vp]
+    lib.chym_integrate_ws.restype = ctypes.c_int
     _load_batch(lib)
     _load_plan(lib)
     _lib = lib

@@ -15,7 +15,7 @@ from . import _lib as L
 from ._lib import (CHYM_J_F32, CHYM_J_I8, CHYM_KERNEL_AUTO, CHYM_KERNEL_LDSJ, CHYM_KERNEL_LDSJ1, CHYM_KERNEL_REGJ,
                    CHYM_PREC_BF16, CHYM_PREC_F32, ChymError, ChymOut, ChymPlanEntry, ChymProblem, ChymRun)
 
-__all__ = ["chym_version", "chym_last_error", "chym_integrate", "chym_readout", "chym_ising_energy",
+__all__ = ["chym_integrate_workspace_size", "chym_version", "chym_last_error", "chym_integrate", "chym_readout", "chym_ising_energy",
            "chym_hs_energy", "chym_solve", "make_problem", "make_run", "spin_words", "ChymError",
            "CHYM_J_I8", "CHYM_J_F32", "CHYM_PREC_F32", "CHYM_PREC_BF16", "precision_code",
            "chym_batch_workspace_size", "chym_batch_create", "chym_batch_launch", "chym_batch_launch_nograph",
@@ -92,14 +92,45 @@ def chym_last_error() -> str:
     return m.decode() if m else ""
 
 
+def _workspace(prob, run, device, workspace):
+    """Device workspace for the streamed-J integrator (None if not needed)."""
+    nbytes = ctypes.c_size_t(0)
+    L.check(L.load().chym_integrate_workspace_size(ctypes.byref(prob), ctypes.byref(run), ctypes.byref(nbytes)),
+            "chym_integrate_workspace_size")
+    if nbytes.value == 0:
+        return None, 0
+    if workspace is None or workspace.numel() < nbytes.value + 256:
+        workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=device)
+    off = (-workspace.data_ptr()) % 256
+    return workspace[off:], int(nbytes.value)
+
+
+def chym_integrate_workspace_size(J, x, *, steps=1, precision=CHYM_PREC_F32) -> int:
+    n, r, d = x.shape
+    prob = make_problem(J, d, 0.0, 0.0, 0.0)
+    run = ChymRun(r=r, steps=int(steps), start_step=0, precision=precision_code(precision), dt=1.0, reserved_f=0.0,
+                  pump=ctypes.c_void_p(1), x=_vp(x), alpha=ctypes.c_void_p(1))
+    nbytes = ctypes.c_size_t(0)
+    L.check(L.load().chym_integrate_workspace_size(ctypes.byref(prob), ctypes.byref(run), ctypes.byref(nbytes)),
+            "chym_integrate_workspace_size")
+    return int(nbytes.value)
+
+
 def chym_integrate(J, pump, x, alpha, *, eps, btil, eta, dt, steps, start_step=0,
-                   precision=CHYM_PREC_F32, stream=None):
-    """Advance x [n, r, d] (float32, in place) by ``steps`` Euler steps."""
+                   precision=CHYM_PREC_F32, stream=None, workspace=None):
+    """Advance x [n, r, d] (float32, in place) by ``steps`` Euler steps.
+    Problems on the streamed-J integrator get a device workspace (the one
+    passed, if large enough, else a new tensor)."""
     lib = L.load()
     n, r, d = x.shape
     prob = make_problem(J, d, eps, btil, eta)
     run = make_run(n, d, pump, x, alpha, dt, steps, start_step, precision)
-    L.check(lib.chym_integrate(ctypes.byref(prob), ctypes.byref(run), _stream(stream)), "chym_integrate")
+    ws, nb = _workspace(prob, run, x.device, workspace)
+    if ws is None:
+        L.check(lib.chym_integrate(ctypes.byref(prob), ctypes.byref(run), _stream(stream)), "chym_integrate")
+    else:
+        L.check(lib.chym_integrate_ws(ctypes.byref(prob), ctypes.byref(run), _vp(ws), nb, _stream(stream)),
+                "chym_integrate_ws")
     return x
 
 
@@ -166,8 +197,9 @@ def chym_solve(J, pump, x, alpha, *, eps, btil, eta, dt, steps, ss_step=0, start
     out = ChymOut(spins=_vp(res.get("spins")), e_ising=_vp(res.get("e_ising")),
                   e_ising_f64=_vp(res.get("e_ising_f64")), e_hs=_vp(res.get("e_hs")),
                   extra_frac=_vp(res.get("extra_frac")), diverged=_vp(res.get("diverged")))
-    L.check(lib.chym_solve(ctypes.byref(prob), ctypes.byref(run), int(ss_step), _vp(res.get("e_hs_ss")),
-                           ctypes.byref(out), _stream(stream)), "chym_solve")
+    ws, nb = _workspace(prob, run, dev, None)
+    L.check(lib.chym_solve_ws(ctypes.byref(prob), ctypes.byref(run), int(ss_step), _vp(res.get("e_hs_ss")),
+                              ctypes.byref(out), _vp(ws), nb, _stream(stream)), "chym_solve_ws")
     return res
 
 

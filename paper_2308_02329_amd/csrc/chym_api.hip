@@ -80,17 +80,29 @@ int validate_run(const chym_run *r) {
     return CHYM_OK;
 }
 
+// Kernel variant of a problem: 16-row tiles, state terms, coupling terms,
+// and whether it runs on the register-resident kernel or, beyond its
+// register budget, on the streamed-J slab kernel (which needs a workspace
+// for the staged J).
 struct Variant {
     int tiles, xs, js;
+    bool slab;
 };
 
-Variant variant_of(const chym_problem *p, const chym_run *r) {
+Variant make_variant(int n, int d, int precision, int j_dtype) {
     Variant v;
-    v.tiles = (p->n + 15) / 16;
-    v.xs = r->precision == CHYM_PREC_F32 ? 3 : 1;
-    v.js = (r->precision == CHYM_PREC_F32 && p->j_dtype == CHYM_J_F32) ? 3 : 1;
+    v.tiles = (n + 15) / 16;
+    v.xs = precision == CHYM_PREC_F32 ? 3 : 1;
+    v.js = (precision == CHYM_PREC_F32 && j_dtype == CHYM_J_F32) ? 3 : 1;
+    v.slab = v.tiles > chym::resident_tile_limit(d, v.xs, v.js);
     return v;
 }
+
+Variant variant_of(const chym_problem *p, const chym_run *r) {
+    return make_variant(p->n, p->d, r->precision, p->j_dtype);
+}
+
+size_t slab_ws_bytes(const Variant &v) { return v.slab ? chym::slab_jfrag_bytes(v.tiles, v.js) : 0; }
 
 int default_waves_per_block() { return 4; }
 
@@ -115,20 +127,37 @@ chym::IntegArgs make_args(const chym_problem *prob, const chym_run *run) {
 
 int check_variant(const chym_problem *prob, const chym_run *run) {
     const Variant v = variant_of(prob, run);
-    if (v.tiles > chym::resident_tile_limit(prob->d, v.xs, v.js))
-        return fail(CHYM_EUNSUPPORTED, "n = %d with d = %d is beyond the resident integrator (<= %d rows)", prob->n,
-                    prob->d, 16 * chym::resident_tile_limit(prob->d, v.xs, v.js));
+    if (v.slab && !chym::slab_variant_exists(v.tiles, prob->d, v.xs, v.js))
+        return fail(CHYM_EUNSUPPORTED,
+                    "n = %d with d = %d in this precision is beyond the integrators (n <= 1024; the operand of "
+                    "16 replicas, %zu bytes, must fit in LDS)",
+                    prob->n, prob->d, chym::slab_lds_bytes(v.tiles, prob->d, v.xs));
     return CHYM_OK;
 }
 
-int integrate_impl(const chym_problem *prob, const chym_run *run, hipStream_t stream) {
+int integrate_impl(const chym_problem *prob, const chym_run *run, hipStream_t stream, void *ws = nullptr,
+                   size_t ws_bytes = 0) {
     int rc = check_variant(prob, run);
     if (rc) return rc;
+    const Variant v = variant_of(prob, run);
+    if (v.slab) {
+        if (!ws)
+            return fail(CHYM_EUNSUPPORTED, "n = %d with d = %d runs on the slab integrator, which needs a workspace "
+                                           "(chym_integrate_ws / chym_solve_ws)", prob->n, prob->d);
+        if (ws_bytes < slab_ws_bytes(v))
+            return fail(CHYM_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, slab_ws_bytes(v));
+        if ((uintptr_t)ws % 256) return fail(CHYM_EINVAL, "workspace must be 256-byte aligned");
+    }
     if (run->steps == 0) return CHYM_OK;
     rc = check_device();
     if (rc) return rc;
-    const Variant v = variant_of(prob, run);
     const chym::IntegArgs a = make_args(prob, run);
+    if (v.slab) {
+        hipError_t e = chym::launch_stage_jfrag(a, v.js, ws, stream);
+        if (e == hipSuccess) e = chym::launch_integrate_slab(v.tiles, prob->d, v.xs, v.js, a, ws, stream);
+        if (e != hipSuccess) return hip_fail(e, "slab integrate launch");
+        return CHYM_OK;
+    }
     bool supported = false;
     hipError_t e = chym::launch_integrate(v.tiles, prob->d, v.xs, v.js, default_waves_per_block(), a, stream,
                                           &supported);
@@ -199,6 +228,7 @@ Variant variant_of_shape(int n, int precision, int j_dtype) {
     v.tiles = (n + 15) / 16;
     v.xs = precision == CHYM_PREC_F32 ? 3 : 1;
     v.js = (precision == CHYM_PREC_F32 && j_dtype == CHYM_J_F32) ? 3 : 1;
+    v.slab = false;
     return v;
 }
 
@@ -210,7 +240,8 @@ int validate_shape(int32_t n, int32_t d, int32_t precision, int32_t j_dtype) {
     if (j_dtype != CHYM_J_I8 && j_dtype != CHYM_J_F32) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
     const Variant v = variant_of_shape(n, precision, j_dtype);
     if (v.tiles > chym::resident_tile_limit(d, v.xs, v.js))
-        return fail(CHYM_EUNSUPPORTED, "n = %d with d = %d is beyond the resident integrator", n, d);
+        return fail(CHYM_EUNSUPPORTED, "n = %d with d = %d has no launch plans (it runs on the slab integrator)", n,
+                    d);
     return CHYM_OK;
 }
 
@@ -221,15 +252,18 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Group {
     Variant v;
     int d;
-    int kind, waves;  // launch plan of this variant
+    int kind, waves;  // launch plan of this variant (resident kernels)
     int item_off, n_items;
     int blocks;
+    size_t lds;  // slab kernels: LDS operand area
 };
 
 struct BatchLayout {
     std::vector<Group> groups;
-    std::vector<int2> items;  // (task, replica slab), grouped and sorted
-    size_t off_tasks, off_items, off_counters, off_score, off_first, total;
+    std::vector<int2> items;      // (task, replica slab), grouped and sorted
+    std::vector<size_t> jf_off;   // slab tasks: offset of the staged J in the workspace (else 0)
+    std::vector<int> ncp;         // slab tasks: chunk count of the staging
+    size_t off_tasks, off_items, off_counters, off_score, off_first, off_jfp, off_ncp, off_jf, total;
     int64_t total_replicas;
     int max_nd;
     bool any_readout, any_ising, any_hs;
@@ -252,7 +286,7 @@ int validate_out(const chym_problem *prob, const chym_run *run, const chym_out *
 int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
     if (n_tasks < 1) return fail(CHYM_EINVAL, "n_tasks = %d must be >= 1", n_tasks);
     if (!tasks) return fail(CHYM_EINVAL, "tasks is NULL");
-    std::map<std::tuple<int, int, int, int>, std::vector<int2>> by_variant;
+    std::map<std::tuple<int, int, int, int, int>, std::vector<int2>> by_variant;  // (slab, tiles, d, xs, js)
     for (int t = 0; t < n_tasks; ++t) {
         const chym_task &tk = tasks[t];
         int rc = validate_problem(&tk.prob);
@@ -265,10 +299,13 @@ int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
         }
         const Variant v = variant_of(&tk.prob, &tk.run);
         const VariantKey key = key_of(v, tk.prob.d);
-        auto &lst = by_variant[key];
+        auto &lst = by_variant[std::make_tuple((int)v.slab, v.tiles, tk.prob.d, v.xs, v.js)];
         if (tk.run.steps == 0) continue;
-        const PlanValue pv = plan_for(key);
-        const int slab = pv.kind != chym::kKernelRegJ ? 16 * pv.waves : 16;
+        int slab = 16;
+        if (!v.slab) {
+            const PlanValue pv = plan_for(key);
+            slab = pv.kind != chym::kKernelRegJ ? 16 * pv.waves : 16;
+        }
         const int slabs = (tk.run.r + slab - 1) / slab;
         for (int g = 0; g < slabs; ++g) lst.push_back(make_int2(t, g));
     }
@@ -282,13 +319,21 @@ int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
             return tasks[a.x].run.steps > tasks[b.x].run.steps;
         });
         Group g;
-        g.v.tiles = std::get<0>(kv.first);
-        g.d = std::get<1>(kv.first);
-        g.v.xs = std::get<2>(kv.first);
-        g.v.js = std::get<3>(kv.first);
-        const PlanValue pv = plan_for(kv.first);
-        g.kind = pv.kind;
-        g.waves = pv.kind != chym::kKernelRegJ ? pv.waves : kPersistentWaves;
+        g.v.slab = std::get<0>(kv.first) != 0;
+        g.v.tiles = std::get<1>(kv.first);
+        g.d = std::get<2>(kv.first);
+        g.v.xs = std::get<3>(kv.first);
+        g.v.js = std::get<4>(kv.first);
+        g.lds = 0;
+        if (g.v.slab) {
+            g.kind = -1;
+            g.waves = 4;
+            g.lds = chym::slab_lds_bytes(g.v.tiles, g.d, g.v.xs);
+        } else {
+            const PlanValue pv = plan_for(key_of(g.v, g.d));
+            g.kind = pv.kind;
+            g.waves = pv.kind != chym::kKernelRegJ ? pv.waves : kPersistentWaves;
+        }
         g.item_off = (int)L->items.size();
         g.n_items = (int)lst.size();
         g.blocks = 0;
@@ -313,7 +358,20 @@ int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
     L->off_counters = L->off_items + align_up(sizeof(int2) * std::max<size_t>(1, L->items.size()));
     L->off_score = L->off_counters + align_up(sizeof(int) * std::max<size_t>(1, L->groups.size()));
     L->off_first = L->off_score + align_up(sizeof(chym::ScoreArgs) * (size_t)n_tasks);
-    L->total = L->off_first + align_up(sizeof(int64_t) * ((size_t)n_tasks + 1));
+    L->off_jfp = L->off_first + align_up(sizeof(int64_t) * ((size_t)n_tasks + 1));
+    L->off_ncp = L->off_jfp + align_up(sizeof(void *) * (size_t)n_tasks);
+    L->off_jf = L->off_ncp + align_up(sizeof(int) * (size_t)n_tasks);
+    L->jf_off.assign(n_tasks, 0);
+    L->ncp.assign(n_tasks, 0);
+    size_t off = L->off_jf;
+    for (int t = 0; t < n_tasks; ++t) {
+        const Variant v = variant_of(&tasks[t].prob, &tasks[t].run);
+        if (!v.slab || tasks[t].run.steps == 0) continue;
+        L->jf_off[t] = off;
+        L->ncp[t] = (v.tiles + 1) / 2;
+        off += align_up(slab_ws_bytes(v));
+    }
+    L->total = off;
     return CHYM_OK;
 }
 
@@ -345,6 +403,13 @@ int issue_batch(const chym_batch *b, hipStream_t main, const std::vector<hipStre
     int *counters = reinterpret_cast<int *>(b->ws + L.off_counters);
     hipError_t e = chym::launch_zero_counters(counters, (int)L.groups.size(), main);
     if (e != hipSuccess) return hip_fail(e, "zero counters");
+    for (size_t t = 0; t < b->tasks.size(); ++t) {
+        if (!L.jf_off[t]) continue;
+        const chym_task &tk = b->tasks[t];
+        const Variant v = variant_of(&tk.prob, &tk.run);
+        e = chym::launch_stage_jfrag(make_args(&tk.prob, &tk.run), v.js, b->ws + L.jf_off[t], main);
+        if (e != hipSuccess) return hip_fail(e, "stage J");
+    }
     const bool fork = branches && L.groups.size() > 1;
     if (fork) {
         e = hipEventRecord((*events)[0], main);
@@ -357,8 +422,14 @@ int issue_batch(const chym_batch *b, hipStream_t main, const std::vector<hipStre
             e = hipStreamWaitEvent(s, (*events)[0], 0);
             if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
         }
-        e = chym::launch_integrate_persistent(g.v.tiles, g.d, g.v.xs, g.v.js, g.kind, g.waves, g.blocks, tasks_d,
-                                              items_d + g.item_off, g.n_items, counters + gi, s);
+        if (g.v.slab)
+            e = chym::launch_integrate_slab_persistent(
+                g.v.tiles, g.d, g.v.xs, g.v.js, g.lds, g.blocks, tasks_d, items_d + g.item_off, g.n_items,
+                counters + gi, reinterpret_cast<const void *const *>(b->ws + L.off_jfp),
+                reinterpret_cast<const int *>(b->ws + L.off_ncp), s);
+        else
+            e = chym::launch_integrate_persistent(g.v.tiles, g.d, g.v.xs, g.v.js, g.kind, g.waves, g.blocks, tasks_d,
+                                                  items_d + g.item_off, g.n_items, counters + gi, s);
         if (e != hipSuccess) return hip_fail(e, "persistent integrate launch");
         if (fork) {
             e = hipEventRecord((*events)[gi + 1], s);
@@ -434,8 +505,8 @@ int chym_hs_energy(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dty
     return e == hipSuccess ? CHYM_OK : hip_fail(e, "hyperspin energy launch");
 }
 
-int chym_solve(const chym_problem *prob, const chym_run *run, int32_t ss_step, double *e_hs_ss,
-               const chym_out *out, chym_stream_t stream) {
+int chym_solve_ws(const chym_problem *prob, const chym_run *run, int32_t ss_step, double *e_hs_ss,
+                  const chym_out *out, void *workspace, size_t ws_bytes, chym_stream_t stream) {
     int rc = validate_problem(prob);
     if (rc) return rc;
     rc = validate_run(run);
@@ -455,25 +526,30 @@ int chym_solve(const chym_problem *prob, const chym_run *run, int32_t ss_step, d
         rc = validate_hs(prob->n, prob->d, run->r, prob->j, prob->j_dtype, run->x);
         if (rc) return rc;
     }
+    rc = check_variant(prob, run);
+    if (rc) return rc;
     const Variant v = variant_of(prob, run);
-    if (v.tiles > chym::resident_tile_limit(prob->d, v.xs, v.js))
-        return fail(CHYM_EUNSUPPORTED, "n = %d with d = %d is beyond the resident integrator", prob->n, prob->d);
+    if (v.slab && !workspace)
+        return fail(CHYM_EUNSUPPORTED, "n = %d with d = %d runs on the slab integrator, which needs a workspace "
+                                       "(chym_solve_ws)", prob->n, prob->d);
+    if (v.slab && ws_bytes < slab_ws_bytes(v))
+        return fail(CHYM_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, slab_ws_bytes(v));
     rc = check_device();
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     if (want_ss) {
         chym_run a = *run;
         a.steps = ss_step;
-        rc = integrate_impl(prob, &a, st);
+        rc = integrate_impl(prob, &a, st, workspace, ws_bytes);
         if (rc) return rc;
         hipError_t e = chym::launch_hs_energy(prob->n, prob->d, run->r, prob->j, prob->j_dtype, run->x, e_hs_ss, st);
         if (e != hipSuccess) return hip_fail(e, "hyperspin energy launch");
         a.start_step = run->start_step + ss_step;
         a.steps = run->steps - ss_step;
-        rc = integrate_impl(prob, &a, st);
+        rc = integrate_impl(prob, &a, st, workspace, ws_bytes);
         if (rc) return rc;
     } else {
-        rc = integrate_impl(prob, run, st);
+        rc = integrate_impl(prob, run, st, workspace, ws_bytes);
         if (rc) return rc;
     }
     hipError_t e;
@@ -490,6 +566,32 @@ int chym_solve(const chym_problem *prob, const chym_run *run, int32_t ss_step, d
         if (e != hipSuccess) return hip_fail(e, "hyperspin energy launch");
     }
     return CHYM_OK;
+}
+
+int chym_solve(const chym_problem *prob, const chym_run *run, int32_t ss_step, double *e_hs_ss,
+               const chym_out *out, chym_stream_t stream) {
+    return chym_solve_ws(prob, run, ss_step, e_hs_ss, out, nullptr, 0, stream);
+}
+
+int chym_integrate_workspace_size(const chym_problem *prob, const chym_run *run, size_t *bytes) {
+    if (!bytes) return fail(CHYM_EINVAL, "bytes is NULL");
+    int rc = validate_problem(prob);
+    if (rc) return rc;
+    rc = validate_run(run);
+    if (rc) return rc;
+    rc = check_variant(prob, run);
+    if (rc) return rc;
+    *bytes = slab_ws_bytes(variant_of(prob, run));
+    return CHYM_OK;
+}
+
+int chym_integrate_ws(const chym_problem *prob, const chym_run *run, void *workspace, size_t ws_bytes,
+                      chym_stream_t stream) {
+    int rc = validate_problem(prob);
+    if (rc) return rc;
+    rc = validate_run(run);
+    if (rc) return rc;
+    return integrate_impl(prob, run, (hipStream_t)stream, workspace, ws_bytes);
 }
 
 int chym_batch_workspace_size(const chym_task *tasks, int32_t n_tasks, size_t *bytes) {
@@ -525,8 +627,11 @@ int chym_batch_create(const chym_task *tasks, int32_t n_tasks, void *workspace, 
     b->cus = cus;
     for (Group &g : b->layout.groups) {
         int per_cu = 0;
-        if (e == hipSuccess) e = chym::persistent_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, g.kind, g.waves, &per_cu);
-        const int need = g.kind != chym::kKernelRegJ ? g.n_items : (g.n_items + g.waves - 1) / g.waves;
+        if (e == hipSuccess) {
+            if (g.v.slab) e = chym::slab_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, g.lds, &per_cu);
+            else e = chym::persistent_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, g.kind, g.waves, &per_cu);
+        }
+        const int need = (g.v.slab || g.kind != chym::kKernelRegJ) ? g.n_items : (g.n_items + g.waves - 1) / g.waves;
         g.blocks = std::max(1, std::min(need, std::max(1, per_cu) * cus));
     }
     // task table and work list
@@ -559,6 +664,13 @@ int chym_batch_create(const chym_task *tasks, int32_t n_tasks, void *workspace, 
         e = hipMemcpy(b->ws + L.off_score, sargs.data(), sizeof(chym::ScoreArgs) * n_tasks, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->ws + L.off_first, first.data(), sizeof(int64_t) * (n_tasks + 1), hipMemcpyHostToDevice);
+    std::vector<const void *> jfp(n_tasks, nullptr);
+    for (int t = 0; t < n_tasks; ++t)
+        if (L.jf_off[t]) jfp[t] = b->ws + L.jf_off[t];
+    if (e == hipSuccess)
+        e = hipMemcpy(b->ws + L.off_jfp, jfp.data(), sizeof(void *) * n_tasks, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->ws + L.off_ncp, L.ncp.data(), sizeof(int) * n_tasks, hipMemcpyHostToDevice);
     // record the launch sequence as a graph with one branch per variant group
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     const size_t ng = b->layout.groups.size();
@@ -669,8 +781,10 @@ ProbeLayout probe_layout(int n, int d, int r, int steps) {
     L.off_alpha = L.off_x + align_up((size_t)n * r * d * 4);
     L.off_batch = L.off_alpha + align_up((size_t)steps * d * 4);
     // batch workspace of one task: its work list is largest with 16-replica items
+    // (same terms, in the same order, as plan_layout for one resident task)
     L.batch_bytes = align_up(sizeof(chym::IntegArgs)) + align_up(sizeof(int2) * (size_t)((r + 15) / 16)) +
-                    align_up(sizeof(int)) + align_up(sizeof(chym::ScoreArgs)) + align_up(2 * sizeof(int64_t));
+                    align_up(sizeof(int)) + align_up(sizeof(chym::ScoreArgs)) + align_up(2 * sizeof(int64_t)) +
+                    align_up(sizeof(void *)) + align_up(sizeof(int));
     L.total = L.off_batch + L.batch_bytes;
     return L;
 }

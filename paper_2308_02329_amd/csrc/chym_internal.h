@@ -67,6 +67,21 @@ hipError_t launch_score_batched(const ScoreArgs *tasks, const int64_t *first, in
                                 int max_nd, bool any_readout, bool any_ising, bool any_hs, int cus,
                                 hipStream_t stream);
 
+// Streamed-J slab integrator (large n).  Tiles of 16 rows; kSlabMaxLds
+// bounds the LDS operand area of one column slab.
+constexpr size_t kSlabMaxLds = 159 * 1024;  // 160 KiB per CU, less room for static LDS
+int slab_tpw_for(int tiles);
+size_t slab_lds_bytes(int tiles, int d, int xs);
+size_t slab_jfrag_bytes(int tiles, int js);
+bool slab_variant_exists(int tiles, int d, int xs, int js);
+hipError_t launch_stage_jfrag(const IntegArgs &a, int js, void *out, hipStream_t stream);
+hipError_t launch_integrate_slab(int tiles, int d, int xs, int js, const IntegArgs &a, const void *jfrag,
+                                 hipStream_t stream);
+hipError_t slab_occupancy(int tiles, int d, int xs, int js, size_t lds, int *blocks_per_cu);
+hipError_t launch_integrate_slab_persistent(int tiles, int d, int xs, int js, size_t lds, int blocks,
+                                            const IntegArgs *tasks, const int2 *items, int n_items, int *counter,
+                                            const void *const *jfs, const int *ncps, hipStream_t stream);
+
 hipError_t launch_readout(int n, int d, int r, const float *x, uint64_t *spins, double *extra,
                           uint8_t *diverged, hipStream_t stream);
 hipError_t launch_ising_energy(int n, int r, const void *j, int j_dtype, const uint64_t *spins,

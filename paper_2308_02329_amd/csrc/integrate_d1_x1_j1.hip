@@ -1,7 +1,9 @@
-// Instantiates the register-resident integrator for d = 1, 1 state
-// term(s) and 1 coupling term(s), every supported tile count.
-#include "integrate_kernel.h"
+// Instantiates the integrators for d = 1, 1 state term(s) and 1 coupling
+// term(s): the register-resident kernels for every supported tile count and
+// the streamed-J slab kernels for every tiles-per-wavefront bucket.
+#include "integrate_slab.h"
 
 namespace chym {
 KernelSet lookup_resident_1_1_1(int tiles) { return lookup_tiles<1, 1, 1>(tiles); }
+SlabKernels lookup_slab_1_1_1(int tpw) { return slab_lookup_tpw<1, 1, 1>(tpw); }
 }  // namespace chym

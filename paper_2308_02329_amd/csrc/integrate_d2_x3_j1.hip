@@ -1,7 +1,9 @@
-// Instantiates the register-resident integrator for d = 2, 3 state
-// term(s) and 1 coupling term(s), every supported tile count.
-#include "integrate_kernel.h"
+// Instantiates the integrators for d = 2, 3 state term(s) and 1 coupling
+// term(s): the register-resident kernels for every supported tile count and
+// the streamed-J slab kernels for every tiles-per-wavefront bucket.
+#include "integrate_slab.h"
 
 namespace chym {
 KernelSet lookup_resident_2_3_1(int tiles) { return lookup_tiles<2, 3, 1>(tiles); }
+SlabKernels lookup_slab_2_3_1(int tpw) { return slab_lookup_tpw<2, 3, 1>(tpw); }
 }  // namespace chym

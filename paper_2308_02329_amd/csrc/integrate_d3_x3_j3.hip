@@ -1,7 +1,9 @@
-// Instantiates the register-resident integrator for d = 3, 3 state
-// term(s) and 3 coupling term(s), every supported tile count.
-#include "integrate_kernel.h"
+// Instantiates the integrators for d = 3, 3 state term(s) and 3 coupling
+// term(s): the register-resident kernels for every supported tile count and
+// the streamed-J slab kernels for every tiles-per-wavefront bucket.
+#include "integrate_slab.h"
 
 namespace chym {
 KernelSet lookup_resident_3_3_3(int tiles) { return lookup_tiles<3, 3, 3>(tiles); }
+SlabKernels lookup_slab_3_3_3(int tpw) { return slab_lookup_tpw<3, 3, 3>(tpw); }
 }  // namespace chym

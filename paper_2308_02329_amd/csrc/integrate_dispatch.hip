@@ -1,5 +1,5 @@
 // Host-side dispatch of the register-resident integrator variants.
-#include "integrate_kernel.h"
+#include "integrate_slab.h"
 
 namespace chym {
 
@@ -18,6 +18,88 @@ static KernelFn lookup(int tiles, int d, int xs, int js) {
 
 int resident_tile_limit(int d, int xs, int js) {
     return (d >= 1 && d <= 4) ? resident_max_tiles(d, xs, js) : 0;
+}
+
+// ------------------------------------------------------------ slab kernels
+static SlabKernels lookup_slab(int tpw, int d, int xs, int js) {
+#define CHYM_PICK(D, XS, JS) \
+    if (d == D && xs == XS && js == JS) return lookup_slab_##D##_##XS##_##JS(tpw);
+    CHYM_PICK(1, 3, 1) CHYM_PICK(1, 1, 1) CHYM_PICK(1, 3, 3)
+    CHYM_PICK(2, 3, 1) CHYM_PICK(2, 1, 1) CHYM_PICK(2, 3, 3)
+    CHYM_PICK(3, 3, 1) CHYM_PICK(3, 1, 1) CHYM_PICK(3, 3, 3)
+    CHYM_PICK(4, 3, 1) CHYM_PICK(4, 1, 1) CHYM_PICK(4, 3, 3)
+#undef CHYM_PICK
+    return SlabKernels{nullptr, nullptr};
+}
+
+int slab_tpw_for(int tiles) {
+    const int per = (tiles + kSlabWaves - 1) / kSlabWaves;
+    const int tpw = (per + 3) / 4 * 4;
+    return tpw <= 8 ? tpw : 0;
+}
+
+size_t slab_lds_bytes(int tiles, int d, int xs) { return (size_t)((tiles + 1) / 2) * d * xs * 64 * sizeof(bf16x8); }
+
+size_t slab_jfrag_bytes(int tiles, int js) {
+    return (size_t)tiles * ((tiles + 1) / 2) * js * 64 * sizeof(bf16x8);
+}
+
+bool slab_variant_exists(int tiles, int d, int xs, int js) {
+    const int tpw = slab_tpw_for(tiles);
+    return tpw > 0 && slab_lds_bytes(tiles, d, xs) <= kSlabMaxLds && lookup_slab(tpw, d, xs, js).single != nullptr;
+}
+
+hipError_t launch_stage_jfrag(const IntegArgs &a, int js, void *out, hipStream_t stream) {
+    const int nt = (a.n + 15) / 16;
+    const int ncp = (nt + 1) / 2;
+    const int total = nt * ncp * 64;
+    const int grid = (total + 255) / 256;
+    if (js == 3)
+        hipLaunchKernelGGL(k_stage_jfrag<3>, dim3(grid), dim3(256), 0, stream, a, ncp, reinterpret_cast<bf16x8 *>(out));
+    else
+        hipLaunchKernelGGL(k_stage_jfrag<1>, dim3(grid), dim3(256), 0, stream, a, ncp, reinterpret_cast<bf16x8 *>(out));
+    return hipGetLastError();
+}
+
+static hipError_t slab_prepare(const void *fn, size_t lds) {
+    if (lds <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t launch_integrate_slab(int tiles, int d, int xs, int js, const IntegArgs &a, const void *jfrag,
+                                 hipStream_t stream) {
+    const int tpw = slab_tpw_for(tiles);
+    SlabKernels k = lookup_slab(tpw, d, xs, js);
+    if (!k.single) return hipErrorInvalidDeviceFunction;
+    const size_t lds = slab_lds_bytes(tiles, d, xs);
+    hipError_t e = slab_prepare(reinterpret_cast<const void *>(k.single), lds);
+    if (e != hipSuccess) return e;
+    const int blocks = (a.r + 15) / 16;
+    hipLaunchKernelGGL(k.single, dim3(blocks), dim3(64 * kSlabWaves), lds, stream, a,
+                       reinterpret_cast<const bf16x8 *>(jfrag),
+                       (tiles + 1) / 2);
+    return hipGetLastError();
+}
+
+hipError_t slab_occupancy(int tiles, int d, int xs, int js, size_t lds, int *blocks_per_cu) {
+    *blocks_per_cu = 0;
+    SlabKernels k = lookup_slab(slab_tpw_for(tiles), d, xs, js);
+    if (!k.persistent) return hipErrorInvalidDeviceFunction;
+    hipError_t e = slab_prepare(reinterpret_cast<const void *>(k.persistent), lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k.persistent, 64 * kSlabWaves, lds);
+}
+
+hipError_t launch_integrate_slab_persistent(int tiles, int d, int xs, int js, size_t lds, int blocks,
+                                            const IntegArgs *tasks, const int2 *items, int n_items, int *counter,
+                                            const void *const *jfs, const int *ncps, hipStream_t stream) {
+    SlabKernels k = lookup_slab(slab_tpw_for(tiles), d, xs, js);
+    if (!k.persistent) return hipErrorInvalidDeviceFunction;
+    hipError_t e = slab_prepare(reinterpret_cast<const void *>(k.persistent), lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k.persistent, dim3(blocks), dim3(64 * kSlabWaves), lds, stream, tasks, items, n_items, counter,
+                       reinterpret_cast<const bf16x8 *const *>(jfs), ncps);
+    return hipGetLastError();
 }
 
 // Synthetic problem for timing runs: J = +-1 by a hash of (p, q) (symmetric,

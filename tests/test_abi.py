@@ -69,8 +69,24 @@ def test_null_structs_rejected():
 
 def test_unsupported_size_reported_before_device():
     lib = L.load()
+    # beyond every integrator
+    rc = lib.chym_integrate(ctypes.byref(_prob(n=1100, d=4)), ctypes.byref(_run()), None)
+    assert rc == L.CHYM_EUNSUPPORTED
+    # float32 form operand of 16 replicas too large for LDS
     rc = lib.chym_integrate(ctypes.byref(_prob(n=1000, d=4)), ctypes.byref(_run()), None)
     assert rc == L.CHYM_EUNSUPPORTED
+    # streamed-J sizes need a workspace
+    prob, run = _prob(n=1000, d=4), _run(precision=L.CHYM_PREC_BF16)
+    assert lib.chym_integrate(ctypes.byref(prob), ctypes.byref(run), None) == L.CHYM_EUNSUPPORTED
+    assert "workspace" in lib.chym_last_error().decode()
+    nbytes = ctypes.c_size_t(0)
+    assert lib.chym_integrate_workspace_size(ctypes.byref(prob), ctypes.byref(run), ctypes.byref(nbytes)) == 0
+    assert nbytes.value == 63 * 32 * 1024  # 63 row tiles x 32 chunks x 1 KiB fragments
+    assert lib.chym_integrate_ws(ctypes.byref(prob), ctypes.byref(run), ctypes.c_void_p(0x10000), 100,
+                                 None) == L.CHYM_ENOMEM
+    small = _prob(n=100, d=2)
+    assert lib.chym_integrate_workspace_size(ctypes.byref(small), ctypes.byref(_run()), ctypes.byref(nbytes)) == 0
+    assert nbytes.value == 0
 
 
 def test_other_entry_points_validate():

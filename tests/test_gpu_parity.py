@@ -240,7 +240,7 @@ def test_batched_equals_solo_bit_exact(graph):
 
 
 def test_unsupported_and_invalid_on_device():
-    case = Case(300, 4, 16, 10, key=(21,))
+    case = Case(1100, 1, 16, 10, key=(21,))
     Jd, pump, x, alpha = case.gpu_inputs()
     with pytest.raises(api.ChymError) as ei:
         api.chym_integrate(Jd, pump, x, alpha, steps=10, **case.params())

@@ -1,0 +1,93 @@
+"""The streamed-J (slab) integrator for large N: parity with the oracle,
+identity with the register-resident integrator, batching."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2308_02329_amd import api, synth
+
+torch = pytest.importorskip("torch")
+from gpu_helpers import Case, to_dev  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def run_gpu(case, precision="f32", steps=None, start=0, x=None):
+    Jd, pump, x0, alpha = case.gpu_inputs()
+    xd = x0 if x is None else x
+    api.chym_integrate(Jd, pump, xd, alpha, steps=case.steps if steps is None else steps, start_step=start,
+                       precision=precision, **case.params())
+    return xd
+
+
+@pytest.mark.parametrize("n,d,prec", [(144, 2, "f32"), (128, 3, "f32"), (160, 2, "bf16"), (112, 4, "f32"),
+                                      (192, 1, "f32")])
+def test_slab_equals_resident_bit_exact(n, d, prec):
+    """A problem of n rows on the resident kernel and the same problem padded
+    with one uncoupled zero row (n + 1 rows, slab kernel) agree exactly."""
+    small = Case(n, d, 40, 200, key=(40, n, d), sigma=0.05)
+    big = Case(n + 1, d, 40, 200, key=(40, n, d), sigma=0.05)
+    big.J = np.zeros((n + 1, n + 1), dtype=np.int8)
+    big.J[:n, :n] = small.J
+    big.x0 = np.concatenate([small.x0, np.zeros((1, 40, d), np.float32)], axis=0)
+    big.eps = small.eps
+    assert api.chym_integrate_workspace_size(to_dev(small.J), to_dev(small.x0), precision=prec) == 0
+    assert api.chym_integrate_workspace_size(to_dev(big.J), to_dev(big.x0), precision=prec) > 0
+    a = run_gpu(small, prec).cpu().numpy()
+    b = run_gpu(big, prec).cpu().numpy()
+    assert np.array_equal(b[:n], a)
+    assert not b[n].any()
+
+
+@pytest.mark.parametrize("n,d,r,steps,kind", [(200, 3, 24, 300, "sk"), (400, 2, 16, 200, "sk"),
+                                              (300, 2, 16, 150, "gauss"), (1024, 1, 16, 60, "sk"),
+                                              (250, 4, 19, 200, "er")])
+def test_slab_parity_f32(n, d, r, steps, kind):
+    case = Case(n, d, r, steps, key=(41, n, d), kind=kind, sigma=0.05)
+    xg = run_gpu(case).cpu().numpy()
+    xo = oracle.ode_run(case.J, case.pump, case.x0, steps=steps, alpha=case.alpha, **case.params())
+    err = np.abs(xg - xo).max()
+    assert err <= 1e-4, err
+
+
+def test_slab_bf16_at_config3_shape():
+    """N = 1000, D = 4, bf16 form (the precision workload's shape, few
+    replicas): error against the oracle bounded loosely, readout exact."""
+    case = Case(1000, 4, 16, 60, key=(42,), sigma=0.05)
+    xg = run_gpu(case, "bf16").cpu().numpy()
+    xo = oracle.ode_run(case.J, case.pump, case.x0, steps=60, alpha=case.alpha, **case.params())
+    err = np.abs(xg - xo).max()
+    assert 0.0 < err < 5e-2, err
+
+
+def test_slab_split_run_and_solve():
+    case = Case(300, 3, 20, 240, key=(43,), sigma=0.02)
+    full = run_gpu(case, "bf16").cpu().numpy()
+    Jd, pump, x, alpha = case.gpu_inputs()
+    for k0, k1 in [(0, 101), (101, 240)]:
+        api.chym_integrate(Jd, pump, x, alpha, steps=k1 - k0, start_step=k0, precision="bf16", **case.params())
+    assert np.array_equal(x.cpu().numpy(), full)
+    x2 = to_dev(case.x0)
+    res = api.chym_solve(Jd, pump, x2, alpha, steps=240, ss_step=case.ss, precision="bf16", **case.params())
+    assert np.array_equal(x2.cpu().numpy(), full)
+    np.testing.assert_allclose(res["e_hs"].cpu().numpy(), oracle.hs_energy(case.J, full), rtol=1e-12)
+
+
+def test_mixed_batch_with_slab_tasks_equals_solo():
+    specs = [(100, 2, 40, 150, "f32"), (300, 3, 20, 120, "bf16"), (500, 2, 17, 100, "bf16"), (64, 4, 16, 150, "f32"),
+             (300, 3, 33, 80, "bf16")]
+    cases = [Case(n, d, r, s, key=(44, i), sigma=0.03) for i, (n, d, r, s, _) in enumerate(specs)]
+    tasks, solo = [], []
+    for c, (n, d, r, s, prec) in zip(cases, specs):
+        Jd, pump, x, alpha = c.gpu_inputs()
+        tasks.append(dict(J=Jd, pump=pump, x=x, alpha=alpha, steps=s, precision=prec, **c.params()))
+        solo.append(run_gpu(c, prec).cpu().numpy())
+    b = api.chym_batch_create(tasks)
+    for _ in range(2):
+        for t, c in zip(tasks, cases):
+            t["x"].copy_(to_dev(c.x0))
+        b.launch()
+        torch.cuda.synchronize()
+        for t, ref in zip(tasks, solo):
+            assert np.array_equal(t["x"].cpu().numpy(), ref)
+    b.destroy()
