@@ -51,7 +51,8 @@ def parse():
     ap.add_argument("--autotune", type=int, default=1, help="time the launch plans of each variant first")
     ap.add_argument("--plan-cache", type=str, default="", help="load plans from this file instead of tuning")
     ap.add_argument("--cpu-baseline", type=int, default=1, help="0 disables the oracle timing leg")
-    ap.add_argument("--cpu-replicas", type=int, default=256)
+    ap.add_argument("--cpu-replicas", type=int, default=2000)
+    ap.add_argument("--tts", type=int, default=1, help="0 skips the time-to-99%%-ground-state comparison")
     return ap.parse_args()
 
 
@@ -117,6 +118,24 @@ def cpu_baseline(args, synth, wl):
     return {"value": ups / sec, "unit": "spin-component updates/s", "cores": oracle.max_threads(), "kind": "oracle",
             "sample": f"instance 0, D in {wl['dims']}, replicas 0..{rs - 1} of {wl['R']}, {steps} steps, "
                       f"{ups:.3e} updates in {sec:.2f} s"}
+
+
+def tts_leg():
+    """Time to 99 % ground-state success, plain FP32 vs BF16 + learned
+    restart, on held-out N=100 SK instances (untimed by the bench clock)."""
+    from paper_2308_02329_amd import learned
+
+    rep = learned.experiment(log=None)
+    keep = ("workload", "tts99_median_ms", "instances_solved", "auc_heldout", "keep_fraction_heldout", "theta",
+            "trajectories_train", "positives_heldout_bf16", "positives_heldout_f32", "updates_per_s", "seconds")
+    def finite(v):
+        if isinstance(v, dict):
+            return {k: finite(x) for k, x in v.items()}
+        return None if isinstance(v, float) and not np.isfinite(v) else v
+
+    out = {k: finite(rep[k]) for k in keep}
+    out["unit"] = "ms (median over instances of the best-pump TTS99)"
+    return out
 
 
 def main():
@@ -205,6 +224,8 @@ def main():
            "autotune": plans}
     if args.cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args, synth, wl)
+    if args.tts:
+        res["tts99"] = tts_leg()
     for p in list(wl["plans"].values()) + [wl["score_plan"]]:
         p.destroy()
     print(json.dumps(res), flush=True)

@@ -224,6 +224,60 @@ int chym_batch_launch_nograph(const chym_batch *plan, chym_stream_t stream);
 int chym_batch_destroy(chym_batch *plan);
 
 /* ------------------------------------------------------------------------
+ * Learned early restart.  A small network predicts, from features of the
+ * first part of a run, whether the run will reach the Ising ground state;
+ * runs predicted to fail are restarted from fresh initial states, and every
+ * kept run is still integrated to the end and scored exactly.
+ *
+ * Features: CHYM_FEATURES = 8 checkpoints x 4 values per replica, stored
+ * [r][CHYM_FEATURES] float32; checkpoint k fills columns 4k .. 4k+3 with
+ *   E_hs / n      hyperspin energy per spin (Eq. (3), unit vectors)
+ *   E / n         Ising energy per spin of the current sign readout
+ *   mean_p |x_p|  mean hyperspin norm
+ *   flips / n     fraction of spins whose sign changed since the previous
+ *                 checkpoint (sign words in prev_words, updated in place)
+ * Network: CHYM_FEATURES -> 128 -> 128 -> 1, ReLU, sigmoid output, binary
+ * cross-entropy; parameters in one block of CHYM_MLP_PARAMS values in the
+ * order W1 [128][32], b1 [128], W2 [128][128], b2 [128], w3 [128], b3, held
+ * as a float32 master copy and a bf16 copy (bf16 bit patterns) that the
+ * forward and backward passes read.
+ */
+#define CHYM_FEATURES 32
+#define CHYM_MLP_PARAMS 20865
+
+/* Sign words [r][ceil(n/64)] of x (bit set iff x_{p,1} >= 0): the reference
+ * of the first checkpoint.  n * (d + 1) <= 8192. */
+int chym_sign_words(int32_t n, int32_t d, int32_t r, const float *x, uint64_t *words, chym_stream_t stream);
+
+/* Features of checkpoint `checkpoint` (0..7) of every replica of x. */
+int chym_features(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dtype, const float *x,
+                  uint64_t *prev_words, float *features, int32_t checkpoint, chym_stream_t stream);
+
+/* Float scratch the backward pass needs for a batch. */
+int chym_mlp_scratch_floats(int32_t batch, size_t *floats);
+
+/* Forward pass: logit [batch]; h1, h2 [batch][128] (post-ReLU activations,
+ * may be NULL unless a backward pass follows). */
+int chym_mlp_forward(int32_t batch, const float *features, const uint16_t *w_bf16, float *logit, float *h1, float *h2,
+                     chym_stream_t stream);
+
+/* Gradient of the mean binary cross-entropy over the batch (labels 0/1 as
+ * float) with respect to the parameters (grad [CHYM_MLP_PARAMS]), and each
+ * sample's loss term (loss [batch]).  Deterministic.  scratch: see
+ * chym_mlp_scratch_floats. */
+int chym_mlp_backward(int32_t batch, const float *features, const float *labels, const uint16_t *w_bf16,
+                      const float *logit, const float *h1, const float *h2, float *scratch, float *grad, float *loss,
+                      chym_stream_t stream);
+
+/* One Adam step (Kingma & Ba) on the float32 master weights (step count
+ * t >= 1 for the bias corrections); refreshes the bf16 copy. */
+int chym_mlp_adam(float *w_master, uint16_t *w_bf16, float *m, float *v, const float *grad, float lr, float beta1,
+                  float beta2, float eps, int32_t t, chym_stream_t stream);
+
+/* bf16 copy (round to nearest even) of n float32 values. */
+int chym_to_bf16(const float *src, uint16_t *dst, int32_t n, chym_stream_t stream);
+
+/* ------------------------------------------------------------------------
  * Launch plans and the autotuner.  A plan entry picks, for one kernel
  * variant (n rounded up to 16-row tiles, d, precision, J storage), how the
  * batched path runs it:

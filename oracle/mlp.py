@@ -1,0 +1,100 @@
+"""FP64 reference of the learned-restart network and its trajectory
+features -- TEST INFRASTRUCTURE (see oracle/__init__.py for the rules).
+
+Network: 32 -> 128 -> 128 -> 1, ReLU, sigmoid output, mean binary
+cross-entropy; parameters in one vector ordered W1 [128][32], b1 [128],
+W2 [128][128], b2 [128], w3 [128], b3.  Written from the definitions
+(matrix products, chain rule); pinned by finite differences and closed forms
+in tests/test_oracle_mlp.py.
+
+Features (per replica and checkpoint): E_hs / n (Eq. (3)), E / n of the sign
+readout, mean hyperspin norm, fraction of flipped signs since the previous
+checkpoint -- composed from the oracle's pinned energy and readout routines.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+F, H1, H2 = 32, 128, 128
+SHAPES = (("W1", (H1, F)), ("b1", (H1,)), ("W2", (H2, H1)), ("b2", (H2,)), ("w3", (H2,)), ("b3", (1,)))
+PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
+
+
+def unpack(w):
+    w = np.asarray(w, dtype=np.float64)
+    out, off = {}, 0
+    for name, shp in SHAPES:
+        size = int(np.prod(shp))
+        out[name] = w[off:off + size].reshape(shp)
+        off += size
+    return out
+
+
+def pack(p):
+    return np.concatenate([np.asarray(p[name], dtype=np.float64).ravel() for name, _ in SHAPES])
+
+
+def forward(x, w):
+    """logit [B], h1 [B][128], h2 [B][128] (post-ReLU)."""
+    p = unpack(w)
+    x = np.asarray(x, dtype=np.float64)
+    h1 = np.maximum(x @ p["W1"].T + p["b1"], 0.0)
+    h2 = np.maximum(h1 @ p["W2"].T + p["b2"], 0.0)
+    z = h2 @ p["w3"] + p["b3"][0]
+    return z, h1, h2
+
+
+def loss(x, y, w):
+    """Mean binary cross-entropy of sigmoid(logit) against labels y."""
+    z, _, _ = forward(x, w)
+    y = np.asarray(y, dtype=np.float64)
+    return float(np.mean(np.logaddexp(0.0, z) - y * z))
+
+
+def grad(x, y, w):
+    """Gradient of the mean BCE by the chain rule."""
+    p = unpack(w)
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    z, h1, h2 = forward(x, w)
+    b = x.shape[0]
+    dz = (1.0 / (1.0 + np.exp(-z)) - y) / b
+    g = {"w3": h2.T @ dz, "b3": np.array([dz.sum()])}
+    d2 = np.outer(dz, p["w3"]) * (h2 > 0)
+    g["W2"] = d2.T @ h1
+    g["b2"] = d2.sum(axis=0)
+    d1 = (d2 @ p["W2"]) * (h1 > 0)
+    g["W1"] = d1.T @ x
+    g["b1"] = d1.sum(axis=0)
+    return pack(g)
+
+
+def adam(w, m, v, g, lr, t, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (Kingma & Ba): returns (w, m, v)."""
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** t)
+    vh = v / (1 - b2 ** t)
+    return w - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def bf16_round(a):
+    """Round float32 values to bf16 (nearest even), returned as float64."""
+    a32 = np.asarray(a, dtype=np.float32)
+    bits = a32.view(np.uint32).astype(np.uint64)
+    rb = ((bits + (((bits >> 16) & 1) + 0x7FFF)) >> 16).astype(np.uint32) << 16
+    return rb.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def features(J, x, prev_sigma):
+    """The four checkpoint features of every replica of x [n, r, d] and the
+    new signs; prev_sigma [r][n] are the signs of the previous checkpoint."""
+    n = x.shape[0]
+    sig = oracle.readout(x)
+    ehs = oracle.hs_energy(J, x) / n
+    eis = oracle.ising_energy(J, sig) / n
+    nrm = np.sqrt((np.asarray(x, dtype=np.float64) ** 2).sum(axis=2)).mean(axis=0)
+    flips = (sig != prev_sigma).mean(axis=1)
+    return np.stack([ehs, eis, nrm, flips], axis=1), sig

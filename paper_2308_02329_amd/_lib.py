@@ -28,7 +28,12 @@ EXPORTS = (
     "chym_batch_launch", "chym_batch_launch_nograph", "chym_batch_destroy", "chym_plan_set", "chym_plan_get",
     "chym_plan_autotune_workspace_size", "chym_plan_autotune", "chym_split3_bf16", "chym_plan_save",
     "chym_plan_load", "chym_integrate_workspace_size", "chym_integrate_ws", "chym_solve_ws",
+    "chym_sign_words", "chym_features", "chym_mlp_scratch_floats", "chym_mlp_forward", "chym_mlp_backward",
+    "chym_mlp_adam", "chym_to_bf16",
 )
+
+CHYM_FEATURES = 32
+CHYM_MLP_PARAMS = 20865
 
 CHYM_KERNEL_AUTO = 0
 CHYM_KERNEL_REGJ = 1
@@ -95,6 +100,7 @@ def load():
     lib.chym_integrate_ws.restype = ctypes.c_int
     _load_batch(lib)
     _load_plan(lib)
+    _load_learned(lib)
     _lib = lib
     return lib
 
@@ -141,3 +147,18 @@ def _load_plan(lib):
     for f in ("chym_plan_set", "chym_plan_get", "chym_plan_autotune_workspace_size", "chym_plan_autotune",
               "chym_split3_bf16", "chym_plan_save", "chym_plan_load"):
         getattr(lib, f).restype = ctypes.c_int
+
+
+def _load_learned(lib):
+    P = ctypes.POINTER
+    lib.chym_sign_words.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp]
+    lib.chym_features.argtypes = [_i32, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _i32, _vp]
+    lib.chym_mlp_scratch_floats.argtypes = [_i32, P(ctypes.c_size_t)]
+    lib.chym_mlp_forward.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.chym_mlp_backward.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    f = ctypes.c_float
+    lib.chym_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, _vp, f, f, f, f, _i32, _vp]
+    lib.chym_to_bf16.argtypes = [_vp, _vp, _i32, _vp]
+    for name in ("chym_sign_words", "chym_features", "chym_mlp_scratch_floats", "chym_mlp_forward",
+                 "chym_mlp_backward", "chym_mlp_adam", "chym_to_bf16"):
+        getattr(lib, name).restype = ctypes.c_int

@@ -15,7 +15,8 @@ from . import _lib as L
 from ._lib import (CHYM_J_F32, CHYM_J_I8, CHYM_KERNEL_AUTO, CHYM_KERNEL_LDSJ, CHYM_KERNEL_LDSJ1, CHYM_KERNEL_REGJ,
                    CHYM_PREC_BF16, CHYM_PREC_F32, ChymError, ChymOut, ChymPlanEntry, ChymProblem, ChymRun)
 
-__all__ = ["chym_integrate_workspace_size", "chym_version", "chym_last_error", "chym_integrate", "chym_readout", "chym_ising_energy",
+__all__ = ["chym_sign_words", "chym_features", "chym_mlp_forward", "chym_mlp_backward", "chym_mlp_adam",
+           "chym_mlp_scratch_floats", "chym_to_bf16", "chym_integrate_workspace_size", "chym_version", "chym_last_error", "chym_integrate", "chym_readout", "chym_ising_energy",
            "chym_hs_energy", "chym_solve", "make_problem", "make_run", "spin_words", "ChymError",
            "CHYM_J_I8", "CHYM_J_F32", "CHYM_PREC_F32", "CHYM_PREC_BF16", "precision_code",
            "chym_batch_workspace_size", "chym_batch_create", "chym_batch_launch", "chym_batch_launch_nograph",
@@ -350,3 +351,68 @@ def chym_split3_bf16(x):
     hi, mid, lo = (torch.empty(n, dtype=torch.int16, device=x.device) for _ in range(3))
     L.check(L.load().chym_split3_bf16(_vp(x), n, _vp(hi), _vp(mid), _vp(lo), _stream(None)), "chym_split3_bf16")
     return hi, mid, lo
+
+
+# --------------------------------------------------------- learned restart
+def chym_sign_words(x, words=None, stream=None):
+    n, r, d = x.shape
+    _need(x, "x", torch.float32)
+    if words is None:
+        words = torch.empty((r, spin_words(n)), dtype=torch.int64, device=x.device)
+    _need(words, "words", torch.int64, (r, spin_words(n)))
+    L.check(L.load().chym_sign_words(n, d, r, _vp(x), _vp(words), _stream(stream)), "chym_sign_words")
+    return words
+
+
+def chym_features(J, x, prev_words, features, checkpoint, stream=None):
+    n, r, d = x.shape
+    _need(J, "J", J.dtype, (n, n))
+    _need(x, "x", torch.float32)
+    _need(prev_words, "prev_words", torch.int64, (r, spin_words(n)))
+    _need(features, "features", torch.float32, (r, L.CHYM_FEATURES))
+    L.check(L.load().chym_features(n, d, r, _vp(J), _jdtype(J), _vp(x), _vp(prev_words), _vp(features),
+                                   int(checkpoint), _stream(stream)), "chym_features")
+
+
+def chym_mlp_forward(features, w_bf16, logit=None, h1=None, h2=None, stream=None):
+    b = features.shape[0]
+    _need(features, "features", torch.float32, (b, L.CHYM_FEATURES))
+    _need(w_bf16, "w_bf16", torch.int16, (L.CHYM_MLP_PARAMS,))
+    if logit is None:
+        logit = torch.empty(b, dtype=torch.float32, device=features.device)
+    L.check(L.load().chym_mlp_forward(b, _vp(features), _vp(w_bf16), _vp(logit), _vp(h1), _vp(h2), _stream(stream)),
+            "chym_mlp_forward")
+    return logit
+
+
+def chym_mlp_scratch_floats(batch) -> int:
+    f = ctypes.c_size_t(0)
+    L.check(L.load().chym_mlp_scratch_floats(int(batch), ctypes.byref(f)), "chym_mlp_scratch_floats")
+    return int(f.value)
+
+
+def chym_mlp_backward(features, labels, w_bf16, logit, h1, h2, scratch, grad, loss, stream=None):
+    b = features.shape[0]
+    _need(labels, "labels", torch.float32, (b,))
+    _need(grad, "grad", torch.float32, (L.CHYM_MLP_PARAMS,))
+    _need(loss, "loss", torch.float32, (b,))
+    if scratch.numel() < chym_mlp_scratch_floats(b):
+        raise ValueError("scratch too small")
+    L.check(L.load().chym_mlp_backward(b, _vp(features), _vp(labels), _vp(w_bf16), _vp(logit), _vp(h1), _vp(h2),
+                                       _vp(scratch), _vp(grad), _vp(loss), _stream(stream)), "chym_mlp_backward")
+
+
+def chym_mlp_adam(w_master, w_bf16, m, v, grad, lr, t, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    for name, tsr in (("w_master", w_master), ("m", m), ("v", v), ("grad", grad)):
+        _need(tsr, name, torch.float32, (L.CHYM_MLP_PARAMS,))
+    _need(w_bf16, "w_bf16", torch.int16, (L.CHYM_MLP_PARAMS,))
+    L.check(L.load().chym_mlp_adam(_vp(w_master), _vp(w_bf16), _vp(m), _vp(v), _vp(grad), float(lr), float(beta1),
+                                   float(beta2), float(eps), int(t), _stream(stream)), "chym_mlp_adam")
+
+
+def chym_to_bf16(src, dst=None, stream=None):
+    _need(src, "src", torch.float32)
+    if dst is None:
+        dst = torch.empty(src.numel(), dtype=torch.int16, device=src.device)
+    L.check(L.load().chym_to_bf16(_vp(src), _vp(dst), src.numel(), _stream(stream)), "chym_to_bf16")
+    return dst

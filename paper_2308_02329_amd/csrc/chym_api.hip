@@ -919,6 +919,85 @@ int chym_split3_bf16(const float *x, int64_t n, uint16_t *hi, uint16_t *mid, uin
     return e == hipSuccess ? CHYM_OK : hip_fail(e, "split launch");
 }
 
+// ----------------------------------------------------------- learned restart
+int chym_sign_words(int32_t n, int32_t d, int32_t r, const float *x, uint64_t *words, chym_stream_t stream) {
+    int rc = validate_sizes(n, d, r);
+    if (rc) return rc;
+    if (!x || !words) return fail(CHYM_EINVAL, "x and words must not be NULL");
+    rc = check_device();
+    if (rc) return rc;
+    hipError_t e = chym::launch_sign_words(n, d, r, x, words, (hipStream_t)stream);
+    return e == hipSuccess ? CHYM_OK : hip_fail(e, "sign words launch");
+}
+
+int chym_features(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dtype, const float *x,
+                  uint64_t *prev_words, float *features, int32_t checkpoint, chym_stream_t stream) {
+    int rc = validate_sizes(n, d, r);
+    if (rc) return rc;
+    if ((long long)n * (d + 1) > 8192) return fail(CHYM_EUNSUPPORTED, "features need n * (d + 1) <= 8192");
+    if (j_dtype != CHYM_J_I8 && j_dtype != CHYM_J_F32) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
+    if (!j || !x || !prev_words || !features) return fail(CHYM_EINVAL, "pointers must not be NULL");
+    if (checkpoint < 0 || 4 * checkpoint + 4 > CHYM_FEATURES)
+        return fail(CHYM_EINVAL, "checkpoint = %d must be in 0..%d", checkpoint, CHYM_FEATURES / 4 - 1);
+    rc = check_device();
+    if (rc) return rc;
+    hipError_t e = chym::launch_features(n, d, r, j, j_dtype, x, prev_words, features, CHYM_FEATURES, 4 * checkpoint,
+                                         (hipStream_t)stream);
+    return e == hipSuccess ? CHYM_OK : hip_fail(e, "features launch");
+}
+
+int chym_mlp_scratch_floats(int32_t batch, size_t *floats) {
+    if (!floats || batch < 0) return fail(CHYM_EINVAL, "bad arguments");
+    *floats = chym::mlp_backward_scratch_floats(batch);
+    return CHYM_OK;
+}
+
+int chym_mlp_forward(int32_t batch, const float *features, const uint16_t *w_bf16, float *logit, float *h1, float *h2,
+                     chym_stream_t stream) {
+    if (batch < 0) return fail(CHYM_EINVAL, "batch = %d must be >= 0", batch);
+    if (!features || !w_bf16 || !logit) return fail(CHYM_EINVAL, "features, weights and logit must not be NULL");
+    if ((h1 == nullptr) != (h2 == nullptr)) return fail(CHYM_EINVAL, "h1 and h2 must both be given or both NULL");
+    if (batch == 0) return CHYM_OK;
+    int rc = check_device();
+    if (rc) return rc;
+    hipError_t e = chym::launch_mlp_forward(batch, features, w_bf16, logit, h1, h2, (hipStream_t)stream);
+    return e == hipSuccess ? CHYM_OK : hip_fail(e, "mlp forward launch");
+}
+
+int chym_mlp_backward(int32_t batch, const float *features, const float *labels, const uint16_t *w_bf16,
+                      const float *logit, const float *h1, const float *h2, float *scratch, float *grad, float *loss,
+                      chym_stream_t stream) {
+    if (batch < 1) return fail(CHYM_EINVAL, "batch = %d must be >= 1", batch);
+    if (!features || !labels || !w_bf16 || !logit || !h1 || !h2 || !scratch || !grad || !loss)
+        return fail(CHYM_EINVAL, "pointers must not be NULL");
+    int rc = check_device();
+    if (rc) return rc;
+    hipError_t e = chym::launch_mlp_backward(batch, features, labels, w_bf16, logit, h1, h2, scratch, grad, loss,
+                                             (hipStream_t)stream);
+    return e == hipSuccess ? CHYM_OK : hip_fail(e, "mlp backward launch");
+}
+
+int chym_mlp_adam(float *w_master, uint16_t *w_bf16, float *m, float *v, const float *grad, float lr, float beta1,
+                  float beta2, float eps, int32_t t, chym_stream_t stream) {
+    if (!w_master || !w_bf16 || !m || !v || !grad) return fail(CHYM_EINVAL, "pointers must not be NULL");
+    if (t < 1) return fail(CHYM_EINVAL, "t = %d must be >= 1", t);
+    if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return fail(CHYM_EINVAL, "bad Adam hyper-parameters");
+    int rc = check_device();
+    if (rc) return rc;
+    hipError_t e = chym::launch_mlp_adam(w_master, w_bf16, m, v, grad, lr, beta1, beta2, eps, t, (hipStream_t)stream);
+    return e == hipSuccess ? CHYM_OK : hip_fail(e, "adam launch");
+}
+
+int chym_to_bf16(const float *src, uint16_t *dst, int32_t n, chym_stream_t stream) {
+    if (!src || !dst || n < 0) return fail(CHYM_EINVAL, "bad arguments");
+    if (n == 0) return CHYM_OK;
+    int rc = check_device();
+    if (rc) return rc;
+    hipError_t e = chym::launch_to_bf16(src, dst, n, (hipStream_t)stream);
+    return e == hipSuccess ? CHYM_OK : hip_fail(e, "bf16 launch");
+}
+
 int chym_plan_save(const char *path) {
     if (!path) return fail(CHYM_EINVAL, "path is NULL");
     FILE *f = fopen(path, "w");

@@ -82,6 +82,21 @@ hipError_t launch_integrate_slab_persistent(int tiles, int d, int xs, int js, si
                                             const IntegArgs *tasks, const int2 *items, int n_items, int *counter,
                                             const void *const *jfs, const int *ncps, hipStream_t stream);
 
+// Learned early restart: trajectory features and the MLP.
+hipError_t launch_features(int n, int d, int r, const void *j, int j_dtype, const float *x, uint64_t *prev,
+                           float *feat, int feat_stride, int feat_off, hipStream_t stream);
+hipError_t launch_sign_words(int n, int d, int r, const float *x, uint64_t *words, hipStream_t stream);
+int mlp_param_count();
+size_t mlp_backward_scratch_floats(int batch);
+hipError_t launch_mlp_forward(int batch, const float *feat, const void *wb, float *logit, float *h1, float *h2,
+                              hipStream_t stream);
+hipError_t launch_mlp_backward(int batch, const float *feat, const float *label, const void *wb, const float *logit,
+                               const float *h1, const float *h2, float *scratch, float *grad, float *loss,
+                               hipStream_t stream);
+hipError_t launch_mlp_adam(float *wm, void *wb, float *m, float *v, const float *grad, float lr, float b1, float b2,
+                           float eps, int t, hipStream_t stream);
+hipError_t launch_to_bf16(const float *src, void *dst, int n, hipStream_t stream);
+
 hipError_t launch_readout(int n, int d, int r, const float *x, uint64_t *spins, double *extra,
                           uint8_t *diverged, hipStream_t stream);
 hipError_t launch_ising_energy(int n, int r, const void *j, int j_dtype, const uint64_t *spins,

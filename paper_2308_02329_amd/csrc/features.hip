@@ -1,0 +1,343 @@
+// Trajectory features for the learned early restart, and the small MLP that
+// maps them to a success logit.
+//
+// Features (per replica, at one checkpoint): the hyperspin energy per spin
+// E_hs / N (Eq. (3), unit vectors), the Ising energy per spin of the current
+// sign readout E / N, the mean hyperspin norm mean_p |x_p|, and the fraction
+// of spins whose sign flipped since the previous checkpoint.  One wavefront
+// per replica, float64 reductions.
+//
+// MLP: 32 -> 128 -> 128 -> 1, ReLU, sigmoid output, binary cross-entropy.
+// Weights are kept as float32 master copies (updated by Adam) and as a bf16
+// copy that the forward and backward passes use; activations and
+// accumulations are float32.
+#include "chym_internal.h"
+
+namespace chym {
+
+template <typename T>
+__device__ __forceinline__ T wsum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// LDS per wavefront: u[n][d] (float64) and the n signs as +-1 (float64).
+__global__ __launch_bounds__(64) void k_features(int n, int d, int r, const void *__restrict__ j, int j_dtype,
+                                                 const float *__restrict__ x, uint64_t *__restrict__ prev,
+                                                 float *__restrict__ feat, int feat_stride, int feat_off) {
+    extern __shared__ double sh[];
+    double *u = sh;            // [n][d]
+    double *sg = sh + n * d;   // [n]
+    const int lane = threadIdx.x;
+    const int rep = blockIdx.x;
+    if (rep >= r) return;
+    const int w = (n + 63) >> 6;
+    double nsum = 0.0;
+    int flips = 0;
+    for (int q = lane; q < n; q += 64) {
+        const float *xq = x + ((size_t)q * r + rep) * d;
+        double s = 0.0;
+        for (int mu = 0; mu < d; ++mu) {
+            const double v = (double)xq[mu];
+            s = s + v * v;
+        }
+        const double nrm = sqrt(s);
+        nsum += nrm;
+        for (int mu = 0; mu < d; ++mu) u[q * d + mu] = nrm > 0.0 ? (double)xq[mu] / nrm : 0.0;
+        const bool up = xq[0] >= 0.0f;
+        sg[q] = up ? 1.0 : -1.0;
+        const bool was = (prev[(size_t)rep * w + (q >> 6)] >> (q & 63)) & 1ull;
+        flips += (up != was);
+    }
+    __syncthreads();
+    double ehs = 0.0, eis = 0.0;
+    for (int q = lane; q < n; q += 64) {
+        double hh = 0.0, hi = 0.0;
+        for (int p = 0; p < n; ++p) {
+            const double jv = (j_dtype == CHYM_J_I8) ? (double)reinterpret_cast<const int8_t *>(j)[(size_t)p * n + q]
+                                                     : (double)reinterpret_cast<const float *>(j)[(size_t)p * n + q];
+            double dot = 0.0;
+            for (int mu = 0; mu < d; ++mu) dot = dot + u[p * d + mu] * u[q * d + mu];
+            hh = hh + jv * dot;
+            hi = hi + jv * sg[p];
+        }
+        ehs += hh;
+        eis += hi * sg[q];
+    }
+    ehs = wsum(ehs);
+    eis = wsum(eis);
+    nsum = wsum(nsum);
+    flips = wsum(flips);
+    // new sign words (one per 64 spins, built by the lanes that own them)
+    __syncthreads();
+    for (int wd = 0; wd < w; ++wd) {
+        const int q = wd * 64 + lane;
+        const bool up = q < n && sg[q] > 0.0;
+        const uint64_t bits = __ballot(up);
+        if (lane == 0) prev[(size_t)rep * w + wd] = bits;
+    }
+    if (lane == 0) {
+        float *f = feat + (size_t)rep * feat_stride + feat_off;
+        f[0] = (float)(-ehs / n);
+        f[1] = (float)(-eis / n);
+        f[2] = (float)(nsum / n);
+        f[3] = (float)flips / (float)n;
+    }
+}
+
+// Sign words of the initial state (the reference of the first checkpoint).
+__global__ __launch_bounds__(64) void k_sign_words(int n, int d, int r, const float *__restrict__ x,
+                                                   uint64_t *__restrict__ words) {
+    const int lane = threadIdx.x;
+    const int rep = blockIdx.x;
+    if (rep >= r) return;
+    const int w = (n + 63) >> 6;
+    for (int wd = 0; wd < w; ++wd) {
+        const int q = wd * 64 + lane;
+        const bool up = q < n && x[((size_t)q * r + rep) * d] >= 0.0f;
+        const uint64_t bits = __ballot(up);
+        if (lane == 0) words[(size_t)rep * w + wd] = bits;
+    }
+}
+
+hipError_t launch_features(int n, int d, int r, const void *j, int j_dtype, const float *x, uint64_t *prev,
+                           float *feat, int feat_stride, int feat_off, hipStream_t stream) {
+    const size_t lds = sizeof(double) * ((size_t)n * d + n);
+    hipLaunchKernelGGL(k_features, dim3(r), dim3(64), lds, stream, n, d, r, j, j_dtype, x, prev, feat, feat_stride,
+                       feat_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_sign_words(int n, int d, int r, const float *x, uint64_t *words, hipStream_t stream) {
+    hipLaunchKernelGGL(k_sign_words, dim3(r), dim3(64), 0, stream, n, d, r, x, words);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ MLP
+// Parameter block layout (float32 master and bf16 copy use the same order):
+//   W1 [H1][F], b1 [H1], W2 [H2][H1], b2 [H2], w3 [H2], b3 [1]
+constexpr int kF = 32, kH1 = 128, kH2 = 128;
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kH1 * kF;
+constexpr int kOffW2 = kOffB1 + kH1;
+constexpr int kOffB2 = kOffW2 + kH2 * kH1;
+constexpr int kOffW3 = kOffB2 + kH2;
+constexpr int kOffB3 = kOffW3 + kH2;
+constexpr int kParams = kOffB3 + 1;
+static_assert(kParams == CHYM_MLP_PARAMS && kF == CHYM_FEATURES, "parameter block must match chym.h");
+
+__device__ __forceinline__ float bf(const __bf16 *w, int i) { return (float)w[i]; }
+
+// Forward pass of one sample per thread; the bf16 weights are staged in LDS
+// as float32 once per block.  Writes the logit, and the hidden activations
+// when h1/h2 are given (for the backward pass).
+__global__ __launch_bounds__(128) void k_mlp_forward(int batch, const float *__restrict__ feat,
+                                                     const __bf16 *__restrict__ wb, float *__restrict__ logit,
+                                                     float *__restrict__ h1, float *__restrict__ h2) {
+    extern __shared__ float w[];  // kParams floats
+    for (int i = threadIdx.x; i < kParams; i += blockDim.x) w[i] = bf(wb, i);
+    __syncthreads();
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= batch) return;
+    float in[kF];
+#pragma unroll
+    for (int i = 0; i < kF; ++i) in[i] = feat[(size_t)s * kF + i];
+    float a1[kH1];
+    for (int o = 0; o < kH1; ++o) {
+        float acc = w[kOffB1 + o];
+#pragma unroll
+        for (int i = 0; i < kF; ++i) acc = fmaf(w[kOffW1 + o * kF + i], in[i], acc);
+        a1[o] = acc > 0.0f ? acc : 0.0f;
+        if (h1) h1[(size_t)s * kH1 + o] = a1[o];
+    }
+    float z = w[kOffB3];
+    for (int o = 0; o < kH2; ++o) {
+        float acc = w[kOffB2 + o];
+        for (int i = 0; i < kH1; ++i) acc = fmaf(w[kOffW2 + o * kH1 + i], a1[i], acc);
+        const float a2 = acc > 0.0f ? acc : 0.0f;
+        if (h2) h2[(size_t)s * kH2 + o] = a2;
+        z = fmaf(w[kOffW3 + o], a2, z);
+    }
+    logit[s] = z;
+}
+
+// Backward pass of the mean binary cross-entropy over the batch, in three
+// deterministic stages:
+//  1. k_mlp_backward_act, one sample per thread: dz = (sigmoid(z) - y) / B,
+//     d2 = dz w3 * [h2 > 0], d1 = (W2^T d2) * [h1 > 0], and the loss term;
+//  2. k_mlp_wgrad, NS samples per block: the block's partial weight
+//     gradients (sums over its samples of outer products), one parameter
+//     per thread at a time, operands staged in LDS;
+//  3. k_mlp_reduce: the partials summed over blocks in block order.
+__global__ __launch_bounds__(128) void k_mlp_backward_act(int batch, const float *__restrict__ label,
+                                                          const __bf16 *__restrict__ wb,
+                                                          const float *__restrict__ logit,
+                                                          const float *__restrict__ h1, const float *__restrict__ h2,
+                                                          float *__restrict__ dzs, float *__restrict__ d1s,
+                                                          float *__restrict__ d2s, float *__restrict__ loss) {
+    extern __shared__ float w[];  // W2 [kH2][kH1], then w3 [kH2]
+    for (int i = threadIdx.x; i < kH2 * kH1; i += blockDim.x) w[i] = bf(wb, kOffW2 + i);
+    for (int i = threadIdx.x; i < kH2; i += blockDim.x) w[kH2 * kH1 + i] = bf(wb, kOffW3 + i);
+    __syncthreads();
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= batch) return;
+    const float z = logit[s];
+    const float y = label[s];
+    const float p = 1.0f / (1.0f + expf(-z));
+    const float dz = (p - y) / (float)batch;
+    dzs[s] = dz;
+    loss[s] = (z > 0.0f ? z + log1pf(expf(-z)) : log1pf(expf(z))) - y * z;
+    float d1[kH1];
+#pragma unroll
+    for (int i = 0; i < kH1; ++i) d1[i] = 0.0f;
+    for (int o = 0; o < kH2; ++o) {
+        const float d2 = h2[(size_t)s * kH2 + o] > 0.0f ? dz * w[kH2 * kH1 + o] : 0.0f;
+        d2s[(size_t)s * kH2 + o] = d2;
+#pragma unroll
+        for (int i = 0; i < kH1; ++i) d1[i] = fmaf(d2, w[o * kH1 + i], d1[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kH1; ++i) d1s[(size_t)s * kH1 + i] = h1[(size_t)s * kH1 + i] > 0.0f ? d1[i] : 0.0f;
+}
+
+constexpr int kNS = 16;  // samples per block of the weight-gradient stage
+
+__global__ __launch_bounds__(256) void k_mlp_wgrad(int batch, const float *__restrict__ feat,
+                                                   const float *__restrict__ h1, const float *__restrict__ h2,
+                                                   const float *__restrict__ dzs, const float *__restrict__ d1s,
+                                                   const float *__restrict__ d2s, float *__restrict__ partial) {
+    __shared__ float sx[kNS][kF], sh1[kNS][kH1], sh2[kNS][kH2], sd1[kNS][kH1], sd2[kNS][kH2], sdz[kNS];
+    const int s0 = blockIdx.x * kNS;
+    const int ns = batch - s0 < kNS ? batch - s0 : kNS;
+    for (int i = threadIdx.x; i < kNS * kH1; i += blockDim.x) {
+        const int a = i / kH1, b = i % kH1;
+        const bool ok = a < ns;
+        sh1[a][b] = ok ? h1[(size_t)(s0 + a) * kH1 + b] : 0.0f;
+        sh2[a][b] = ok ? h2[(size_t)(s0 + a) * kH2 + b] : 0.0f;
+        sd1[a][b] = ok ? d1s[(size_t)(s0 + a) * kH1 + b] : 0.0f;
+        sd2[a][b] = ok ? d2s[(size_t)(s0 + a) * kH2 + b] : 0.0f;
+    }
+    for (int i = threadIdx.x; i < kNS * kF; i += blockDim.x) {
+        const int a = i / kF, b = i % kF;
+        sx[a][b] = a < ns ? feat[(size_t)(s0 + a) * kF + b] : 0.0f;
+    }
+    for (int i = threadIdx.x; i < kNS; i += blockDim.x) sdz[i] = i < ns ? dzs[s0 + i] : 0.0f;
+    __syncthreads();
+    float *out = partial + (size_t)blockIdx.x * kParams;
+    for (int pi = threadIdx.x; pi < kParams; pi += blockDim.x) {
+        float acc = 0.0f;
+        if (pi < kOffB1) {  // W1[o][k] = sum d1[o] x[k]
+            const int o = pi / kF, k = pi % kF;
+            for (int a = 0; a < kNS; ++a) acc = fmaf(sd1[a][o], sx[a][k], acc);
+        } else if (pi < kOffW2) {
+            const int o = pi - kOffB1;
+            for (int a = 0; a < kNS; ++a) acc += sd1[a][o];
+        } else if (pi < kOffB2) {  // W2[o][i] = sum d2[o] h1[i]
+            const int o = (pi - kOffW2) / kH1, i = (pi - kOffW2) % kH1;
+            for (int a = 0; a < kNS; ++a) acc = fmaf(sd2[a][o], sh1[a][i], acc);
+        } else if (pi < kOffW3) {
+            const int o = pi - kOffB2;
+            for (int a = 0; a < kNS; ++a) acc += sd2[a][o];
+        } else if (pi < kOffB3) {  // w3[o] = sum dz h2[o]
+            const int o = pi - kOffW3;
+            for (int a = 0; a < kNS; ++a) acc = fmaf(sdz[a], sh2[a][o], acc);
+        } else {
+            for (int a = 0; a < kNS; ++a) acc += sdz[a];
+        }
+        out[pi] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_reduce(int blocks, const float *__restrict__ partial,
+                                                    float *__restrict__ grad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kParams) return;
+    float acc = 0.0f;
+    for (int b = 0; b < blocks; ++b) acc += partial[(size_t)b * kParams + i];
+    grad[i] = acc;
+}
+
+// Adam (Kingma & Ba) on the float32 master weights; refreshes the bf16 copy.
+__global__ __launch_bounds__(256) void k_mlp_adam(float *__restrict__ wm, __bf16 *__restrict__ wb,
+                                                  float *__restrict__ m, float *__restrict__ v,
+                                                  const float *__restrict__ grad, float lr, float b1, float b2,
+                                                  float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kParams) return;
+    const float gi = grad[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / c1, vh = vi / c2;
+    const float wi = wm[i] - lr * mh / (sqrtf(vh) + eps);
+    wm[i] = wi;
+    wb[i] = (__bf16)wi;
+}
+
+__global__ __launch_bounds__(256) void k_to_bf16(const float *__restrict__ src, __bf16 *__restrict__ dst, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (__bf16)src[i];
+}
+
+int mlp_param_count() { return kParams; }
+
+hipError_t launch_mlp_forward(int batch, const float *feat, const void *wb, float *logit, float *h1, float *h2,
+                              hipStream_t stream) {
+    if (batch <= 0) return hipSuccess;
+    const int block = 128;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_forward),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(float) * kParams));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_forward, dim3((batch + block - 1) / block), dim3(block), sizeof(float) * kParams,
+                       stream, batch, feat, reinterpret_cast<const __bf16 *>(wb), logit, h1, h2);
+    return hipGetLastError();
+}
+
+// Backward scratch: dz [B], d1 [B][H1], d2 [B][H2], per-block partial
+// gradients [ceil(B / kNS)][kParams].
+size_t mlp_backward_scratch_floats(int batch) {
+    return (size_t)batch * (1 + kH1 + kH2) + (size_t)((batch + kNS - 1) / kNS) * kParams;
+}
+
+hipError_t launch_mlp_backward(int batch, const float *feat, const float *label, const void *wb, const float *logit,
+                               const float *h1, const float *h2, float *scratch, float *grad, float *loss,
+                               hipStream_t stream) {
+    if (batch <= 0) return hipSuccess;
+    float *dzs = scratch;
+    float *d1s = dzs + batch;
+    float *d2s = d1s + (size_t)batch * kH1;
+    float *partial = d2s + (size_t)batch * kH2;
+    const int block = 128;
+    const size_t lds = sizeof(float) * (kH2 * kH1 + kH2);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_backward_act),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_backward_act, dim3((batch + block - 1) / block), dim3(block), lds, stream, batch, label,
+                       reinterpret_cast<const __bf16 *>(wb), logit, h1, h2, dzs, d1s, d2s, loss);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int wblocks = (batch + kNS - 1) / kNS;
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3(wblocks), dim3(256), 0, stream, batch, feat, h1, h2, dzs, d1s, d2s, partial);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kParams + 255) / 256), dim3(256), 0, stream, wblocks, partial, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float *wm, void *wb, float *m, float *v, const float *grad, float lr, float b1, float b2,
+                           float eps, int t, hipStream_t stream) {
+    const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+    hipLaunchKernelGGL(k_mlp_adam, dim3((kParams + 255) / 256), dim3(256), 0, stream, wm,
+                       reinterpret_cast<__bf16 *>(wb), m, v, grad, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float *src, void *dst, int n, hipStream_t stream) {
+    hipLaunchKernelGGL(k_to_bf16, dim3((n + 255) / 256), dim3(256), 0, stream, src, reinterpret_cast<__bf16 *>(dst),
+                       n);
+    return hipGetLastError();
+}
+
+}  // namespace chym

@@ -1,0 +1,423 @@
+"""Learned early restart for the CHYM and its time-to-solution accounting.
+
+A run of the machine is cheap to start and expensive to finish.  From
+features of its first part (default: the first 10 % of the Euler steps,
+sampled at 8 checkpoints, see ``chym_features`` in include/chym.h) a small
+network predicts whether the run will end in the Ising ground state; runs
+predicted to fail are abandoned and restarted from fresh initial states.
+Every kept run is still integrated to the end and judged by its exact Ising
+energy, so the method's answers are unchanged; only the cost per success
+changes.  The plain method (no restarts) is the fallback.
+
+All arithmetic runs in libchym's kernels: the integrator, the feature
+kernel, and the network's forward, backward and Adam kernels.  This module
+holds the orchestration: data generation, the training loop, the
+restart policy and the time-to-99%-success (TTS99) bookkeeping
+
+    TTS99 = t_attempt * ln(0.01) / ln(1 - p_success_per_attempt)
+
+(t_attempt = GPU time per attempt; p >= 0.99 gives one attempt; p = 0 gives
+infinity).  With restarts an attempt costs the partial run, plus the rest of
+the run when kept, and succeeds when kept and successful.
+
+The ground-state energy of an instance is the best energy found by any run
+of it (a putative ground state; exact ones come from exhaustive search in
+the tests).
+
+    python -m paper_2308_02329_amd.learned --out report.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import api, synth
+
+N_CKPT = 8
+N_FEAT = L.CHYM_FEATURES
+
+
+# ---------------------------------------------------------------- network
+class RestartNet:
+    """32 -> 128 -> 128 -> 1 network on the GPU: float32 master weights, a
+    bf16 copy used by the forward/backward kernels, Adam moments, and the
+    feature standardization (mean, scale) learned from the training set."""
+
+    def __init__(self, seed: int = 0, device: str = "cuda"):
+        g = np.random.default_rng(seed)
+        # He initialization for the ReLU layers, zero biases
+        w1 = g.standard_normal((128, 32)) * math.sqrt(2.0 / 32)
+        w2 = g.standard_normal((128, 128)) * math.sqrt(2.0 / 128)
+        w3 = g.standard_normal(128) * math.sqrt(1.0 / 128)
+        w = np.concatenate([w1.ravel(), np.zeros(128), w2.ravel(), np.zeros(128), w3, np.zeros(1)])
+        self.device = torch.device(device)
+        self.w = torch.from_numpy(w.astype(np.float32)).to(self.device)
+        self.wb = api.chym_to_bf16(self.w)
+        self.m = torch.zeros_like(self.w)
+        self.v = torch.zeros_like(self.w)
+        self.t = 0
+        self.mu = torch.zeros(N_FEAT, device=self.device)
+        self.sd = torch.ones(N_FEAT, device=self.device)
+        self._bufs = {}
+
+    def state(self):
+        return [t.clone() for t in (self.w, self.wb, self.m, self.v)] + [self.t]
+
+    def load_state(self, st):
+        for dst, src in zip((self.w, self.wb, self.m, self.v), st[:4]):
+            dst.copy_(src)
+        self.t = st[4]
+
+    def set_scaler(self, feats: torch.Tensor):
+        self.mu = feats.mean(dim=0)
+        self.sd = feats.std(dim=0).clamp_min(1e-6)
+
+    def standardize(self, feats: torch.Tensor) -> torch.Tensor:
+        return ((feats - self.mu) / self.sd).contiguous()
+
+    def _buf(self, b):
+        if b not in self._bufs:
+            dev = self.device
+            self._bufs[b] = dict(
+                h1=torch.empty((b, 128), dtype=torch.float32, device=dev),
+                h2=torch.empty((b, 128), dtype=torch.float32, device=dev),
+                logit=torch.empty(b, dtype=torch.float32, device=dev),
+                loss=torch.empty(b, dtype=torch.float32, device=dev),
+                scratch=torch.empty(api.chym_mlp_scratch_floats(b), dtype=torch.float32, device=dev),
+                grad=torch.empty(L.CHYM_MLP_PARAMS, dtype=torch.float32, device=dev))
+        return self._bufs[b]
+
+    def train_step(self, xs: torch.Tensor, y: torch.Tensor, lr: float) -> float:
+        """One Adam step on standardized features xs [B, 32] and labels y."""
+        b = xs.shape[0]
+        bf = self._buf(b)
+        api.chym_mlp_forward(xs, self.wb, bf["logit"], bf["h1"], bf["h2"])
+        api.chym_mlp_backward(xs, y, self.wb, bf["logit"], bf["h1"], bf["h2"], bf["scratch"], bf["grad"], bf["loss"])
+        self.t += 1
+        api.chym_mlp_adam(self.w, self.wb, self.m, self.v, bf["grad"], lr=lr, t=self.t)
+        return float(bf["loss"].mean().item())
+
+    def logits(self, xs: torch.Tensor) -> torch.Tensor:
+        """Logits of standardized features."""
+        return api.chym_mlp_forward(xs.contiguous(), self.wb)
+
+    def inference_weights(self) -> torch.Tensor:
+        """bf16 weights with the standardization folded into the first layer,
+        so that raw features go straight into the forward kernel:
+        W1' = W1 / sd (per input), b1' = b1 - W1' mu."""
+        w = self.w.clone()
+        w1 = w[:4096].view(128, 32) / self.sd[None, :]
+        w[:4096] = w1.reshape(-1)
+        w[4096:4224] = w[4096:4224] - w1 @ self.mu
+        return api.chym_to_bf16(w)
+
+    def predict_raw(self, feats: torch.Tensor, wb_inf: torch.Tensor | None = None) -> torch.Tensor:
+        wb_inf = self.inference_weights() if wb_inf is None else wb_inf
+        return api.chym_mlp_forward(feats.contiguous(), wb_inf)
+
+    def fit(self, xs: torch.Tensor, y: torch.Tensor, epochs: int = 4, batch: int = 8192, lr: float = 2e-3,
+            seed: int = 0, pos_frac: float = 0.0, log=None) -> list:
+        """Mini-batch training on standardized features; returns epoch losses.
+        pos_frac > 0 draws that share of every batch from the positives (with
+        replacement): rare successes are otherwise a handful per batch."""
+        g = torch.Generator(device=xs.device)
+        g.manual_seed(seed)
+        n = xs.shape[0]
+        batch = min(batch, n)
+        pos = torch.nonzero(y > 0.5).flatten()
+        neg = torch.nonzero(y <= 0.5).flatten()
+        n_pos = int(round(pos_frac * batch)) if pos_frac > 0 and len(pos) and len(neg) else 0
+        hist = []
+        for ep in range(epochs):
+            tot, cnt = 0.0, 0
+            if n_pos:
+                for _ in range(max(1, n // batch)):
+                    ip = pos[torch.randint(len(pos), (n_pos,), generator=g, device=xs.device)]
+                    ineg = neg[torch.randint(len(neg), (batch - n_pos,), generator=g, device=xs.device)]
+                    idx = torch.cat([ip, ineg])
+                    tot += self.train_step(xs[idx].contiguous(), y[idx].contiguous(), lr)
+                    cnt += 1
+            else:
+                perm = torch.randperm(n, generator=g, device=xs.device)
+                for s in range(0, n - batch + 1, batch):
+                    idx = perm[s:s + batch]
+                    tot += self.train_step(xs[idx].contiguous(), y[idx].contiguous(), lr)
+                    cnt += 1
+            hist.append(tot / max(cnt, 1))
+            if log:
+                log(f"epoch {ep}: loss {hist[-1]:.4f}")
+        return hist
+
+
+# ------------------------------------------------------------- simulation
+def run_instance(J, pumps_per_replica, x0, steps, dt, eps, btil, eta, precision, frac=0.1, n_ckpt=N_CKPT,
+                 d=3):
+    """Integrate one instance with feature checkpoints in the first `frac` of
+    the steps.  Returns (features [R, 32], Ising energies [R], gpu ms of the
+    partial phase, gpu ms of the rest, total updates)."""
+    dev = x0.device
+    n, r, _ = x0.shape
+    alpha = torch.from_numpy(synth.anneal_schedule(steps, d)[0]).to(dev)
+    x = x0.clone()
+    k_feat = max(n_ckpt, int(round(frac * steps)))
+    ckpts = [int(round(k_feat * (c + 1) / n_ckpt)) for c in range(n_ckpt)]
+    feats = torch.zeros((r, N_FEAT), dtype=torch.float32, device=dev)
+    prm = dict(eps=eps, btil=btil, eta=eta, dt=dt, precision=precision)
+    ws = None
+    nbytes = api.chym_integrate_workspace_size(J, x, precision=precision)
+    if nbytes:
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    words = api.chym_sign_words(x)
+    k = 0
+    for c, kc in enumerate(ckpts):
+        api.chym_integrate(J, pumps_per_replica, x, alpha, steps=kc - k, start_step=k, workspace=ws, **prm)
+        api.chym_features(J, x, words, feats, c)
+        k = kc
+    e1.record()
+    api.chym_integrate(J, pumps_per_replica, x, alpha, steps=steps - k, start_step=k, workspace=ws, **prm)
+    spins = torch.empty((r, api.spin_words(n)), dtype=torch.int64, device=dev)
+    api.chym_readout(x, spins)
+    e = torch.empty(r, dtype=torch.int32, device=dev)
+    api.chym_ising_energy(J, spins, e)
+    e2.record()
+    torch.cuda.synchronize()
+    return feats, e, e0.elapsed_time(e1), e1.elapsed_time(e2), n * r * d * steps
+
+
+def generate(n_inst, n=200, d=3, n_ic=1000, n_pumps=20, steps=5000, dt=0.01, precision="bf16", seed_base=0,
+             config=5, device="cuda", frac=0.1, log=None):
+    """Simulated trajectories of n_inst SK instances (n_ic initial states x
+    n_pumps pumps each).  Returns per-instance dicts."""
+    dev = torch.device(device)
+    pumps = np.linspace(0.5, 2.0, n_pumps)
+    pr = torch.from_numpy(synth.pump_grid(n_ic, pumps)).to(dev)
+    out = []
+    for i in range(n_inst):
+        Jn = synth.sk_pm1(n, config, seed_base + i)
+        eps = float(np.float32(synth.default_eps(Jn)))
+        J = torch.from_numpy(Jn).to(dev)
+        x0 = synth.initial_states_torch(n, n_ic * n_pumps, d, seed=1000003 * config + seed_base + i, device=dev)
+        f, e, t_part, t_rest, ups = run_instance(J, pr, x0, steps, dt, eps, 1.0, 2e-4, precision, frac=frac, d=d)
+        out.append(dict(index=seed_base + i, J=Jn, feats=f, E=e, t_part_ms=t_part, t_rest_ms=t_rest, updates=ups,
+                        n_ic=n_ic, n_pumps=n_pumps, pumps=pumps))
+        if log:
+            log(f"instance {seed_base + i}: {precision} {t_part + t_rest:.1f} ms, best E {int(e.min().item())}")
+    return out
+
+
+# -------------------------------------------------------------- accounting
+def tts99(cost, p):
+    """Time to 99 % success from cost per attempt and success per attempt."""
+    if p <= 0.0:
+        return math.inf
+    if p >= 0.99:
+        return cost
+    return cost * math.log(0.01) / math.log1p(-p)
+
+
+def auc(scores, labels):
+    """Area under the ROC curve (rank statistic)."""
+    scores = np.asarray(scores, dtype=np.float64)
+    labels = np.asarray(labels, dtype=bool)
+    npos, nneg = labels.sum(), (~labels).sum()
+    if npos == 0 or nneg == 0:
+        return float("nan")
+    order = np.argsort(scores, kind="mergesort")
+    ranks = np.empty(len(scores))
+    ranks[order] = np.arange(1, len(scores) + 1)
+    # average ranks of ties
+    s_sorted = scores[order]
+    i = 0
+    while i < len(s_sorted):
+        j = i
+        while j + 1 < len(s_sorted) and s_sorted[j + 1] == s_sorted[i]:
+            j += 1
+        if j > i:
+            ranks[order[i:j + 1]] = (i + j + 2) / 2.0
+        i = j + 1
+    return float((ranks[labels].sum() - npos * (npos + 1) / 2) / (npos * nneg))
+
+
+def instance_tts(inst, egs, q=None, theta=0.0):
+    """Best-pump TTS99 (ms) of an instance, with the restart policy
+    'keep if q >= theta' when q is given."""
+    e = inst["E"].cpu().numpy()
+    succ = e == egs
+    R = len(e)
+    t_part = inst["t_part_ms"] / R
+    t_full = (inst["t_part_ms"] + inst["t_rest_ms"]) / R
+    best = math.inf
+    n_ic, n_p = inst["n_ic"], inst["n_pumps"]
+    for k in range(n_p):
+        sl = slice(k * n_ic, (k + 1) * n_ic)
+        s = succ[sl]
+        if q is None:
+            t = tts99(t_full, s.mean())
+        else:
+            keep = q[sl] >= theta
+            cost = t_part + keep.mean() * (t_full - t_part)
+            t = tts99(cost, (keep & s).mean())
+        best = min(best, t)
+    return best
+
+
+def evaluate(insts_plain, insts_learned, egs, net, theta):
+    q_all = []
+    rows = []
+    for ip, il, g in zip(insts_plain, insts_learned, egs):
+        q = torch.sigmoid(net.predict_raw(il["feats"])).cpu().numpy()
+        q_all.append(q)
+        rows.append(dict(index=ip["index"], egs=int(g), tts_plain_f32_ms=instance_tts(ip, g),
+                         tts_bf16_ms=instance_tts(il, g), tts_bf16_learned_ms=instance_tts(il, g, q, theta),
+                         p_best_f32=float(max((ip["E"].cpu().numpy() == g)[k * ip["n_ic"]:(k + 1) * ip["n_ic"]].mean()
+                                              for k in range(ip["n_pumps"])))))
+    return rows, q_all
+
+
+def choose_theta(insts, egs, net, grid=None):
+    """Restart threshold minimizing the median best-pump TTS99 on insts."""
+    grid = np.concatenate([[0.0], np.geomspace(1e-4, 0.5, 40)]) if grid is None else grid
+    qs = [torch.sigmoid(net.predict_raw(i["feats"])).cpu().numpy() for i in insts]
+    best = (math.inf, 0.0)
+    for th in grid:
+        med = float(np.median([instance_tts(i, g, q, th) for i, g, q in zip(insts, egs, qs)]))
+        if med < best[0]:
+            best = (med, float(th))
+    return best[1], best[0]
+
+
+def search_egs(Jn, n_rep=20000, d=3, steps=20000, dt=0.01, seed=0, device="cuda"):
+    """Best Ising energy of long BF16 runs (pumps r in [1.0, 2.0]): a
+    stronger putative ground state than the runs under test find."""
+    dev = torch.device(device)
+    n = Jn.shape[0]
+    pumps = np.linspace(1.0, 2.0, 10)
+    pr = torch.from_numpy(synth.pump_grid(n_rep // 10, pumps)).to(dev)
+    x = synth.initial_states_torch(n, pr.shape[0], d, seed=seed, device=dev)
+    al = torch.from_numpy(synth.anneal_schedule(steps, d)[0]).to(dev)
+    out = api.chym_solve(torch.from_numpy(Jn).to(dev), pr, x, al, eps=float(np.float32(synth.default_eps(Jn))),
+                         btil=1.0, eta=2e-4, dt=dt, steps=steps, precision="bf16", want=("spins", "e_ising"))
+    return int(out["e_ising"].min().item())
+
+
+def experiment(n_train=50, n_val=10, n_test=20, n=100, d=3, n_ic=1000, n_pumps=20, steps=5000, epochs=6, seed=0,
+               frac=0.1, pos_frac=0.1, lr=2e-3, search_steps=20000, n_ic_eval=5000, log=print):
+    """Generate, train, evaluate; returns a JSON-able report.
+
+    Training and validation instances are run in the BF16 form; held-out
+    instances in both forms from the same initial states.  The putative
+    ground state of an instance is the best energy of any of its runs,
+    including a longer search (search_steps > 0).  The epoch and the
+    restart threshold are those with the lowest median TTS99 on the
+    validation instances; threshold 0 (never restart, the plain method) is
+    always a candidate.  Validation and held-out instances get n_ic_eval
+    initial states per pump: success is rare enough that a best-pump
+    TTS99 from fewer runs is mostly noise."""
+    t0 = time.time()
+    kw = dict(n=n, d=d, n_ic=n_ic, n_pumps=n_pumps, steps=steps, frac=frac, log=log)
+    train = generate(n_train, precision="bf16", seed_base=0, **kw)
+    kw["n_ic"] = n_ic_eval
+    val = generate(n_val, precision="bf16", seed_base=5_000, **kw)
+    test_bf16 = generate(n_test, precision="bf16", seed_base=10_000, **kw)
+    test_f32 = generate(n_test, precision="f32", seed_base=10_000, **kw)
+
+    def putative(insts, extra=()):
+        out = []
+        for k, i in enumerate(insts):
+            e = int(i["E"].min().item())
+            for o in extra:
+                e = min(e, int(o[k]["E"].min().item()))
+            if search_steps:
+                e = min(e, search_egs(i["J"], d=d, steps=search_steps, seed=7 + i["index"]))
+            out.append(e)
+        return out
+
+    egs_train, egs_val = putative(train), putative(val)
+    egs_test = putative(test_bf16, (test_f32,))
+    feats = torch.cat([i["feats"] for i in train])
+    labels = torch.cat([(i["E"] == g).float() for i, g in zip(train, egs_train)])
+    net = RestartNet(seed=seed)
+    net.set_scaler(feats)
+    xs = net.standardize(feats)
+    t_fit = time.time()
+    hist, val_curve = [], []
+    base_val = float(np.median([instance_tts(i, g) for i, g in zip(val, egs_val)]))
+    best = (base_val, 0.0, -1, net.state())  # never restart
+    for ep in range(epochs):
+        hist += net.fit(xs, labels, epochs=1, lr=lr, pos_frac=pos_frac, seed=seed * 1000 + ep)
+        th, med_val = choose_theta(val, egs_val, net)
+        val_curve.append(dict(epoch=ep, theta=th, tts99_val_ms=med_val))
+        if log:
+            log(f"epoch {ep}: loss {hist[-1]:.4f} val TTS99 {med_val:.4f} ms (theta {th:.4g})")
+        if med_val < best[0]:
+            best = (med_val, th, ep, net.state())
+    net.load_state(best[3])
+    theta = best[1]
+    torch.cuda.synchronize()
+    t_fit = time.time() - t_fit
+    a_train = auc(torch.sigmoid(net.predict_raw(feats)).cpu().numpy(), labels.cpu().numpy() > 0.5)
+    rows, qs = evaluate(test_f32, test_bf16, egs_test, net, theta)
+    lab = np.concatenate([(i["E"].cpu().numpy() == g) for i, g in zip(test_bf16, egs_test)])
+    a = auc(np.concatenate(qs), lab)
+    keep = float(np.mean(np.concatenate(qs) >= theta))
+
+    def med(key):
+        return float(np.median([r[key] for r in rows]))
+
+    upd = sum(i["updates"] for i in test_f32)
+    ms_f32 = sum(i["t_part_ms"] + i["t_rest_ms"] for i in test_f32)
+    ms_bf16 = sum(i["t_part_ms"] + i["t_rest_ms"] for i in test_bf16)
+    report = dict(
+        workload=f"SK +-1 N={n}, D={d}, {n_pumps} pumps, {steps} steps, features over the first {frac:.0%} of "
+                 f"steps; {n_train} training instances x {n_ic} initial states per pump, {n_val} validation and "
+                 f"{n_test} held-out instances x {n_ic_eval}",
+        trajectories_train=int(feats.shape[0]), positives_train=float(labels.mean().item()),
+        positives_heldout_bf16=float(lab.mean()),
+        positives_heldout_f32=float(np.mean(np.concatenate([(i["E"].cpu().numpy() == g)
+                                                            for i, g in zip(test_f32, egs_test)]))),
+        loss_history=hist, validation=val_curve, tts99_val_without_restart_ms=base_val, chosen_epoch=best[2],
+        train_seconds=t_fit, theta=theta, keep_fraction_heldout=keep, auc_train=a_train, auc_heldout=a,
+        tts99_median_ms=dict(plain_f32=med("tts_plain_f32_ms"), bf16=med("tts_bf16_ms"),
+                             bf16_learned=med("tts_bf16_learned_ms")),
+        instances_solved=dict(plain_f32=sum(math.isfinite(r["tts_plain_f32_ms"]) for r in rows),
+                              bf16=sum(math.isfinite(r["tts_bf16_ms"]) for r in rows),
+                              bf16_learned=sum(math.isfinite(r["tts_bf16_learned_ms"]) for r in rows)),
+        updates_per_s=dict(f32=upd / (ms_f32 / 1e3), bf16=upd / (ms_bf16 / 1e3)),
+        per_instance=rows, seconds=time.time() - t0)
+    return report
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=40)
+    ap.add_argument("--val", type=int, default=10)
+    ap.add_argument("--test", type=int, default=20)
+    ap.add_argument("--n", type=int, default=100)
+    ap.add_argument("--d", type=int, default=3)
+    ap.add_argument("--ics", type=int, default=1000)
+    ap.add_argument("--pumps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--epochs", type=int, default=6)
+    ap.add_argument("--frac", type=float, default=0.1)
+    ap.add_argument("--search-steps", type=int, default=20000)
+    ap.add_argument("--out", type=str, default="")
+    a = ap.parse_args()
+    rep = experiment(a.train, a.val, a.test, a.n, a.d, a.ics, a.pumps, a.steps, a.epochs, frac=a.frac,
+                     search_steps=a.search_steps)
+    s = json.dumps(rep, default=float)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(s)
+    print(json.dumps({k: v for k, v in rep.items() if k != "per_instance"}, default=float))
+
+
+if __name__ == "__main__":
+    main()
