@@ -65,17 +65,24 @@ extern "C" {
 #define CHYM_EHIP (-4)         /* a HIP runtime call failed; see chym_last_error() */
 #define CHYM_ENOMEM (-5)       /* caller-provided workspace too small */
 
-/* storage type of the coupling matrix J */
-#define CHYM_J_I8 0  /* int8 integer couplings (e.g. +-1 / 0): contraction and Ising energy exact */
-#define CHYM_J_F32 1 /* float32 couplings (e.g. Gaussian) */
+/* Storage type of the coupling matrix J_N of Eq. (1)-(2), row-major, row p
+ * holding the couplings J_pq that feed hyperspin p. */
+#define CHYM_J_I8 0  /* int8 [n][n] integer couplings (e.g. +-1 / 0): contraction and Ising energy exact */
+#define CHYM_J_F32 1 /* float32 [n][n] couplings (e.g. Gaussian) */
+#define CHYM_J_BF16 2 /* bfloat16 [n][n] (bit patterns as uint16) */
+#define CHYM_J_FP8 3  /* OCP FP8 E4M3 (e4m3fn) [n][n] bytes followed by n OCP E8M0 row-exponent bytes:
+                         J_pq = e4m3(q_pq) * 2^(E_p - 127), n * (n + 1) bytes in all.  Every such value
+                         is exact in bf16 (and float32) as long as it is zero or at least 2^-126 in
+                         magnitude, so the contraction sees the stored J exactly.  E4M3 0x7f / 0xff
+                         and E8M0 0xff decode to NaN.  chym_quantize_fp8() writes this format. */
 
 /* arithmetic of the J x contraction (the state and every other step are float32) */
 #define CHYM_PREC_F32 0  /* x fed to the matrix cores as an exact sum of three bf16 terms
                             (and J as three terms when it is not an integer matrix), float32
                             accumulation: float32-accurate products */
 #define CHYM_PREC_BF16 1 /* x rounded to bf16 (round to nearest even) at the matrix-core
-                            input, J rounded to bf16 (exact for integer |J| <= 256),
-                            float32 accumulation and float32 state */
+                            input, J rounded to bf16 (exact for integer |J| <= 256 and for
+                            CHYM_J_BF16 / CHYM_J_FP8), float32 accumulation and float32 state */
 
 typedef void *chym_stream_t; /* hipStream_t */
 
@@ -85,9 +92,9 @@ typedef void *chym_stream_t; /* hipStream_t */
 typedef struct chym_problem {
     int32_t n;        /* hyperspins N >= 1 */
     int32_t d;        /* components per hyperspin, 1 <= D <= 4 */
-    int32_t j_dtype;  /* CHYM_J_I8 or CHYM_J_F32 */
+    int32_t j_dtype;  /* CHYM_J_I8, CHYM_J_F32, CHYM_J_BF16 or CHYM_J_FP8 */
     int32_t reserved; /* must be 0 */
-    const void *j;    /* device [n][n] */
+    const void *j;    /* device, layout by j_dtype (chym_j_bytes) */
     float eps;        /* coupling strength */
     float btil;       /* nonlocal loss coefficient (1 for the CHYM, 0 for the CIM) */
     float eta;        /* local cubic saturation coefficient */
@@ -334,6 +341,19 @@ int chym_plan_autotune(int32_t n, int32_t d, int32_t precision, int32_t j_dtype,
  * |x| >= 2^-100 (the residual terms are then normal floats; below that they
  * may be flushed to zero, an error of at most 2^-8 |x|).  n must be a
  * multiple of 8; hi, mid and lo 16-byte aligned. */
+/* Bytes of a coupling matrix of n hyperspins stored as j_dtype. */
+int chym_j_bytes(int32_t n, int32_t j_dtype, size_t *bytes);
+
+/* Quantizes a float32 coupling matrix J [n][n] (device) into the CHYM_J_FP8
+ * format at out (device, n * (n + 1) bytes).  Row p gets the exponent
+ * e_p = the least integer with max_q |J_pq| <= 448 * 2^e_p (E_p = e_p + 127;
+ * e_p = 0 for an all-zero row), then q_pq = J_pq / 2^e_p rounded to the
+ * nearest E4M3 value, ties to even (values below the smallest subnormal
+ * round to a signed zero).  A row holding a non-finite value, or whose e_p
+ * falls outside [-127, 127], gets E_p = 0xff (NaN), so runs on it end
+ * flagged as diverged.  Deterministic; no host synchronization. */
+int chym_quantize_fp8(int32_t n, const float *j, uint8_t *out, chym_stream_t stream);
+
 int chym_split3_bf16(const float *x, int64_t n, uint16_t *hi, uint16_t *mid, uint16_t *lo, chym_stream_t stream);
 
 /* Write the plan table to / merge it from a text file (one entry per line:

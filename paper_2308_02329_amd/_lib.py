@@ -18,6 +18,8 @@ ERROR_NAMES = {0: "CHYM_OK", -1: "CHYM_EINVAL", -2: "CHYM_EUNSUPPORTED", -3: "CH
 
 CHYM_J_I8 = 0
 CHYM_J_F32 = 1
+CHYM_J_BF16 = 2
+CHYM_J_FP8 = 3
 CHYM_PREC_F32 = 0
 CHYM_PREC_BF16 = 1
 
@@ -26,7 +28,7 @@ EXPORTS = (
     "chym_version", "chym_last_error", "chym_integrate", "chym_readout", "chym_ising_energy",
     "chym_hs_energy", "chym_solve", "chym_batch_workspace_size", "chym_batch_create",
     "chym_batch_launch", "chym_batch_launch_nograph", "chym_batch_destroy", "chym_plan_set", "chym_plan_get",
-    "chym_plan_autotune_workspace_size", "chym_plan_autotune", "chym_split3_bf16", "chym_plan_save",
+    "chym_plan_autotune_workspace_size", "chym_plan_autotune", "chym_split3_bf16", "chym_j_bytes", "chym_quantize_fp8", "chym_plan_save",
     "chym_plan_load", "chym_integrate_workspace_size", "chym_integrate_ws", "chym_solve_ws",
     "chym_sign_words", "chym_features", "chym_mlp_scratch_floats", "chym_mlp_forward", "chym_mlp_backward",
     "chym_mlp_adam", "chym_to_bf16",
@@ -142,10 +144,12 @@ def _load_plan(lib):
     lib.chym_plan_autotune.argtypes = [_i32, _i32, _i32, _i32, _i32, _i32, _vp, ctypes.c_size_t, P(ChymPlanEntry),
                                        P(ChymPlanEntry), _i32, P(_i32), _vp]
     lib.chym_split3_bf16.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
+    lib.chym_j_bytes.argtypes = [_i32, _i32, P(ctypes.c_size_t)]
+    lib.chym_quantize_fp8.argtypes = [_i32, _vp, _vp, _vp]
     lib.chym_plan_save.argtypes = [ctypes.c_char_p]
     lib.chym_plan_load.argtypes = [ctypes.c_char_p]
     for f in ("chym_plan_set", "chym_plan_get", "chym_plan_autotune_workspace_size", "chym_plan_autotune",
-              "chym_split3_bf16", "chym_plan_save", "chym_plan_load"):
+              "chym_split3_bf16", "chym_plan_save", "chym_plan_load", "chym_j_bytes", "chym_quantize_fp8"):
         getattr(lib, f).restype = ctypes.c_int
 
 

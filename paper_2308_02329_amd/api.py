@@ -12,13 +12,13 @@ import ctypes
 import torch
 
 from . import _lib as L
-from ._lib import (CHYM_J_F32, CHYM_J_I8, CHYM_KERNEL_AUTO, CHYM_KERNEL_LDSJ, CHYM_KERNEL_LDSJ1, CHYM_KERNEL_REGJ,
+from ._lib import (CHYM_J_BF16, CHYM_J_F32, CHYM_J_FP8, CHYM_J_I8, CHYM_KERNEL_AUTO, CHYM_KERNEL_LDSJ, CHYM_KERNEL_LDSJ1, CHYM_KERNEL_REGJ,
                    CHYM_PREC_BF16, CHYM_PREC_F32, ChymError, ChymOut, ChymPlanEntry, ChymProblem, ChymRun)
 
 __all__ = ["chym_sign_words", "chym_features", "chym_mlp_forward", "chym_mlp_backward", "chym_mlp_adam",
            "chym_mlp_scratch_floats", "chym_to_bf16", "chym_integrate_workspace_size", "chym_version", "chym_last_error", "chym_integrate", "chym_readout", "chym_ising_energy",
            "chym_hs_energy", "chym_solve", "make_problem", "make_run", "spin_words", "ChymError",
-           "CHYM_J_I8", "CHYM_J_F32", "CHYM_PREC_F32", "CHYM_PREC_BF16", "precision_code",
+           "CHYM_J_I8", "CHYM_J_F32", "CHYM_J_BF16", "CHYM_J_FP8", "j_size", "chym_j_bytes", "chym_quantize_fp8", "CHYM_PREC_F32", "CHYM_PREC_BF16", "precision_code",
            "chym_batch_workspace_size", "chym_batch_create", "chym_batch_launch", "chym_batch_launch_nograph",
            "chym_batch_destroy", "ChymBatch", "chym_plan_set", "chym_plan_get", "chym_plan_autotune",
            "chym_plan_save", "chym_plan_load", "chym_split3_bf16", "CHYM_KERNEL_REGJ", "CHYM_KERNEL_LDSJ",
@@ -59,16 +59,28 @@ def _need(t, name, dtype, shape=None):
 
 
 def _jdtype(J) -> int:
-    if J.dtype == torch.int8:
-        return CHYM_J_I8
-    if J.dtype == torch.float32:
-        return CHYM_J_F32
-    raise TypeError("J must be int8 or float32")
+    """Storage type of J: int8 [n, n], float32 [n, n], bfloat16 [n, n], or
+    uint8 [n + 1, n] for FP8 (E4M3 rows, then the row of E8M0 exponents)."""
+    t = {torch.int8: CHYM_J_I8, torch.float32: CHYM_J_F32, torch.bfloat16: CHYM_J_BF16,
+         torch.uint8: CHYM_J_FP8}.get(J.dtype)
+    if t is None:
+        raise TypeError("J must be int8, float32, bfloat16 or uint8 (FP8 with row exponents)")
+    return t
+
+
+def j_size(J) -> int:
+    """Hyperspin count n of a coupling tensor in any storage type."""
+    return int(J.shape[1])
+
+
+def _need_j(J, n):
+    shape = (n + 1, n) if J.dtype == torch.uint8 else (n, n)
+    return _need(J, "J", J.dtype, shape)
 
 
 def make_problem(J, d: int, eps: float, btil: float, eta: float) -> ChymProblem:
-    n = J.shape[0]
-    _need(J, "J", J.dtype, (n, n))
+    n = j_size(J)
+    _need_j(J, n)
     return ChymProblem(n=n, d=int(d), j_dtype=_jdtype(J), reserved=0, j=_vp(J), eps=float(eps),
                        btil=float(btil), eta=float(eta), reserved_f=0.0)
 
@@ -151,9 +163,9 @@ def chym_readout(x, spins=None, extra_frac=None, diverged=None, stream=None):
 
 def chym_ising_energy(J, spins, e_i32=None, e_f64=None, stream=None):
     lib = L.load()
-    n = J.shape[0]
+    n = j_size(J)
     r = spins.shape[0]
-    _need(J, "J", J.dtype, (n, n))
+    _need_j(J, n)
     _need(spins, "spins", torch.int64, (r, spin_words(n)))
     if e_i32 is not None:
         _need(e_i32, "e_i32", torch.int32, (r,))
@@ -166,7 +178,7 @@ def chym_ising_energy(J, spins, e_i32=None, e_f64=None, stream=None):
 def chym_hs_energy(J, x, e_hs, stream=None):
     lib = L.load()
     n, r, d = x.shape
-    _need(J, "J", J.dtype, (n, n))
+    _need_j(J, n)
     _need(x, "x", torch.float32)
     _need(e_hs, "e_hs", torch.float64, (r,))
     L.check(lib.chym_hs_energy(n, d, r, _vp(J), _jdtype(J), _vp(x), _vp(e_hs), _stream(stream)),
@@ -297,7 +309,8 @@ def _entry_dict(e: ChymPlanEntry) -> dict:
 
 def _jcode(j_dtype) -> int:
     if isinstance(j_dtype, torch.dtype):
-        return CHYM_J_I8 if j_dtype == torch.int8 else CHYM_J_F32
+        return {torch.int8: CHYM_J_I8, torch.float32: CHYM_J_F32, torch.bfloat16: CHYM_J_BF16,
+                torch.uint8: CHYM_J_FP8}[j_dtype]
     return int(j_dtype)
 
 
@@ -366,7 +379,7 @@ def chym_sign_words(x, words=None, stream=None):
 
 def chym_features(J, x, prev_words, features, checkpoint, stream=None):
     n, r, d = x.shape
-    _need(J, "J", J.dtype, (n, n))
+    _need_j(J, n)
     _need(x, "x", torch.float32)
     _need(prev_words, "prev_words", torch.int64, (r, spin_words(n)))
     _need(features, "features", torch.float32, (r, L.CHYM_FEATURES))
@@ -416,3 +429,22 @@ def chym_to_bf16(src, dst=None, stream=None):
         dst = torch.empty(src.numel(), dtype=torch.int16, device=src.device)
     L.check(L.load().chym_to_bf16(_vp(src), _vp(dst), src.numel(), _stream(stream)), "chym_to_bf16")
     return dst
+
+
+# ------------------------------------------------------------ FP8 couplings
+def chym_j_bytes(n, j_dtype) -> int:
+    b = ctypes.c_size_t(0)
+    L.check(L.load().chym_j_bytes(int(n), int(j_dtype), ctypes.byref(b)), "chym_j_bytes")
+    return int(b.value)
+
+
+def chym_quantize_fp8(J, out=None, stream=None):
+    """float32 J [n, n] (device) -> uint8 [n + 1, n]: E4M3 rows, then the
+    E8M0 row exponents."""
+    n = J.shape[0]
+    _need(J, "J", torch.float32, (n, n))
+    if out is None:
+        out = torch.empty((n + 1, n), dtype=torch.uint8, device=J.device)
+    _need(out, "out", torch.uint8, (n + 1, n))
+    L.check(L.load().chym_quantize_fp8(n, _vp(J), _vp(out), _stream(stream)), "chym_quantize_fp8")
+    return out

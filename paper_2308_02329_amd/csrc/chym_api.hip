@@ -53,12 +53,14 @@ int check_device() {
 
 bool finite(float v) { return isfinite(v); }
 
+bool valid_jdtype(int t) { return t == CHYM_J_I8 || t == CHYM_J_F32 || t == CHYM_J_BF16 || t == CHYM_J_FP8; }
+
 int validate_problem(const chym_problem *p) {
     if (!p) return fail(CHYM_EINVAL, "problem is NULL");
     if (p->n < 1) return fail(CHYM_EINVAL, "n = %d must be >= 1", p->n);
     if (p->d < 1 || p->d > 4) return fail(CHYM_EINVAL, "d = %d must be in 1..4", p->d);
-    if (p->j_dtype != CHYM_J_I8 && p->j_dtype != CHYM_J_F32)
-        return fail(CHYM_EINVAL, "j_dtype = %d is not CHYM_J_I8 or CHYM_J_F32", p->j_dtype);
+    if (!valid_jdtype(p->j_dtype))
+        return fail(CHYM_EINVAL, "j_dtype = %d is not CHYM_J_I8, CHYM_J_F32, CHYM_J_BF16 or CHYM_J_FP8", p->j_dtype);
     if (!p->j) return fail(CHYM_EINVAL, "J is NULL");
     if (p->reserved != 0 || p->reserved_f != 0.0f) return fail(CHYM_EINVAL, "reserved fields must be 0");
     if (!finite(p->eps) || !finite(p->btil) || !finite(p->eta))
@@ -176,7 +178,7 @@ int validate_sizes(int32_t n, int32_t d, int32_t r) {
 int validate_energy(int32_t n, int32_t r, const void *j, int32_t j_dtype, const uint64_t *spins, int32_t *e_i32) {
     if (n < 1 || r < 1) return fail(CHYM_EINVAL, "n and r must be >= 1");
     if (n > 2048) return fail(CHYM_EUNSUPPORTED, "n = %d > 2048", n);
-    if (j_dtype != CHYM_J_I8 && j_dtype != CHYM_J_F32) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
+    if (!valid_jdtype(j_dtype)) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
     if (!j || !spins) return fail(CHYM_EINVAL, "J and spins must not be NULL");
     if (e_i32 && j_dtype != CHYM_J_I8) return fail(CHYM_EINVAL, "int32 energy needs integer J (CHYM_J_I8)");
     return CHYM_OK;
@@ -186,7 +188,7 @@ int validate_hs(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dtype,
     int rc = validate_sizes(n, d, r);
     if (rc) return rc;
     if (n > 2048 || n * d > 8192) return fail(CHYM_EUNSUPPORTED, "hyperspin energy needs n <= 2048, n*d <= 8192");
-    if (j_dtype != CHYM_J_I8 && j_dtype != CHYM_J_F32) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
+    if (!valid_jdtype(j_dtype)) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
     if (!j || !x) return fail(CHYM_EINVAL, "J and x must not be NULL");
     return CHYM_OK;
 }
@@ -237,7 +239,7 @@ int validate_shape(int32_t n, int32_t d, int32_t precision, int32_t j_dtype) {
     if (d < 1 || d > 4) return fail(CHYM_EINVAL, "d = %d must be in 1..4", d);
     if (precision != CHYM_PREC_F32 && precision != CHYM_PREC_BF16)
         return fail(CHYM_EINVAL, "precision = %d is not CHYM_PREC_F32 or CHYM_PREC_BF16", precision);
-    if (j_dtype != CHYM_J_I8 && j_dtype != CHYM_J_F32) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
+    if (!valid_jdtype(j_dtype)) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
     const Variant v = variant_of_shape(n, precision, j_dtype);
     if (v.tiles > chym::resident_tile_limit(d, v.xs, v.js))
         return fail(CHYM_EUNSUPPORTED, "n = %d with d = %d has no launch plans (it runs on the slab integrator)", n,
@@ -811,14 +813,17 @@ int chym_plan_autotune(int32_t n, int32_t d, int32_t precision, int32_t j_dtype,
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     char *ws = static_cast<char *>(workspace);
-    hipError_t e = chym::launch_fill_probe(ws + L.off_j, j_dtype, n, reinterpret_cast<float *>(ws + L.off_pump),
+    // the integrator variant depends on J's storage only through its term count: probe with
+    // float32 J when it is split, else with +-1 int8 J
+    const int probe_jt = (j_dtype == CHYM_J_F32) ? CHYM_J_F32 : CHYM_J_I8;
+    hipError_t e = chym::launch_fill_probe(ws + L.off_j, probe_jt, n, reinterpret_cast<float *>(ws + L.off_pump),
                                            replicas, reinterpret_cast<float *>(ws + L.off_alpha), steps * d, st);
     if (e != hipSuccess) return hip_fail(e, "probe fill");
     chym_task task;
     memset(&task, 0, sizeof task);
     task.prob.n = n;
     task.prob.d = d;
-    task.prob.j_dtype = j_dtype;
+    task.prob.j_dtype = probe_jt;
     task.prob.j = ws + L.off_j;
     task.prob.eps = 0.05f;
     task.prob.btil = 1.0f;
@@ -907,6 +912,30 @@ int chym_plan_autotune(int32_t n, int32_t d, int32_t precision, int32_t j_dtype,
     return chym_plan_get(n, d, precision, j_dtype, best);
 }
 
+int chym_j_bytes(int32_t n, int32_t j_dtype, size_t *bytes) {
+    if (!bytes) return fail(CHYM_EINVAL, "bytes is NULL");
+    if (n < 1) return fail(CHYM_EINVAL, "n = %d must be >= 1", n);
+    if (!valid_jdtype(j_dtype)) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
+    const size_t nn = (size_t)n * n;
+    switch (j_dtype) {
+        case CHYM_J_I8: *bytes = nn; break;
+        case CHYM_J_F32: *bytes = 4 * nn; break;
+        case CHYM_J_BF16: *bytes = 2 * nn; break;
+        default: *bytes = nn + (size_t)n; break;
+    }
+    return CHYM_OK;
+}
+
+int chym_quantize_fp8(int32_t n, const float *j, uint8_t *out, chym_stream_t stream) {
+    if (n < 1) return fail(CHYM_EINVAL, "n = %d must be >= 1", n);
+    if (!j || !out) return fail(CHYM_EINVAL, "j and out must not be NULL");
+    int rc = check_device();
+    if (rc) return rc;
+    hipError_t e = chym::launch_quantize_fp8(n, j, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "quantize launch");
+    return CHYM_OK;
+}
+
 int chym_split3_bf16(const float *x, int64_t n, uint16_t *hi, uint16_t *mid, uint16_t *lo, chym_stream_t stream) {
     if (n < 0 || n % 8) return fail(CHYM_EINVAL, "n = %lld must be a non-negative multiple of 8", (long long)n);
     if (!x || !hi || !mid || !lo) return fail(CHYM_EINVAL, "pointers must not be NULL");
@@ -935,7 +964,7 @@ int chym_features(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dtyp
     int rc = validate_sizes(n, d, r);
     if (rc) return rc;
     if ((long long)n * (d + 1) > 8192) return fail(CHYM_EUNSUPPORTED, "features need n * (d + 1) <= 8192");
-    if (j_dtype != CHYM_J_I8 && j_dtype != CHYM_J_F32) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
+    if (!valid_jdtype(j_dtype)) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
     if (!j || !x || !prev_words || !features) return fail(CHYM_EINVAL, "pointers must not be NULL");
     if (checkpoint < 0 || 4 * checkpoint + 4 > CHYM_FEATURES)
         return fail(CHYM_EINVAL, "checkpoint = %d must be in 0..%d", checkpoint, CHYM_FEATURES / 4 - 1);

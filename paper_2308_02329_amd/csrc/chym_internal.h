@@ -11,6 +11,38 @@ namespace chym {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 
+// Value of an OCP E4M3 (e4m3fn) byte: sign, 4 exponent bits (bias 7), 3
+// mantissa bits; exponent field 0 holds the subnormals m * 2^-9; 0x7f and
+// 0xff are NaN (the format has no infinities).
+__device__ __forceinline__ float e4m3_value(uint32_t b) {
+    const uint32_t mag = b & 0x7fu;
+    float v;
+    if (mag == 0x7fu)
+        v = __builtin_nanf("");
+    else if (mag < 8u)
+        v = (float)mag * 0x1p-9f;
+    else
+        v = __uint_as_float((((mag >> 3) + 120u) << 23) | ((mag & 7u) << 20));
+    return (b & 0x80u) ? -v : v;
+}
+
+// Coupling J_pq of an n x n matrix stored as j_dtype, as float (exact for
+// every storage type but float32 input, where it is the stored value).
+__device__ __forceinline__ float coupling(const void *j, int j_dtype, int n, int p, int q) {
+    const size_t i = (size_t)p * n + q;
+    switch (j_dtype) {
+        case CHYM_J_I8: return (float)reinterpret_cast<const int8_t *>(j)[i];
+        case CHYM_J_F32: return reinterpret_cast<const float *>(j)[i];
+        case CHYM_J_BF16: return __uint_as_float((uint32_t)reinterpret_cast<const uint16_t *>(j)[i] << 16);
+        default: {
+            const uint8_t *b = reinterpret_cast<const uint8_t *>(j);
+            const uint32_t e = b[(size_t)n * n + p];
+            if (e == 0xffu) return __builtin_nanf("");
+            return ldexpf(e4m3_value(b[i]), (int)e - 127);
+        }
+    }
+}
+
 // Largest row-tile count (16 rows per tile) of the register-resident
 // integrator for d components, xs state terms and js J terms (0 if none).
 int resident_tile_limit(int d, int xs, int js);
@@ -39,6 +71,7 @@ constexpr int kKernelLdsJ1 = 2;  // one wavefront per SIMD
 hipError_t persistent_occupancy(int tiles, int d, int xs, int js, int kind, int waves_per_block, int *blocks_per_cu);
 hipError_t launch_zero_counters(int *counters, int n, hipStream_t stream);
 // Synthetic timing problem for the autotuner.
+hipError_t launch_quantize_fp8(int n, const float *j, uint8_t *out, hipStream_t stream);
 hipError_t launch_fill_probe(void *j, int j_dtype, int n, float *pump, int r, float *alpha, int na,
                              hipStream_t stream);
 hipError_t launch_fill_state(float *x, size_t nx, hipStream_t stream);

@@ -55,8 +55,7 @@ __global__ __launch_bounds__(64) void k_features(int n, int d, int r, const void
     for (int q = lane; q < n; q += 64) {
         double hh = 0.0, hi = 0.0;
         for (int p = 0; p < n; ++p) {
-            const double jv = (j_dtype == CHYM_J_I8) ? (double)reinterpret_cast<const int8_t *>(j)[(size_t)p * n + q]
-                                                     : (double)reinterpret_cast<const float *>(j)[(size_t)p * n + q];
+            const double jv = (double)coupling(j, j_dtype, n, p, q);
             double dot = 0.0;
             for (int mu = 0; mu < d; ++mu) dot = dot + u[p * d + mu] * u[q * d + mu];
             hh = hh + jv * dot;

@@ -107,8 +107,7 @@ __device__ __forceinline__ void split8(const float (&v)[8], XSplit<XS> &out, con
 // Loads one coupling value as float (0 outside the n x n matrix).
 __device__ __forceinline__ float j_at(const IntegArgs &a, int p, int q) {
     if (p >= a.n || q >= a.n) return 0.0f;
-    return (a.j_dtype == CHYM_J_I8) ? (float)reinterpret_cast<const int8_t *>(a.j)[(size_t)p * a.n + q]
-                                    : reinterpret_cast<const float *>(a.j)[(size_t)p * a.n + q];
+    return coupling(a.j, a.j_dtype, a.n, p, q);
 }
 
 // A fragment (I, c) for lane (i, g): slot s holds

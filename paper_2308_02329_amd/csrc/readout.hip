@@ -60,7 +60,7 @@ __device__ __forceinline__ int spin_of(const uint64_t *s, int p) {
 // Ising energy of one replica by one wavefront:
 // E = -sum_q sigma_q sum_p J_pq sigma_p.  Lanes own columns q (coalesced
 // reads of each row of J); the sigma_p are uniform across the wave.  Integer
-// J: exact int32; float J: float64.
+// J: exact int32; other J: float64 of the stored values.
 __device__ void ising_one(int n, int rep, const void *__restrict__ j, int j_dtype, const uint64_t *__restrict__ spins,
                           int32_t *__restrict__ e_i32, double *__restrict__ e_f64) {
     const int lane = threadIdx.x & 63;
@@ -80,11 +80,10 @@ __device__ void ising_one(int n, int rep, const void *__restrict__ j, int j_dtyp
             if (e_f64) e_f64[rep] = -(double)acc;
         }
     } else {
-        const float *J = reinterpret_cast<const float *>(j);
         double acc = 0.0;
         for (int q = lane; q < n; q += 64) {
             double h = 0.0;
-            for (int p = 0; p < n; ++p) h += (double)J[(size_t)p * n + q] * (double)spin_of(s, p);
+            for (int p = 0; p < n; ++p) h += (double)coupling(j, j_dtype, n, p, q) * (double)spin_of(s, p);
             acc += (double)spin_of(s, q) * h;
         }
         acc = wave_sum(acc);
@@ -126,8 +125,7 @@ __device__ void hs_one(int n, int d, int r, int rep, const void *__restrict__ j,
         for (int p = 0; p < n; ++p) {
             double dot = 0.0;
             for (int mu = 0; mu < d; ++mu) dot = dot + u[p * d + mu] * u[q * d + mu];
-            const double jv = (j_dtype == CHYM_J_I8) ? (double)reinterpret_cast<const int8_t *>(j)[(size_t)p * n + q]
-                                                     : (double)reinterpret_cast<const float *>(j)[(size_t)p * n + q];
+            const double jv = (double)coupling(j, j_dtype, n, p, q);
             h = h + jv * dot;
         }
         acc += h;
