@@ -53,6 +53,10 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1, help="0 disables the oracle timing leg")
     ap.add_argument("--cpu-replicas", type=int, default=2000)
     ap.add_argument("--tts", type=int, default=1, help="0 skips the time-to-99%%-ground-state comparison")
+    ap.add_argument("--workload", type=str, default="sk100", choices=["sk100", "precision", "batched"],
+                    help="sk100: the default throughput workload; precision: N=1000, D=4, 4096 replicas, "
+                         "10000 steps with +-1, bf16 Gaussian and FP8 Gaussian couplings; batched: 10000 "
+                         "solves of mixed N, D and graph family in one graph launch")
     return ap.parse_args()
 
 
@@ -138,6 +142,169 @@ def tts_leg():
     return out
 
 
+def lambda_max_power(J, iters=200):
+    """Largest eigenvalue of a symmetric matrix by power iteration on the
+    shifted matrix J + s I (host, float64); sets the run input eps only."""
+    J = J.astype(np.float64)
+    s = np.abs(J).sum(axis=1).max()  # Gershgorin: J + s I is positive semidefinite
+    v = np.random.default_rng(0).standard_normal(J.shape[0])
+    lam = 0.0
+    for _ in range(iters):
+        w = J @ v + s * v
+        lam = float(np.linalg.norm(w))
+        v = w / lam
+    return lam - s
+
+
+def timed_events(torch, stream, fn, reps):
+    """Runs fn reps times between HIP events on stream; returns ms per call."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def run_precision(args, torch, api, synth):
+    """N = 1000, D = 4, 16 pumps x 256 initial states = 4096 replicas, 10000
+    steps, BF16 form, three couplings: SK +-1 (int8, exact), Gaussian rounded
+    to bf16, Gaussian in FP8 (E4M3 + E8M0 row exponents)."""
+    dev = torch.device("cuda:0")
+    n, d, steps = 1000, 4, args.euler_steps if args.euler_steps != 5000 else 10000
+    R = 4096
+    pumps = torch.from_numpy(synth.pump_grid(256, np.linspace(0.5, 2.0, 16))).to(dev)
+    alpha = torch.from_numpy(synth.anneal_schedule(steps, d)[0]).to(dev)
+    sk = synth.sk_pm1(n, 3, 0)
+    ga = synth.gaussian_j(n, 3, 1).astype(np.float32)
+    Js = {"sk_pm1_int8": torch.from_numpy(sk).to(dev),
+          "gauss_bf16": torch.from_numpy(ga).to(dev).to(torch.bfloat16),
+          "gauss_fp8": api.chym_quantize_fp8(torch.from_numpy(ga).to(dev))}
+    eps = {"sk_pm1_int8": 0.5 / lambda_max_power(sk), "gauss_bf16": 0.5 / lambda_max_power(ga)}
+    eps["gauss_fp8"] = eps["gauss_bf16"]
+    x0 = synth.initial_states_torch(n, R, d, seed=2308023293, device=dev)
+    x = torch.empty_like(x0)
+    ws = torch.empty(api.chym_integrate_workspace_size(Js["sk_pm1_int8"], x, precision="bf16") + 256,
+                     dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    res_kind = {}
+
+    def run(kind):
+        api.chym_integrate(Js[kind], pumps, x, alpha, eps=float(eps[kind]), btil=1.0, eta=2e-4, dt=args.dt,
+                           steps=steps, precision="bf16", workspace=ws)
+
+    for kind in Js:
+        x.copy_(x0)
+        run(kind)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for kind in Js:
+            x.copy_(x0)
+            res_kind[kind] = res_kind.get(kind, 0.0) + timed_events(torch, stream, lambda: run(kind), 1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    res_kind = {k: v / args.steps for k, v in res_kind.items()}
+    upd = n * R * d * steps * len(Js)
+    ms_sk = res_kind["sk_pm1_int8"]
+    flops = n * R * d * steps * 2.0 * (n - 1)
+    achieved = flops / (ms_sk / 1e3) / 1e12
+    return {"metric": METRIC, "value": upd / (wall / args.steps), "unit": "spin-component updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": f"N={n} D={d}, 16 pumps x 256 initial states = {R} replicas, {steps} Euler steps, "
+                                   f"bf16 form; couplings SK +-1 int8, Gaussian bf16, Gaussian FP8 E4M3+E8M0",
+                       "n": n, "d": d, "replicas": R, "euler_steps": steps, "precision": "bf16"},
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                         "kernel": "k_integrate_slab<4, 1, 1, 8, 8> (SK +-1 J, E4M3 stream)", "kernel_ms": ms_sk},
+            "integrate_ms": res_kind}
+
+
+def run_batched(args, torch, api, synth):
+    """10000 solves in one graph launch: N uniform in {50, 100, 200, 400,
+    800}, D uniform in {2, 3, 4}, SK +-1 or 3-regular +-1 (half each), one
+    pump r ~ U[0.5, 2] per solve, 32 initial states, 5000 steps, BF16 form,
+    plans autotuned per resident (N, D) bucket."""
+    dev = torch.device("cuda:0")
+    g = np.random.default_rng(2308023294)
+    n_solves, reps, steps = args.instances if args.instances != 1000 else 10000, 32, args.euler_steps
+    Ns = g.choice([50, 100, 200, 400, 800], n_solves)
+    Ds = g.choice([2, 3, 4], n_solves)
+    fam = g.random(n_solves) < 0.5
+    hs = g.uniform(0.5, 2.0, n_solves).astype(np.float32)
+    tuned = {}
+    for nn in (50, 100, 200, 400, 800):
+        for dd in (2, 3, 4):
+            try:
+                tuned[f"{nn}/{dd}"] = api.chym_plan_autotune(int(nn), int(dd), "bf16", torch.int8, steps=200)[0]
+            except api.ChymError:
+                tuned[f"{nn}/{dd}"] = "streamed-J (no plan)"
+    jsz = [int(nn) * int(nn) for nn in Ns]
+    xsz = [int(nn) * reps * int(dd) for nn, dd in zip(Ns, Ds)]
+    Jh = np.empty(sum(jsz), dtype=np.int8)
+    eps = np.empty(n_solves)
+    off = 0
+    flops = 0.0
+    for i in range(n_solves):
+        nn = int(Ns[i])
+        J = synth.regular3_pm1(nn, 4, i) if fam[i] else synth.sk_pm1(nn, 4, i)
+        Jh[off:off + nn * nn] = J.ravel()
+        eps[i] = 0.5 / lambda_max_power(J, 100)
+        off += nn * nn
+        flops += nn * reps * int(Ds[i]) * steps * (6.0 if fam[i] else 2.0 * (nn - 1))
+    Jd = torch.from_numpy(Jh).to(dev)
+    x0 = synth.initial_states_torch(sum(xsz), 1, 1, seed=2308023294, device=dev).view(-1)
+    x = torch.empty_like(x0)
+    alphas = {dd: torch.from_numpy(synth.anneal_schedule(steps, dd)[0]).to(dev) for dd in (2, 3, 4)}
+    pump_all = torch.from_numpy(np.repeat(hs, reps)).to(dev)
+    tasks = []
+    joff = xoff = 0
+    for i in range(n_solves):
+        nn, dd = int(Ns[i]), int(Ds[i])
+        tasks.append(dict(J=Jd[joff:joff + nn * nn].view(nn, nn), pump=pump_all[i * reps:(i + 1) * reps],
+                          x=x[xoff:xoff + nn * reps * dd].view(nn, reps, dd), alpha=alphas[dd], eps=float(eps[i]),
+                          btil=1.0, eta=2e-4, dt=args.dt, steps=steps, precision="bf16",
+                          spins=torch.empty((reps, api.spin_words(nn)), dtype=torch.int64, device=dev),
+                          e_ising=torch.empty(reps, dtype=torch.int32, device=dev)))
+        joff += nn * nn
+        xoff += nn * reps * dd
+    t_setup = time.perf_counter()
+    plan = api.chym_batch_create(tasks)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    stream = torch.cuda.current_stream()
+
+    def one():
+        x.copy_(x0)
+        plan.launch()
+
+    one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = 0.0
+    for _ in range(args.steps):
+        ms += timed_events(torch, stream, one, 1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    upd = float(sum(int(nn) * reps * int(dd) * steps for nn, dd in zip(Ns, Ds)))
+    achieved = flops / (ms / args.steps / 1e3) / 1e12
+    plan.destroy()
+    return {"metric": METRIC, "value": upd / (wall / args.steps), "unit": "spin-component updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": f"{n_solves} solves in one graph launch: N in {{50,100,200,400,800}}, D in {{2,3,4}}, "
+                                   f"SK or 3-regular +-1, one pump per solve, {reps} initial states, {steps} steps, "
+                                   f"bf16 form", "solves": n_solves, "replicas_per_solve": reps,
+                       "euler_steps": steps, "precision": "bf16"},
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                         "kernel": "whole batch launch (algorithmic flops: 2(N-1) per SK update, 6 per 3-regular)",
+                         "kernel_ms": ms / args.steps},
+            "setup_s": t_setup, "plans": tuned}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -145,6 +312,14 @@ def main():
                           "n_gpus_requested": args.gpus}))
         sys.exit(2)
     import torch
+
+    if args.workload != "sk100":
+        from paper_2308_02329_amd import api, synth
+
+        torch.cuda.set_device(0)
+        fn = run_precision if args.workload == "precision" else run_batched
+        print(json.dumps(fn(args, torch, api, synth), default=str), flush=True)
+        return
 
     from paper_2308_02329_amd import api, synth
 

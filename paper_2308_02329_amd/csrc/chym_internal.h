@@ -26,6 +26,44 @@ __device__ __forceinline__ float e4m3_value(uint32_t b) {
     return (b & 0x80u) ? -v : v;
 }
 
+// Nearest E4M3 code of a (|a| <= 448 assumed), ties to even; sign from the
+// float's sign bit.
+__device__ __forceinline__ uint32_t e4m3_code(float v) {
+    const uint32_t bits = __float_as_uint(v);
+    const uint32_t sign = (bits >> 24) & 0x80u;
+    const float a = fabsf(v);
+    uint32_t code;
+    if (a < 0x1p-6f) {
+        // subnormal spacing 2^-9; a * 512 is exact, rintf rounds to even
+        code = (uint32_t)rintf(a * 512.0f);  // 8 is the smallest normal, 0x08
+    } else {
+        const uint32_t ab = __float_as_uint(a);
+        int e = (int)(ab >> 23) - 127;
+        const uint32_t mant = ab & 0x7fffffu;
+        uint32_t m3 = mant >> 20;
+        const uint32_t rest = mant & 0xfffffu;
+        if (rest > 0x80000u || (rest == 0x80000u && (m3 & 1u))) ++m3;
+        if (m3 == 8u) {
+            m3 = 0u;
+            ++e;
+        }
+        code = ((uint32_t)(e + 7) << 3) | m3;
+    }
+    return sign | code;
+}
+
+// Least e with amax <= 448 * 2^e (0 for amax = 0): the power-of-two row
+// scale that puts a row's largest magnitude at the top E4M3 binade.
+__device__ __forceinline__ int e4m3_row_exponent(float amax) {
+    if (!(amax > 0.0f)) return 0;
+    int k;
+    frexpf(amax, &k);  // amax = f 2^k, f in [0.5, 1)
+    int e = k - 9;     // 448 * 2^(k - 9) = 0.875 * 2^k: the answer is e or e + 1
+    if (amax > ldexpf(448.0f, e)) ++e;
+    if (amax <= ldexpf(448.0f, e - 1)) --e;
+    return e;
+}
+
 // Coupling J_pq of an n x n matrix stored as j_dtype, as float (exact for
 // every storage type but float32 input, where it is the stored value).
 __device__ __forceinline__ float coupling(const void *j, int j_dtype, int n, int p, int q) {

@@ -21,19 +21,28 @@ int resident_tile_limit(int d, int xs, int js) {
 }
 
 // ------------------------------------------------------------ slab kernels
-static SlabKernels lookup_slab(int tpw, int d, int xs, int js) {
+static SlabKernels lookup_slab_shape(int tpw, int waves, int d, int xs, int js) {
 #define CHYM_PICK(D, XS, JS) \
-    if (d == D && xs == XS && js == JS) return lookup_slab_##D##_##XS##_##JS(tpw);
+    if (d == D && xs == XS && js == JS) return lookup_slab_##D##_##XS##_##JS(tpw, waves);
     CHYM_PICK(1, 3, 1) CHYM_PICK(1, 1, 1) CHYM_PICK(1, 3, 3)
     CHYM_PICK(2, 3, 1) CHYM_PICK(2, 1, 1) CHYM_PICK(2, 3, 3)
     CHYM_PICK(3, 3, 1) CHYM_PICK(3, 1, 1) CHYM_PICK(3, 3, 3)
     CHYM_PICK(4, 3, 1) CHYM_PICK(4, 1, 1) CHYM_PICK(4, 3, 3)
 #undef CHYM_PICK
-    return SlabKernels{nullptr, nullptr};
+    return SlabKernels{nullptr, nullptr, 0};
+}
+
+// Block shape of the slab kernel for a tile count: eight wavefronts with 4
+// or 8 tiles each, up to 64 tiles.
+static SlabKernels lookup_slab(int tiles, int d, int xs, int js) {
+    const int per = (tiles + 7) / 8;
+    const int tpw = (per + 3) / 4 * 4;
+    if (tpw > 8) return SlabKernels{nullptr, nullptr, 0};
+    return lookup_slab_shape(tpw, 8, d, xs, js);
 }
 
 int slab_tpw_for(int tiles) {
-    const int per = (tiles + kSlabWaves - 1) / kSlabWaves;
+    const int per = (tiles + 7) / 8;
     const int tpw = (per + 3) / 4 * 4;
     return tpw <= 8 ? tpw : 0;
 }
@@ -41,12 +50,59 @@ int slab_tpw_for(int tiles) {
 size_t slab_lds_bytes(int tiles, int d, int xs) { return (size_t)((tiles + 1) / 2) * d * xs * 64 * sizeof(bf16x8); }
 
 size_t slab_jfrag_bytes(int tiles, int js) {
-    return (size_t)tiles * ((tiles + 1) / 2) * js * 64 * sizeof(bf16x8);
+    return stage_frag_offset(tiles) + (size_t)tiles * ((tiles + 1) / 2) * js * 64 * sizeof(bf16x8);
 }
 
 bool slab_variant_exists(int tiles, int d, int xs, int js) {
-    const int tpw = slab_tpw_for(tiles);
-    return tpw > 0 && slab_lds_bytes(tiles, d, xs) <= kSlabMaxLds && lookup_slab(tpw, d, xs, js).single != nullptr;
+    return slab_lds_bytes(tiles, d, xs) <= kSlabMaxLds && lookup_slab(tiles, d, xs, js).single != nullptr;
+}
+
+// Decides whether the couplings can be staged as E4M3 bytes: every row must
+// be a set of E4M3 values times one power of two (the row scale, chosen as
+// in the FP8 quantizer), checked element by element; FP8 storage always
+// qualifies.  Writes the header flag and the row scales.  One block of 1024
+// threads: wavefront w takes rows w, w + 16, ...
+__global__ __launch_bounds__(1024) void k_stage_prep(IntegArgs a, int tiles, unsigned char *__restrict__ stage) {
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) s_ok = 1;
+    __syncthreads();
+    float *scale = reinterpret_cast<float *>(stage + kStageHeader);
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int n = a.n;
+    bool ok = true;
+    for (int p = w; p < tiles * 16; p += 16) {
+        float sc = 1.0f;
+        if (p < n) {
+            if (a.j_dtype == CHYM_J_FP8) {
+                const uint32_t e = reinterpret_cast<const uint8_t *>(a.j)[(size_t)n * n + p];
+                sc = e == 0xffu ? __builtin_nanf("") : ldexpf(1.0f, (int)e - 127);
+            } else {
+                float amax = 0.0f;
+                bool fin = true;
+                for (int q = lane; q < n; q += 64) {
+                    const float v = coupling(a.j, a.j_dtype, n, p, q);
+                    fin = fin && __builtin_isfinite(v);
+                    amax = fmaxf(amax, fabsf(v));
+                }
+                for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+                const int e = e4m3_row_exponent(amax);
+                if (!__all(fin) || e < -126 || e > 127) {
+                    ok = false;
+                } else {
+                    sc = ldexpf(1.0f, e);
+                    for (int q = lane; q < n; q += 64) {
+                        const float v = coupling(a.j, a.j_dtype, n, p, q);
+                        if (ldexpf(e4m3_value(e4m3_code(ldexpf(v, -e))), e) != v) ok = false;
+                    }
+                }
+            }
+        }
+        if (lane == 0) scale[p] = sc;
+    }
+    if (!ok) atomicAnd(&s_ok, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) *reinterpret_cast<int *>(stage) = (a.j_dtype == CHYM_J_FP8) ? 1 : s_ok;
 }
 
 hipError_t launch_stage_jfrag(const IntegArgs &a, int js, void *out, hipStream_t stream) {
@@ -54,10 +110,13 @@ hipError_t launch_stage_jfrag(const IntegArgs &a, int js, void *out, hipStream_t
     const int ncp = (nt + 1) / 2;
     const int total = nt * ncp * 64;
     const int grid = (total + 255) / 256;
-    if (js == 3)
-        hipLaunchKernelGGL(k_stage_jfrag<3>, dim3(grid), dim3(256), 0, stream, a, ncp, reinterpret_cast<bf16x8 *>(out));
-    else
-        hipLaunchKernelGGL(k_stage_jfrag<1>, dim3(grid), dim3(256), 0, stream, a, ncp, reinterpret_cast<bf16x8 *>(out));
+    unsigned char *stage = reinterpret_cast<unsigned char *>(out);
+    if (js == 3) {
+        hipLaunchKernelGGL(k_stage_jfrag<3>, dim3(grid), dim3(256), 0, stream, a, ncp, stage);
+    } else {
+        hipLaunchKernelGGL(k_stage_prep, dim3(1), dim3(1024), 0, stream, a, nt, stage);
+        hipLaunchKernelGGL(k_stage_jfrag<1>, dim3(grid), dim3(256), 0, stream, a, ncp, stage);
+    }
     return hipGetLastError();
 }
 
@@ -68,37 +127,36 @@ static hipError_t slab_prepare(const void *fn, size_t lds) {
 
 hipError_t launch_integrate_slab(int tiles, int d, int xs, int js, const IntegArgs &a, const void *jfrag,
                                  hipStream_t stream) {
-    const int tpw = slab_tpw_for(tiles);
-    SlabKernels k = lookup_slab(tpw, d, xs, js);
+    SlabKernels k = lookup_slab(tiles, d, xs, js);
     if (!k.single) return hipErrorInvalidDeviceFunction;
     const size_t lds = slab_lds_bytes(tiles, d, xs);
     hipError_t e = slab_prepare(reinterpret_cast<const void *>(k.single), lds);
     if (e != hipSuccess) return e;
     const int blocks = (a.r + 15) / 16;
-    hipLaunchKernelGGL(k.single, dim3(blocks), dim3(64 * kSlabWaves), lds, stream, a,
-                       reinterpret_cast<const bf16x8 *>(jfrag),
+    hipLaunchKernelGGL(k.single, dim3(blocks), dim3(64 * k.waves), lds, stream, a,
+                       reinterpret_cast<const unsigned char *>(jfrag),
                        (tiles + 1) / 2);
     return hipGetLastError();
 }
 
 hipError_t slab_occupancy(int tiles, int d, int xs, int js, size_t lds, int *blocks_per_cu) {
     *blocks_per_cu = 0;
-    SlabKernels k = lookup_slab(slab_tpw_for(tiles), d, xs, js);
+    SlabKernels k = lookup_slab(tiles, d, xs, js);
     if (!k.persistent) return hipErrorInvalidDeviceFunction;
     hipError_t e = slab_prepare(reinterpret_cast<const void *>(k.persistent), lds);
     if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k.persistent, 64 * kSlabWaves, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k.persistent, 64 * k.waves, lds);
 }
 
 hipError_t launch_integrate_slab_persistent(int tiles, int d, int xs, int js, size_t lds, int blocks,
                                             const IntegArgs *tasks, const int2 *items, int n_items, int *counter,
                                             const void *const *jfs, const int *ncps, hipStream_t stream) {
-    SlabKernels k = lookup_slab(slab_tpw_for(tiles), d, xs, js);
+    SlabKernels k = lookup_slab(tiles, d, xs, js);
     if (!k.persistent) return hipErrorInvalidDeviceFunction;
     hipError_t e = slab_prepare(reinterpret_cast<const void *>(k.persistent), lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k.persistent, dim3(blocks), dim3(64 * kSlabWaves), lds, stream, tasks, items, n_items, counter,
-                       reinterpret_cast<const bf16x8 *const *>(jfs), ncps);
+    hipLaunchKernelGGL(k.persistent, dim3(blocks), dim3(64 * k.waves), lds, stream, tasks, items, n_items, counter,
+                       reinterpret_cast<const unsigned char *const *>(jfs), ncps);
     return hipGetLastError();
 }
 

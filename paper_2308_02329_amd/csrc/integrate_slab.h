@@ -1,9 +1,9 @@
 // Streamed-J CHYM integrator for large N (gfx950).
 //
-// One block of eight wavefronts (two per SIMD) owns a column slab -- 16
-// replicas x D components of one problem -- for the whole run.  Row tiles (16
-// rows) are dealt to the wavefronts round-robin: wavefront w owns tiles w,
-// w+8, ...,
+// One block of W wavefronts (eight: two per SIMD, or four: one per SIMD with
+// twice the registers) owns a column slab -- 16 replicas x D components of
+// one problem -- for the whole run.  Row tiles (16 rows) are dealt to the
+// wavefronts round-robin: wavefront w owns tiles w, w+W, ...,
 // whose float32 state lives in its registers in the 16x16 MFMA accumulator
 // layout (lane j + 16 g holds rows 16 I + 4 g + v of replica j).
 //
@@ -17,19 +17,60 @@
 // kernel, so the two kernels accumulate every G in the same order and give
 // identical results.  J is staged once per problem into the caller's
 // workspace as A fragments in that order and is streamed from L2 every step
-// (at this size it does not fit in LDS).
+// (at this size it does not fit in LDS).  When every row of J is a set of
+// E4M3 values times one power of two (+-1 couplings in any storage, FP8
+// storage always), J is staged as one byte per coupling and widened to bf16
+// in registers (v_cvt_scalef32_pk_bf16_fp8, exact); this halves the L2
+// traffic, which is what bounds the kernel at N ~ 1000.
 //
 // Per step: for each group of four owned tiles, accumulate G over all
 // chunks (the J fragments of the next chunk are fetched while the current
 // chunk's matrix-core work runs), then apply the fused Euler update to those
 // tiles in registers; after a barrier every wavefront writes its tiles' new
 // operand terms to LDS, and a second barrier publishes them.
-constexpr int kSlabWaves = 8;
 #pragma once
 
 #include "integrate_kernel.h"
 
 namespace chym {
+
+// Staged couplings of one problem (caller workspace, 256-byte aligned):
+//   [0, 256)           header: int32, 1 if the fragments are E4M3 bytes
+//   [256, 256 + S)     float row scales 2^e_p [tiles * 16] (E4M3 fragments)
+//   [256 + S, ...)     fragments: bf16 [tile][chunk][JS][64 lanes] x 16 B, or
+//                      E4M3 [tile][chunk][64 lanes] x 8 B
+constexpr size_t kStageHeader = 256;
+__host__ __device__ inline size_t stage_scale_bytes(int tiles) { return ((size_t)tiles * 64 + 255) / 256 * 256; }
+__host__ __device__ inline size_t stage_frag_offset(int tiles) { return kStageHeader + stage_scale_bytes(tiles); }
+
+// Buffer resource over n bytes at p (raw, 32-bit data format): loads through
+// it take a per-lane offset and a wave-uniform offset, and return 0 past n.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_over(const void *p, uint32_t n) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)n, 0x00020000);
+}
+
+__device__ __forceinline__ bf16x8 load_frag16(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    typedef __attribute__((ext_vector_type(4))) int i4;
+    const i4 v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+__device__ __forceinline__ uint2 load_frag8(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    typedef __attribute__((ext_vector_type(2))) int i2;
+    const i2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return uint2{(uint32_t)v.x, (uint32_t)v.y};
+}
+
+// Eight E4M3 codes (slots 0..7 in byte order) times a power of two, as bf16.
+__device__ __forceinline__ bf16x8 fp8_fragment(uint2 w, float scale) {
+    const bf16x2 a = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w.x, scale, false);
+    const bf16x2 b = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w.x, scale, true);
+    const bf16x2 c = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w.y, scale, false);
+    const bf16x2 d = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w.y, scale, true);
+    const auto ab = __builtin_shufflevector(a, b, 0, 1, 2, 3);
+    const auto cd = __builtin_shufflevector(c, d, 0, 1, 2, 3);
+    return __builtin_shufflevector(ab, cd, 0, 1, 2, 3, 4, 5, 6, 7);
+}
 
 // LDS operand layout: [chunk][component][term][64 lanes] of bf16x8 (1 KB each).
 __device__ __forceinline__ int slab_b_index(int c, int mu, int t, int lane, int D, int XS) {
@@ -66,25 +107,39 @@ __device__ __forceinline__ void slab_write_tile(const float (&xt)[D][4], int I, 
     }
 }
 
-// Integrates the column slab rep0 .. rep0+15 of problem a.  jf: staged A
-// fragments [tile][chunk][JS][64]; ncp: chunk count of the staging; lb: LDS
-// operand area of ncp * D * XS fragments.  Called by all kSlabWaves
-// wavefronts of the block; contains block barriers.
-template <int D, int XS, int JS, int TPW>
-__device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, const bf16x8 *__restrict__ jf, int ncp,
-                                               bf16x8 *lb) {
-    constexpr int GS = D >= 3 ? 2 : 4;  // tiles accumulated together (register budget)
+// Integrates the column slab rep0 .. rep0+15 of problem a.  stage: the
+// staged couplings (layout above); F8: its fragments are E4M3 bytes; ncp:
+// chunk count of the staging; lb: LDS operand area of ncp * D * XS
+// fragments.  Called by all W wavefronts of the block; contains block
+// barriers.
+template <int D, int XS, int JS, int TPW, bool F8, int W>
+__device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, const unsigned char *__restrict__ stage,
+                                               int ncp, bf16x8 *lb) {
+    // tiles accumulated together (register budget: 256 per lane at two
+    // wavefronts per SIMD, 512 at one)
+    constexpr int GS = W == 8 ? (D >= 3 ? 2 : 4) : (D >= 3 ? 4 : 8);
+    constexpr int RD = 2;  // chunks of J fragments in flight (more spills at D = 4)
     constexpr int NG = TPW / GS;        // groups of owned tiles
     const int n = a.n;
     const int r = a.r;
     const int nt = (n + 15) / 16;
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    // wave-uniform: tile and chunk offsets stay in scalar registers
+    const int w0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int w = w0;
     const int jcol = lane & 15;
     const int g = lane >> 4;
     const int rep = rep0 + jcol;
     const bool valid = rep < r;
     const NegPair negk = neg_pair();
+    // J fragments through a buffer resource: per-lane offset lane * bytes,
+    // wave-uniform offset of (tile, chunk, term) in scalar registers
+    constexpr int FB = F8 ? 8 : 16;                // bytes per lane per fragment
+    constexpr int CHB = (F8 ? 1 : JS) * 64 * FB;   // bytes per (tile, chunk)
+    const __amdgpu_buffer_rsrc_t jres = buffer_over(stage + stage_frag_offset(nt), (uint32_t)(nt * ncp * CHB));
+    const int jvoff = lane * FB;
+    // row scales 2^e_p of the E4M3 fragments (per-lane offset jcol, tile offset uniform)
+    const __amdgpu_buffer_rsrc_t sres = buffer_over(stage + kStageHeader, (uint32_t)(nt * 64));
 
     // zero the operand area (chunks past the last tile read as zero)
     for (int i = threadIdx.x; i < ncp * D * XS * 64; i += blockDim.x) lb[i] = bf16x8{};
@@ -93,7 +148,7 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
     float x[TPW][D][4];
 #pragma unroll
     for (int k = 0; k < TPW; ++k) {
-        const int I = w + kSlabWaves * k;
+        const int I = w + W * k;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int p = 16 * I + 4 * g + v;
@@ -114,6 +169,10 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
     constexpr int px[6] = {JS == 1 ? XS - 1 : 0, JS == 1 ? (XS > 1 ? XS - 2 : 0) : 1, JS == 1 ? 0 : 2, 0, 1, 0};
 
     for (int k = 0; k < a.steps; ++k) {
+        // tile offsets are cheap scalar arithmetic: form them again every step
+        // instead of keeping them live in registers across the run
+        int w = w0;
+        asm volatile("" : "+s"(w));
         const float *al = a.alpha + (size_t)(a.start_step + k) * D;
         float ga[D];
 #pragma unroll
@@ -122,28 +181,39 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
 #pragma unroll
         for (int grp = 0; grp < NG; ++grp) {
             // tiles I0 + 8 i, i < GS
-            const int I0 = w + GS * kSlabWaves * grp;
+            const int I0 = w + GS * W * grp;
             if (I0 >= nt) break;  // wave-uniform
             f32x4 acc[GS][D];
 #pragma unroll
             for (int i = 0; i < GS; ++i)
 #pragma unroll
                 for (int mu = 0; mu < D; ++mu) acc[i][mu] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-            const bf16x8 *jrow[GS];
+            int jso[GS];  // byte offset of the tile's first chunk
+            float sc[GS];
 #pragma unroll
             for (int i = 0; i < GS; ++i) {
-                const int I = I0 + kSlabWaves * i < nt ? I0 + kSlabWaves * i : I0;  // past the end: a valid tile
-                jrow[i] = jf + (size_t)I * ncp * JS * 64 + lane;
+                const int I = I0 + W * i < nt ? I0 + W * i : I0;  // past the end: a valid tile
+                jso[i] = I * ncp * CHB;
+                // the lane's A row is 16 I + (lane & 15)
+                sc[i] = F8 ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sres, jcol * 4, I * 64, 0))
+                           : 1.0f;
             }
-            // J fragments two chunks ahead: ring slots 0 (even chunks), 1 (odd)
-            bf16x8 ring[2][GS][JS];
+            // J fragments RD chunks ahead: ring slot sl holds chunk c with c % RD == sl
+            bf16x8 ring[F8 ? 1 : RD][GS][JS];
+            uint2 ring8[F8 ? RD : 1][GS];
 #pragma unroll
-            for (int sl = 0; sl < 2; ++sl)
+            for (int sl = 0; sl < RD; ++sl)
 #pragma unroll
-                for (int i = 0; i < GS; ++i)
+                for (int i = 0; i < GS; ++i) {
+                    if constexpr (F8) {
+                        ring8[sl][i] = sl < ncp ? load_frag8(jres, jvoff, jso[i] + sl * CHB) : uint2{0u, 0u};
+                    } else {
 #pragma unroll
-                    for (int t = 0; t < JS; ++t)
-                        ring[sl][i][t] = sl < ncp ? jrow[i][(size_t)(sl * JS + t) * 64] : bf16x8{};
+                        for (int t = 0; t < JS; ++t)
+                            ring[sl][i][t] = sl < ncp ? load_frag16(jres, jvoff, jso[i] + sl * CHB + t * 1024)
+                                                      : bf16x8{};
+                    }
+                }
             auto chunk = [&](int c, bf16x8 (&af)[GS][JS]) __attribute__((always_inline)) {
                 bf16x8 bx[D][XS];
 #pragma unroll
@@ -159,32 +229,51 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
                             acc[i][mu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i][pj[q]], bx[mu][px[q]],
                                                                                 acc[i][mu], 0, 0, 0);
             };
-            for (int c = 0; c < ncp; c += 2) {
+            // RD chunks per iteration; the refill of each ring slot is
+            // unconditional (a buffer load past the staged data returns 0 and
+            // is never used), so the slot's next value is always the load
+            // itself and stays in the register the load writes.  The last
+            // ncp % RD chunks are peeled off.
+            auto take = [&](int sl, int cnext, bf16x8 (&af)[GS][JS]) __attribute__((always_inline)) {
+                if constexpr (F8) {
 #pragma unroll
-                for (int sl = 0; sl < 2; ++sl) {
-                    const int cc = c + sl;
-                    if (cc < ncp) {
-                        bf16x8 af[GS][JS];
+                    for (int i = 0; i < GS; ++i) af[i][0] = fp8_fragment(ring8[sl][i], sc[i]);
 #pragma unroll
-                        for (int i = 0; i < GS; ++i)
+                    for (int i = 0; i < GS; ++i) ring8[sl][i] = load_frag8(jres, jvoff, jso[i] + cnext * CHB);
+                } else {
 #pragma unroll
-                            for (int t = 0; t < JS; ++t) af[i][t] = ring[sl][i][t];
-                        if (cc + 2 < ncp) {
+                    for (int i = 0; i < GS; ++i)
 #pragma unroll
-                            for (int i = 0; i < GS; ++i)
+                        for (int t = 0; t < JS; ++t) af[i][t] = ring[sl][i][t];
 #pragma unroll
-                                for (int t = 0; t < JS; ++t)
-                                    ring[sl][i][t] = jrow[i][(size_t)((cc + 2) * JS + t) * 64];
-                        }
-                        chunk(cc, af);
-                    }
+                    for (int i = 0; i < GS; ++i)
+#pragma unroll
+                        for (int t = 0; t < JS; ++t)
+                            ring[sl][i][t] = load_frag16(jres, jvoff, jso[i] + cnext * CHB + t * 1024);
+                }
+            };
+            int c = 0;
+            for (; c + RD <= ncp; c += RD) {
+#pragma unroll
+                for (int sl = 0; sl < RD; ++sl) {
+                    bf16x8 af[GS][JS];
+                    take(sl, c + sl + RD, af);
+                    chunk(c + sl, af);
+                }
+            }
+#pragma unroll
+            for (int sl = 0; sl + 1 < RD; ++sl) {
+                if (c + sl < ncp) {
+                    bf16x8 af[GS][JS];
+                    take(sl, c + sl + RD, af);
+                    chunk(c + sl, af);
                 }
             }
             // fused Euler update of the group's tiles
 #pragma unroll
             for (int i = 0; i < GS; ++i) {
                 const int kk = GS * grp + i;
-                if (w + kSlabWaves * kk >= nt) continue;
+                if (w + W * kk >= nt) continue;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     float x2[D];
@@ -205,65 +294,98 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
         __syncthreads();  // every wavefront is done reading the old operand
 #pragma unroll
         for (int kk = 0; kk < TPW; ++kk) {
-            const int I = w + kSlabWaves * kk;
+            const int I = w + W * kk;
             if (I < nt) slab_write_tile<D, XS>(x[kk], I, lane, lb, negk);
         }
         __syncthreads();
     }
 
+    // addresses of the final store are formed here, not kept live through the run
+    int lane_s = lane;
+    asm volatile("" : "+v"(lane_s));
+    const int g_s = lane_s >> 4;
+    const int rep_s = rep0 + (lane_s & 15);
 #pragma unroll
     for (int kk = 0; kk < TPW; ++kk) {
-        const int I = w + kSlabWaves * kk;
+        const int I = w + W * kk;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int p = 16 * I + 4 * g + v;
-            if (valid && p < n) {
+            const int p = 16 * I + 4 * g_s + v;
+            if (rep_s < r && p < n) {
 #pragma unroll
-                for (int mu = 0; mu < D; ++mu) a.x[((size_t)p * r + rep) * D + mu] = x[kk][mu][v];
+                for (int mu = 0; mu < D; ++mu) a.x[((size_t)p * r + rep_s) * D + mu] = x[kk][mu][v];
             }
         }
     }
 }
 
-// Stages J of one problem as A fragments [tile][chunk][JS][64 lanes].
+// Stages J of one problem as A fragments: bf16 [tile][chunk][JS][64 lanes],
+// or (JS = 1 and the header flag set) E4M3 [tile][chunk][64 lanes] in the
+// same slot order.
 template <int JS>
-__global__ __launch_bounds__(256) void k_stage_jfrag(IntegArgs a, int ncp, bf16x8 *__restrict__ out) {
+__global__ __launch_bounds__(256) void k_stage_jfrag(IntegArgs a, int ncp, unsigned char *__restrict__ stage) {
     const int nt = (a.n + 15) / 16;
     const int total = nt * ncp * 64;
+    const bool f8 = JS == 1 && *reinterpret_cast<const int *>(stage) != 0;
+    const float *scale = reinterpret_cast<const float *>(stage + kStageHeader);
+    bf16x8 *out = reinterpret_cast<bf16x8 *>(stage + stage_frag_offset(nt));
+    uint2 *out8 = reinterpret_cast<uint2 *>(stage + stage_frag_offset(nt));
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
         const int lane = idx & 63;
         const int c = (idx >> 6) % ncp;
         const int I = (idx >> 6) / ncp;
-        bf16x8 f[JS];
-        j_fragment<JS>(a, I, c, lane, f);
+        if (f8) {
+            const int i = lane & 15, g = lane >> 4;
+            const int p = 16 * I + i;
+            const int e = p < a.n ? ilogbf(scale[p]) : 0;
+            uint32_t wd[2] = {0u, 0u};
 #pragma unroll
-        for (int t = 0; t < JS; ++t) out[((size_t)(I * ncp + c) * JS + t) * 64 + lane] = f[t];
+            for (int s = 0; s < 8; ++s) {
+                const int q = 32 * c + 16 * (s >> 2) + 4 * g + (s & 3);
+                uint32_t code = 0u;
+                if (p < a.n && q < a.n) {
+                    code = (a.j_dtype == CHYM_J_FP8) ? reinterpret_cast<const uint8_t *>(a.j)[(size_t)p * a.n + q]
+                                                      : e4m3_code(ldexpf(coupling(a.j, a.j_dtype, a.n, p, q), -e));
+                }
+                wd[s >> 2] |= code << (8 * (s & 3));
+            }
+            out8[(size_t)(I * ncp + c) * 64 + lane] = uint2{wd[0], wd[1]};
+        } else {
+            bf16x8 f[JS];
+            j_fragment<JS>(a, I, c, lane, f);
+#pragma unroll
+            for (int t = 0; t < JS; ++t) out[((size_t)(I * ncp + c) * JS + t) * 64 + lane] = f[t];
+        }
     }
 }
 
-// Column slabs of one problem: block b integrates replicas 16 b .. 16 b + 15.
-template <int D, int XS, int JS, int TPW>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
-void k_integrate_slab(IntegArgs a, const bf16x8 *__restrict__ jf, int ncp) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    integrate_slab<D, XS, JS, TPW>(a, blockIdx.x * 16, jf, ncp, reinterpret_cast<bf16x8 *>(smem));
+// The E4M3 path exists for single-term couplings; the flag is uniform.
+template <int D, int XS, int JS, int TPW, int W>
+__device__ __forceinline__ void slab_run(const IntegArgs &a, int rep0, const unsigned char *stage, int ncp,
+                                         bf16x8 *lb) {
+    if constexpr (JS == 1) {
+        if (__builtin_amdgcn_readfirstlane(*reinterpret_cast<const int *>(stage)) != 0) {
+            integrate_slab<D, XS, JS, TPW, true, W>(a, rep0, stage, ncp, lb);
+            return;
+        }
+    }
+    integrate_slab<D, XS, JS, TPW, false, W>(a, rep0, stage, ncp, lb);
 }
 
-// One work item of the persistent form.
-template <int D, int XS, int JS, int TPW>
-__device__ __forceinline__ void slab_item(const IntegArgs *__restrict__ tasks, int2 wi,
-                                                    const bf16x8 *const *__restrict__ jfs, const int *__restrict__ ncps,
-                                                    bf16x8 *lb) {
-    const IntegArgs a = tasks[wi.x];
-    integrate_slab<D, XS, JS, TPW>(a, wi.y * 16, jfs[wi.x], ncps[wi.x], lb);
+// Column slabs of one problem: block b integrates replicas 16 b .. 16 b + 15.
+template <int D, int XS, int JS, int TPW, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W / 4)))
+void k_integrate_slab(IntegArgs a, const unsigned char *__restrict__ stage, int ncp) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    slab_run<D, XS, JS, TPW, W>(a, blockIdx.x * 16, stage, ncp, reinterpret_cast<bf16x8 *>(smem));
 }
 
 // Persistent form: blocks pop (task, column slab) items; jfs[task] is the
 // task's staged J and ncps[task] its chunk count.
-template <int D, int XS, int JS, int TPW>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+template <int D, int XS, int JS, int TPW, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W / 4)))
 void k_integrate_slab_persistent(const IntegArgs *__restrict__ tasks, const int2 *__restrict__ items, int n_items,
-                                 int *__restrict__ counter, const bf16x8 *const *__restrict__ jfs,
+                                 int *__restrict__ counter, const unsigned char *const *__restrict__ jfs,
                                  const int *__restrict__ ncps) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_item;
@@ -273,25 +395,31 @@ void k_integrate_slab_persistent(const IntegArgs *__restrict__ tasks, const int2
         __syncthreads();
         const int it = __builtin_amdgcn_readfirstlane(s_item);
         if (it >= n_items) break;
-        slab_item<D, XS, JS, TPW>(tasks, items[it], jfs, ncps, reinterpret_cast<bf16x8 *>(smem));
+        const int2 wi = items[it];
+        const IntegArgs a = tasks[wi.x];
+        slab_run<D, XS, JS, TPW, W>(a, wi.y * 16, jfs[wi.x], ncps[wi.x], reinterpret_cast<bf16x8 *>(smem));
     }
 }
 
 struct SlabKernels {
-    void (*single)(IntegArgs, const bf16x8 *, int);
-    void (*persistent)(const IntegArgs *, const int2 *, int, int *, const bf16x8 *const *, const int *);
+    void (*single)(IntegArgs, const unsigned char *, int);
+    void (*persistent)(const IntegArgs *, const int2 *, int, int *, const unsigned char *const *, const int *);
+    int waves;
 };
 
+// Slab shapes: eight wavefronts with 4 or 8 tiles each.  (One wavefront per
+// SIMD with 16 tiles measured slower at N = 1000, D = 4: a lone wavefront
+// cannot cover the L2 latency of the J stream.)
 template <int D, int XS, int JS>
-SlabKernels slab_lookup_tpw(int tpw) {
-    switch (tpw) {
-        case 4: return SlabKernels{k_integrate_slab<D, XS, JS, 4>, k_integrate_slab_persistent<D, XS, JS, 4>};
-        case 8: return SlabKernels{k_integrate_slab<D, XS, JS, 8>, k_integrate_slab_persistent<D, XS, JS, 8>};
-        default: return SlabKernels{nullptr, nullptr};
-    }
+SlabKernels slab_lookup_tpw(int tpw, int waves) {
+    if (waves == 8 && tpw == 4)
+        return SlabKernels{k_integrate_slab<D, XS, JS, 4, 8>, k_integrate_slab_persistent<D, XS, JS, 4, 8>, 8};
+    if (waves == 8 && tpw == 8)
+        return SlabKernels{k_integrate_slab<D, XS, JS, 8, 8>, k_integrate_slab_persistent<D, XS, JS, 8, 8>, 8};
+    return SlabKernels{nullptr, nullptr, 0};
 }
 
-#define CHYM_DECLARE_SLAB(D, XS, JS) SlabKernels lookup_slab_##D##_##XS##_##JS(int tpw);
+#define CHYM_DECLARE_SLAB(D, XS, JS) SlabKernels lookup_slab_##D##_##XS##_##JS(int tpw, int waves);
 CHYM_DECLARE_SLAB(1, 3, 1) CHYM_DECLARE_SLAB(1, 1, 1) CHYM_DECLARE_SLAB(1, 3, 3)
 CHYM_DECLARE_SLAB(2, 3, 1) CHYM_DECLARE_SLAB(2, 1, 1) CHYM_DECLARE_SLAB(2, 3, 3)
 CHYM_DECLARE_SLAB(3, 3, 1) CHYM_DECLARE_SLAB(3, 1, 1) CHYM_DECLARE_SLAB(3, 3, 3)

@@ -6,32 +6,6 @@
 
 namespace chym {
 
-// Nearest E4M3 code of a (|a| <= 448 assumed), ties to even; sign from the
-// float's sign bit.
-__device__ __forceinline__ uint32_t e4m3_code(float v) {
-    const uint32_t bits = __float_as_uint(v);
-    const uint32_t sign = (bits >> 24) & 0x80u;
-    const float a = fabsf(v);
-    uint32_t code;
-    if (a < 0x1p-6f) {
-        // subnormal spacing 2^-9; a * 512 is exact, rintf rounds to even
-        code = (uint32_t)rintf(a * 512.0f);  // 8 is the smallest normal, 0x08
-    } else {
-        const uint32_t ab = __float_as_uint(a);
-        int e = (int)(ab >> 23) - 127;
-        const uint32_t mant = ab & 0x7fffffu;
-        uint32_t m3 = mant >> 20;
-        const uint32_t rest = mant & 0xfffffu;
-        if (rest > 0x80000u || (rest == 0x80000u && (m3 & 1u))) ++m3;
-        if (m3 == 8u) {
-            m3 = 0u;
-            ++e;
-        }
-        code = ((uint32_t)(e + 7) << 3) | m3;
-    }
-    return sign | code;
-}
-
 // One wavefront per row: the row's exponent from its largest magnitude,
 // then its codes.
 __global__ __launch_bounds__(256) void k_quantize_fp8(int n, const float *__restrict__ j, uint8_t *__restrict__ out) {
@@ -48,15 +22,7 @@ __global__ __launch_bounds__(256) void k_quantize_fp8(int n, const float *__rest
     }
     for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
     finite = __all(finite);
-    // least e with amax <= 448 * 2^e
-    int e = 0;
-    if (amax > 0.0f) {
-        int k;
-        frexpf(amax, &k);  // amax = f 2^k, f in [0.5, 1)
-        e = k - 9;         // 448 * 2^(k - 9) = 0.875 * 2^k: one of e, e + 1 is the answer
-        if (amax > ldexpf(448.0f, e)) ++e;
-        if (amax <= ldexpf(448.0f, e - 1)) --e;
-    }
+    const int e = e4m3_row_exponent(amax);
     const bool ok = finite && e >= -127 && e <= 127;
     uint8_t *dst = out + (size_t)row * n;
     for (int q = lane; q < n; q += 64) dst[q] = ok ? (uint8_t)e4m3_code(ldexpf(src[q], -e)) : (uint8_t)0x7fu;

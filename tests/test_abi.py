@@ -81,7 +81,8 @@ def test_unsupported_size_reported_before_device():
     assert "workspace" in lib.chym_last_error().decode()
     nbytes = ctypes.c_size_t(0)
     assert lib.chym_integrate_workspace_size(ctypes.byref(prob), ctypes.byref(run), ctypes.byref(nbytes)) == 0
-    assert nbytes.value == 63 * 32 * 1024  # 63 row tiles x 32 chunks x 1 KiB fragments
+    # header, row scales of 63 x 16 rows, 63 row tiles x 32 chunks x 1 KiB fragments
+    assert nbytes.value == 256 + 4096 + 63 * 32 * 1024
     assert lib.chym_integrate_ws(ctypes.byref(prob), ctypes.byref(run), ctypes.c_void_p(0x10000), 100,
                                  None) == L.CHYM_ENOMEM
     small = _prob(n=100, d=2)
@@ -166,3 +167,27 @@ def test_plan_table_validation_and_file_roundtrip(tmp_path):
         assert lib.chym_plan_set(ctypes.byref(e2)) in (L.CHYM_EINVAL, L.CHYM_EUNSUPPORTED)
     assert lib.chym_split3_bf16(None, 8, None, None, None, None) == L.CHYM_EINVAL
     assert lib.chym_split3_bf16(0x1000, 7, 0x2000, 0x3000, 0x4000, None) == L.CHYM_EINVAL
+
+
+def test_coupling_storage_sizes_and_quantizer_validation():
+    lib = L.load()
+    b = ctypes.c_size_t(0)
+    for jt, want in ((L.CHYM_J_I8, 25), (L.CHYM_J_F32, 100), (L.CHYM_J_BF16, 50), (L.CHYM_J_FP8, 30)):
+        assert lib.chym_j_bytes(5, jt, ctypes.byref(b)) == L.CHYM_OK
+        assert b.value == want
+    assert lib.chym_j_bytes(5, 9, ctypes.byref(b)) == L.CHYM_EINVAL
+    assert lib.chym_j_bytes(0, L.CHYM_J_FP8, ctypes.byref(b)) == L.CHYM_EINVAL
+    assert lib.chym_j_bytes(5, L.CHYM_J_FP8, None) == L.CHYM_EINVAL
+    assert lib.chym_quantize_fp8(0, 0x1000, 0x2000, None) == L.CHYM_EINVAL
+    assert lib.chym_quantize_fp8(8, None, 0x2000, None) == L.CHYM_EINVAL
+    assert lib.chym_quantize_fp8(8, 0x1000, None, None) == L.CHYM_EINVAL
+    for jt in (L.CHYM_J_BF16, L.CHYM_J_FP8):
+        # int32 energies need integer couplings (rejected before any device work)
+        assert lib.chym_ising_energy(16, 4, 0x1000, jt, 0x2000, 0x3000, None, None) == L.CHYM_EINVAL
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        return  # the calls below pass fake pointers: only where no device can run them
+    for jt in (L.CHYM_J_BF16, L.CHYM_J_FP8):
+        # the new storages pass validation and stop at the missing device
+        rc = lib.chym_integrate(ctypes.byref(_prob(j_dtype=jt)), ctypes.byref(_run()), None)
+        assert rc == L.CHYM_ENODEV
