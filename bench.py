@@ -34,6 +34,23 @@ PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak (TFLOP/s)
 PEAK_FP32_MATRIX_TFLOPS = 157.3
 
 
+# HBM bytes per launch of the dominant kernel on the default workload, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by the same counters on the
+# bench's own 4 GB state copy (profiles/integrate_persistent_sk100_d23_f32.md);
+# keyed by kernel and workload, valid for the kernels as they are now.
+TRAFFIC = {("k_integrate_persistent<7, 3, 3, 1>", 100, 1000, 2000): 4.922e9}
+
+
+def kernel_name(tiles, d, precision, plan):
+    xs = 3 if precision == "f32" else 1
+    kind = plan.get("kernel")
+    if kind == 2:
+        return f"k_integrate_persistent_lds<{tiles}, {d}, {xs}, 1, 2>"
+    if kind == 3:
+        return f"k_integrate_persistent_lds<{tiles}, {d}, {xs}, 1, 1>"
+    return f"k_integrate_persistent<{tiles}, {d}, {xs}, 1>"
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,6 +67,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--autotune", type=int, default=1, help="time the launch plans of each variant first")
     ap.add_argument("--plan-cache", type=str, default="", help="load plans from this file instead of tuning")
+    ap.add_argument("--save-plans", type=str, default="", help="write the plans used to this file")
     ap.add_argument("--cpu-baseline", type=int, default=1, help="0 disables the oracle timing leg")
     ap.add_argument("--cpu-replicas", type=int, default=2000)
     ap.add_argument("--tts", type=int, default=1, help="0 skips the time-to-99%%-ground-state comparison")
@@ -332,6 +350,8 @@ def main():
         for d in [int(v) for v in args.dims.split(",")]:
             best, cands = api.chym_plan_autotune(args.n, d, args.precision, torch.int8, steps=400)
             plans[str(d)] = {"chosen": best, "candidates": cands}
+    if args.save_plans:
+        api.chym_plan_save(args.save_plans)
     wl = build_workload(args, torch, synth, api, dev)
     stream = torch.cuda.current_stream()
     dims = wl["dims"]
@@ -374,10 +394,11 @@ def main():
     flops_k = upd_k * 2.0 * (n - 1)  # algorithmic: 2 (N-1) flops per update (dense J, zero diagonal)
     avg_s = kern_ms[dk] / args.steps / 1e3
     achieved = flops_k / avg_s / 1e12
+    plan = api.chym_plan_get(args.n, dk, args.precision, torch.int8)
+    kname = kernel_name((n + 15) // 16, dk, args.precision, plan)
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
-            "kernel": f"k_integrate_persistent<tiles={(n + 15) // 16}, D={dk}, {args.precision}>",
-            "kernel_ms": kern_ms[dk] / args.steps}
+            "frac": achieved / PEAK_BF16_TFLOPS, "traffic": TRAFFIC.get((kname, args.n, args.instances, R)),
+            "kernel": kname, "kernel_ms": kern_ms[dk] / args.steps}
 
     # run statistics of the last step (not timed)
     diverged = sum(int(o["diverged"].sum().item()) for _, _, o in wl["outs"])
