@@ -71,10 +71,11 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1, help="0 disables the oracle timing leg")
     ap.add_argument("--cpu-replicas", type=int, default=2000)
     ap.add_argument("--tts", type=int, default=1, help="0 skips the time-to-99%%-ground-state comparison")
-    ap.add_argument("--workload", type=str, default="sk100", choices=["sk100", "precision", "batched"],
+    ap.add_argument("--workload", type=str, default="sk100", choices=["sk100", "precision", "batched", "map"],
                     help="sk100: the default throughput workload; precision: N=1000, D=4, 4096 replicas, "
                          "10000 steps with +-1, bf16 Gaussian and FP8 Gaussian couplings; batched: 10000 "
-                         "solves of mixed N, D and graph family in one graph launch")
+                         "solves of mixed N, D and graph family in one graph launch; map: the round-trip "
+                         "map of Eq. (2) at the paper's parameters, N=100, D=3, 65536 replicas")
     return ap.parse_args()
 
 
@@ -323,6 +324,53 @@ def run_batched(args, torch, api, synth):
             "setup_s": t_setup, "plans": tuned}
 
 
+def run_map(args, torch, api, synth):
+    """The literal round-trip map: N = 100 SK, D = 3, 65536 replicas (pumps
+    1.1 .. 2 h_th), kappa L = 0.1, beta b^2 = 25, b = d = 0.01, 2000 round
+    trips with the anneal, float32 form."""
+    import math
+
+    dev = torch.device("cuda:0")
+    n, d, R, steps = 100, 3, 65536, 2000
+    b = dd = 0.01
+    kl, bb2 = 0.1, 25.0
+    J = synth.sk_pm1(n, 6, 0)
+    jmag = 0.5 / lambda_max_power(J) * (b + dd) / b
+    hth = -math.log((1 - b) * (1 - dd)) / kl
+    h = torch.from_numpy((np.linspace(1.1, 2.0, R) * hth).astype(np.float32)).to(dev)
+    A0 = synth.initial_states_torch(n, R, d, seed=2308023295, device=dev) * (100.0 * math.sqrt((b + dd) / bb2))
+    A = torch.empty_like(A0)
+    alpha = torch.from_numpy(synth.anneal_schedule(steps, d)[0]).to(dev)
+    Jd = torch.from_numpy(J).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def run():
+        api.chym_map_integrate(Jd, h, A, alpha, b=b, loss=dd, kl=kl, beta_b2=bb2, jmag=jmag, steps=steps)
+
+    A.copy_(A0)
+    run()
+    torch.cuda.synchronize()
+    ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        A.copy_(A0)
+        ms += timed_events(torch, stream, run, 1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    upd = n * R * d * steps
+    kms = ms / args.steps
+    achieved = upd * 2.0 * (n - 1) / (kms / 1e3) / 1e12
+    return {"metric": METRIC, "value": upd / (wall / args.steps), "unit": "spin-component updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"round-trip map of Eq. (2): SK +-1 N={n}, D={d}, {R} replicas, {steps} round "
+                                   f"trips, kappa L={kl}, beta b^2={bb2}, b=d={b}, linear anneal, f32 form",
+                       "n": n, "d": d, "replicas": R, "round_trips": steps, "precision": "f32"},
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                         "kernel": "k_integrate_resident<7, 3, 3, 1, true>", "kernel_ms": kms}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -335,7 +383,7 @@ def main():
         from paper_2308_02329_amd import api, synth
 
         torch.cuda.set_device(0)
-        fn = run_precision if args.workload == "precision" else run_batched
+        fn = {"precision": run_precision, "batched": run_batched, "map": run_map}[args.workload]
         print(json.dumps(fn(args, torch, api, synth), default=str), flush=True)
         return
 

@@ -156,6 +156,36 @@ int chym_integrate_workspace_size(const chym_problem *prob, const chym_run *run,
 int chym_integrate_ws(const chym_problem *prob, const chym_run *run, void *workspace, size_t ws_bytes,
                       chym_stream_t stream);
 
+/* The round-trip map of Eq. (2) itself, one step per round trip (the
+ * paper's own simulation model; chym_integrate integrates its continuous
+ * limit).  For every parametric oscillator j = (p, mu):
+ *   B_j  = K(A_j) A_j,  K(A) = P / (P cosh(kl P) - h sinh(kl P)),  P = sqrt(h^2 + A^2)
+ *          (exact solution of the degenerate phase-matched coupled-mode
+ *          equations over the medium, the NLM paragraph; h the pump),
+ *   Y_j  = (1 - b) B_j + b jmag alpha_mu sum_q J_pq B_{q,mu} - beta_b2 B_j sum_nu B_{p,nu}^2,
+ *   A'_j = (1 - loss) Y_j.
+ * J holds the coupling pattern (e.g. +-1); jmag is the coupling magnitude J.
+ * run->pump holds h per replica (absolute, not normalized), run->x the
+ * amplitudes A [n][r][d] (in/out), run->dt must be 1 (one round trip per
+ * step), run->alpha the annealing table as for chym_integrate.  N <= 112
+ * (register-resident integrator); couplings must be exact in one bf16 term
+ * (CHYM_J_I8, CHYM_J_BF16, CHYM_J_FP8); otherwise CHYM_EUNSUPPORTED. */
+typedef struct chym_map_problem {
+    int32_t n;        /* parametric-oscillator blocks (hyperspins) N >= 1 */
+    int32_t d;        /* components per hyperspin, 1 <= D <= 4 */
+    int32_t j_dtype;  /* CHYM_J_I8, CHYM_J_BF16 or CHYM_J_FP8 */
+    int32_t reserved; /* must be 0 */
+    const void *j;    /* device, layout by j_dtype */
+    float b;          /* coupler fraction per round trip, 0 < b < 1 */
+    float loss;       /* linear loss d per round trip, 0 <= d < 1 */
+    float kl;         /* kappa L of the medium, > 0 */
+    float beta_b2;    /* nonlocal-loss coefficient beta b^2, >= 0 */
+    float jmag;       /* coupling magnitude J */
+    float reserved_f; /* must be 0 */
+} chym_map_problem;
+
+int chym_map_integrate(const chym_map_problem *prob, const chym_run *run, chym_stream_t stream);
+
 /* Sign readout of x (paper: the Ising spins are read at the end of a run).
  * spins [r][ceil(n/64)], extra_frac [r], diverged [r]; each may be NULL. */
 int chym_readout(int32_t n, int32_t d, int32_t r, const float *x, uint64_t *spins,

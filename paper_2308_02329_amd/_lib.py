@@ -31,7 +31,7 @@ EXPORTS = (
     "chym_plan_autotune_workspace_size", "chym_plan_autotune", "chym_split3_bf16", "chym_j_bytes", "chym_quantize_fp8", "chym_plan_save",
     "chym_plan_load", "chym_integrate_workspace_size", "chym_integrate_ws", "chym_solve_ws",
     "chym_sign_words", "chym_features", "chym_mlp_scratch_floats", "chym_mlp_forward", "chym_mlp_backward",
-    "chym_mlp_adam", "chym_to_bf16",
+    "chym_mlp_adam", "chym_to_bf16", "chym_map_integrate",
 )
 
 CHYM_FEATURES = 32
@@ -50,6 +50,12 @@ class ChymProblem(ctypes.Structure):
     _fields_ = [("n", _i32), ("d", _i32), ("j_dtype", _i32), ("reserved", _i32), ("j", _vp),
                 ("eps", ctypes.c_float), ("btil", ctypes.c_float), ("eta", ctypes.c_float),
                 ("reserved_f", ctypes.c_float)]
+
+
+class ChymMapProblem(ctypes.Structure):
+    _fields_ = [("n", _i32), ("d", _i32), ("j_dtype", _i32), ("reserved", _i32), ("j", _vp),
+                ("b", ctypes.c_float), ("loss", ctypes.c_float), ("kl", ctypes.c_float),
+                ("beta_b2", ctypes.c_float), ("jmag", ctypes.c_float), ("reserved_f", ctypes.c_float)]
 
 
 class ChymRun(ctypes.Structure):
@@ -86,6 +92,8 @@ def load():
     lib.chym_last_error.restype = ctypes.c_char_p
     lib.chym_integrate.argtypes = [P(ChymProblem), P(ChymRun), _vp]
     lib.chym_integrate.restype = ctypes.c_int
+    lib.chym_map_integrate.argtypes = [P(ChymMapProblem), P(ChymRun), _vp]
+    lib.chym_map_integrate.restype = ctypes.c_int
     lib.chym_readout.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp]
     lib.chym_readout.restype = ctypes.c_int
     lib.chym_ising_energy.argtypes = [_i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp]

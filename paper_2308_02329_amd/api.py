@@ -18,7 +18,7 @@ from ._lib import (CHYM_J_BF16, CHYM_J_F32, CHYM_J_FP8, CHYM_J_I8, CHYM_KERNEL_A
 __all__ = ["chym_sign_words", "chym_features", "chym_mlp_forward", "chym_mlp_backward", "chym_mlp_adam",
            "chym_mlp_scratch_floats", "chym_to_bf16", "chym_integrate_workspace_size", "chym_version", "chym_last_error", "chym_integrate", "chym_readout", "chym_ising_energy",
            "chym_hs_energy", "chym_solve", "make_problem", "make_run", "spin_words", "ChymError",
-           "CHYM_J_I8", "CHYM_J_F32", "CHYM_J_BF16", "CHYM_J_FP8", "j_size", "chym_j_bytes", "chym_quantize_fp8", "CHYM_PREC_F32", "CHYM_PREC_BF16", "precision_code",
+           "CHYM_J_I8", "CHYM_J_F32", "CHYM_J_BF16", "CHYM_J_FP8", "chym_map_integrate", "j_size", "chym_j_bytes", "chym_quantize_fp8", "CHYM_PREC_F32", "CHYM_PREC_BF16", "precision_code",
            "chym_batch_workspace_size", "chym_batch_create", "chym_batch_launch", "chym_batch_launch_nograph",
            "chym_batch_destroy", "ChymBatch", "chym_plan_set", "chym_plan_get", "chym_plan_autotune",
            "chym_plan_save", "chym_plan_load", "chym_split3_bf16", "CHYM_KERNEL_REGJ", "CHYM_KERNEL_LDSJ",
@@ -145,6 +145,20 @@ def chym_integrate(J, pump, x, alpha, *, eps, btil, eta, dt, steps, start_step=0
         L.check(lib.chym_integrate_ws(ctypes.byref(prob), ctypes.byref(run), _vp(ws), nb, _stream(stream)),
                 "chym_integrate_ws")
     return x
+
+
+def chym_map_integrate(J, h, A, alpha, *, b, loss, kl, beta_b2, jmag, steps, start_step=0,
+                       precision=CHYM_PREC_F32, stream=None):
+    """Advance the amplitudes A [n, r, d] (float32, in place) by ``steps``
+    round trips of the map of Eq. (2); h [r] is the pump of each replica."""
+    n, r, d = A.shape
+    _need_j(J, n)
+    run = make_run(n, d, h, A, alpha, 1.0, steps, start_step, precision)
+    prob = L.ChymMapProblem(n=n, d=d, j_dtype=_jdtype(J), reserved=0, j=_vp(J), b=float(b), loss=float(loss),
+                            kl=float(kl), beta_b2=float(beta_b2), jmag=float(jmag), reserved_f=0.0)
+    L.check(L.load().chym_map_integrate(ctypes.byref(prob), ctypes.byref(run), _stream(stream)),
+            "chym_map_integrate")
+    return A
 
 
 def chym_readout(x, spins=None, extra_frac=None, diverged=None, stream=None):

@@ -124,6 +124,8 @@ chym::IntegArgs make_args(const chym_problem *prob, const chym_run *run) {
     a.btil = prob->btil;
     a.eta = prob->eta;
     a.dt = run->dt;
+    a.kl = 0.0f;
+    a.c0 = 0.0f;
     return a;
 }
 
@@ -471,6 +473,57 @@ int chym_integrate(const chym_problem *prob, const chym_run *run, chym_stream_t 
     rc = validate_run(run);
     if (rc) return rc;
     return integrate_impl(prob, run, (hipStream_t)stream);
+}
+
+int chym_map_integrate(const chym_map_problem *m, const chym_run *run, chym_stream_t stream) {
+    if (!m) return fail(CHYM_EINVAL, "problem is NULL");
+    if (m->n < 1) return fail(CHYM_EINVAL, "n = %d must be >= 1", m->n);
+    if (m->d < 1 || m->d > 4) return fail(CHYM_EINVAL, "d = %d must be in 1..4", m->d);
+    if (!valid_jdtype(m->j_dtype)) return fail(CHYM_EINVAL, "bad j_dtype %d", m->j_dtype);
+    if (!m->j) return fail(CHYM_EINVAL, "J is NULL");
+    if (m->reserved != 0 || m->reserved_f != 0.0f) return fail(CHYM_EINVAL, "reserved fields must be 0");
+    if (!(m->b > 0.0f && m->b < 1.0f)) return fail(CHYM_EINVAL, "b must be in (0, 1)");
+    if (!(m->loss >= 0.0f && m->loss < 1.0f)) return fail(CHYM_EINVAL, "loss must be in [0, 1)");
+    if (!(m->kl > 0.0f) || !finite(m->kl)) return fail(CHYM_EINVAL, "kl must be finite and > 0");
+    if (!(m->beta_b2 >= 0.0f) || !finite(m->beta_b2)) return fail(CHYM_EINVAL, "beta_b2 must be finite and >= 0");
+    if (!finite(m->jmag)) return fail(CHYM_EINVAL, "jmag must be finite");
+    int rc = validate_run(run);
+    if (rc) return rc;
+    if (run->dt != 1.0f) return fail(CHYM_EINVAL, "the map takes one round trip per step: dt must be 1");
+    if (m->j_dtype == CHYM_J_F32)
+        return fail(CHYM_EUNSUPPORTED, "the map form takes couplings exact in one bf16 term (I8, BF16, FP8)");
+    const int tiles = (m->n + 15) / 16;
+    const int xs = run->precision == CHYM_PREC_F32 ? 3 : 1;
+    if (tiles > std::min(chym::resident_tile_limit(m->d, xs, 1), chym::kMapMaxTiles))
+        return fail(CHYM_EUNSUPPORTED, "the map form runs n <= %d (n = %d, d = %d)",
+                    16 * std::min(chym::resident_tile_limit(m->d, xs, 1), chym::kMapMaxTiles), m->n, m->d);
+    if (run->steps == 0) return CHYM_OK;
+    rc = check_device();
+    if (rc) return rc;
+    chym::IntegArgs a;
+    a.j = m->j;
+    a.pump = run->pump;
+    a.x = run->x;
+    a.alpha = run->alpha;
+    a.n = m->n;
+    a.d = m->d;
+    a.r = run->r;
+    a.steps = run->steps;
+    a.start_step = run->start_step;
+    a.j_dtype = m->j_dtype;
+    a.dt = 1.0f;
+    // A' = (1 - loss) [(1 - b) B - beta_b2 B S(B)] + (1 - loss) b jmag alpha (J B),  B = K(A) A
+    a.eps = (1.0f - m->loss) * m->b * m->jmag;
+    a.btil = (1.0f - m->loss) * m->beta_b2;
+    a.eta = 0.0f;
+    a.kl = m->kl;
+    a.c0 = (1.0f - m->loss) * (1.0f - m->b);
+    bool supported = false;
+    hipError_t e = chym::launch_integrate_map(tiles, m->d, xs, default_waves_per_block(), a, (hipStream_t)stream,
+                                              &supported);
+    if (!supported) return fail(CHYM_EUNSUPPORTED, "no map variant for n = %d, d = %d", m->n, m->d);
+    if (e != hipSuccess) return hip_fail(e, "map integrate launch");
+    return CHYM_OK;
 }
 
 int chym_readout(int32_t n, int32_t d, int32_t r, const float *x, uint64_t *spins, double *extra_frac,

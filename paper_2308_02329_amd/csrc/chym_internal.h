@@ -93,12 +93,21 @@ struct IntegArgs {
     const float *alpha;
     int32_t n, d, r, steps, start_step, j_dtype;
     float eps, btil, eta, dt;
+    // round-trip map form only: kappa L of the medium, and the constant part
+    // (1 - loss)(1 - b) of the per-round-trip factor
+    float kl, c0;
 };
 
 // Host-side launcher of the resident integrator for one (tiles, d, xs, js)
 // variant; returns hipSuccess or the launch error.
 hipError_t launch_integrate(int tiles, int d, int xs, int js, int waves_per_block,
                             const IntegArgs &a, hipStream_t stream, bool *supported);
+// The round-trip map form (single coupling term only), up to this many row
+// tiles (the medium's gain per amplitude needs registers the largest
+// register-resident shapes do not have).
+constexpr int kMapMaxTiles = 7;
+hipError_t launch_integrate_map(int tiles, int d, int xs, int waves_per_block, const IntegArgs &a,
+                                hipStream_t stream, bool *supported);
 bool integrate_variant_exists(int tiles, int d, int xs, int js);
 // Persistent kernel kinds: J gathered into each wavefront's registers, work
 // items of 16 replicas; or J staged in LDS per block, work items of

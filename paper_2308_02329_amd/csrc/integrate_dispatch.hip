@@ -13,7 +13,7 @@ static KernelFn lookup(int tiles, int d, int xs, int js) {
     CHYM_PICK(3, 3, 1) CHYM_PICK(3, 1, 1) CHYM_PICK(3, 3, 3)
     CHYM_PICK(4, 3, 1) CHYM_PICK(4, 1, 1) CHYM_PICK(4, 3, 3)
 #undef CHYM_PICK
-    return KernelSet{nullptr, nullptr, nullptr, nullptr, 0};
+    return KernelSet{nullptr, nullptr, nullptr, nullptr, 0, nullptr};
 }
 
 int resident_tile_limit(int d, int xs, int js) {
@@ -244,6 +244,17 @@ hipError_t launch_integrate(int tiles, int d, int xs, int js, int waves_per_bloc
 }
 
 bool integrate_variant_exists(int tiles, int d, int xs, int js) { return lookup(tiles, d, xs, js).single != nullptr; }
+
+hipError_t launch_integrate_map(int tiles, int d, int xs, int waves_per_block, const IntegArgs &a,
+                                hipStream_t stream, bool *supported) {
+    KernelFn fn = lookup(tiles, d, xs, 1);
+    *supported = fn.single_map != nullptr;
+    if (!fn.single_map) return hipSuccess;
+    const int reps_per_block = 16 * waves_per_block;
+    const int blocks = (a.r + reps_per_block - 1) / reps_per_block;
+    hipLaunchKernelGGL(fn.single_map, dim3(blocks), dim3(64 * waves_per_block), 0, stream, a);
+    return hipGetLastError();
+}
 
 static void (*lds_kernel(const KernelFn &fn, int kind))(const IntegArgs *, const int2 *, int, int *) {
     return kind == kKernelLdsJ1 ? fn.persistent_lds1 : fn.persistent_lds;

@@ -147,10 +147,29 @@ __device__ __forceinline__ void stage_j(const IntegArgs &a, bf16x8 *jl) {
     }
 }
 
+// Gain of the nonlinear medium for a field of amplitude A under pump h:
+// K = P / (P cosh(kl P) - h sinh(kl P)), P = sqrt(h^2 + A^2), written as
+// 2 P e / ((P + h) + (P - h) e^2) with e = exp(kl P) and P - h = A^2 / (P + h),
+// which has no cancellation for h >= 0.  The square root, reciprocals and
+// exponential are the hardware's (each within about 1 ulp); kl2 = kl log2(e).
+__device__ __forceinline__ float nlm_gain(float A, float h, float kl2) {
+    const float A2 = A * A;
+    const float P = __builtin_amdgcn_sqrtf(fmaf(h, h, A2));
+    const float s = P + h;
+    if (!(s > 0.0f)) return 1.0f;  // A = h = 0: the medium is transparent
+    const float e = __builtin_amdgcn_exp2f(kl2 * P);
+    const float den = fmaf(A2 * __builtin_amdgcn_rcpf(s), e * e, s);
+    return (2.0f * P * e) * __builtin_amdgcn_rcpf(den);
+}
+
 // Integrates the 16 replicas rep0 .. rep0+15 of problem a for a.steps steps.
 // Called by one whole wavefront.  JLDS: J fragments are read from the
 // block's LDS copy every step; otherwise they are gathered into registers.
-template <int NT, int D, int XS, int JS, bool JLDS>
+// MAP: the round-trip map of Eq. (2) instead of its continuous limit: every
+// amplitude first passes the medium (A <- K(A) A, pump h = pump[replica]),
+// then the same update runs with the map's coefficients, which the host puts
+// in eps, btil, eta and c0 (dt = 1).
+template <int NT, int D, int XS, int JS, bool JLDS, bool MAP = false>
 __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0, const bf16x8 *jl) {
     constexpr int NC = (NT + 1) / 2;
     const int n = a.n;
@@ -186,7 +205,10 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0, co
             for (int mu = 0; mu < D; ++mu) x[I][mu][v] = ok ? a.x[((size_t)p * r + rep) * D + mu] : 0.0f;
         }
 
-    const float base = valid ? fmaf(a.dt, a.pump[rep] - 1.0f, 1.0f) : 0.0f;  // 1 + dt (r_i - 1)
+    // 1 + dt (r_i - 1); for the map the constant (1 - loss)(1 - b), and its pump h
+    const float base = valid ? (MAP ? a.c0 : fmaf(a.dt, a.pump[rep] - 1.0f, 1.0f)) : 0.0f;
+    const float hmap = (MAP && valid) ? a.pump[rep] : 0.0f;
+    const float kl2 = a.kl * 1.44269504088896340736f;  // kl log2(e)
     const NegPair negk = neg_pair();
     const float nbd = -(a.dt * a.btil);
     const float ned = -(a.dt * a.eta);
@@ -223,6 +245,11 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0, co
                     if (I < NT) {
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
+                            if constexpr (MAP) {
+#pragma unroll
+                                for (int mu = 0; mu < D; ++mu)
+                                    x[I][mu][v] = nlm_gain(x[I][mu][v], hmap, kl2) * x[I][mu][v];
+                            }
                             float x2[D];
 #pragma unroll
                             for (int mu = 0; mu < D; ++mu) x2[mu] = x[I][mu][v] * x[I][mu][v];
@@ -296,12 +323,12 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0, co
 }
 
 // One problem: wavefront w of the grid integrates replicas 16 w .. 16 w + 15.
-template <int NT, int D, int XS, int JS>
+template <int NT, int D, int XS, int JS, bool MAP = false>
 __global__ __launch_bounds__(256) void k_integrate_resident(IntegArgs a) {
     const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int rep0 = wave * 16;
     if (rep0 >= a.r) return;
-    integrate_group<NT, D, XS, JS, false>(a, rep0, nullptr);
+    integrate_group<NT, D, XS, JS, false, MAP>(a, rep0, nullptr);
 }
 
 // Many problems of one variant: a persistent grid whose wavefronts pop work
@@ -366,6 +393,7 @@ struct KernelSet {
     void (*persistent_lds)(const IntegArgs *, const int2 *, int, int *);   // two wavefronts per SIMD
     void (*persistent_lds1)(const IntegArgs *, const int2 *, int, int *);  // one wavefront per SIMD
     size_t lds_bytes;
+    void (*single_map)(IntegArgs);  // round-trip map form (single coupling term only)
 };
 
 // Largest row-tile count per (d, xs, js) that compiles without scratch
@@ -383,9 +411,10 @@ KernelSet variant_or_null() {
     if constexpr (NT <= resident_max_tiles(D, XS, JS))
         return KernelSet{k_integrate_resident<NT, D, XS, JS>, k_integrate_persistent<NT, D, XS, JS>,
                          k_integrate_persistent_lds<NT, D, XS, JS, 2>, k_integrate_persistent_lds<NT, D, XS, JS, 1>,
-                         lds_j_bytes<NT, JS>()};
+                         lds_j_bytes<NT, JS>(),
+                         (JS == 1 && NT <= kMapMaxTiles) ? k_integrate_resident<NT, D, XS, JS, true> : nullptr};
     else
-        return KernelSet{nullptr, nullptr, nullptr, nullptr, 0};
+        return KernelSet{nullptr, nullptr, nullptr, nullptr, 0, nullptr};
 }
 
 // One translation unit per (D, XS, JS) instantiates all tile counts.
@@ -404,7 +433,7 @@ KernelSet lookup_tiles(int tiles) {
         case 10: return variant_or_null<10, D, XS, JS>();
         case 11: return variant_or_null<11, D, XS, JS>();
         case 12: return variant_or_null<12, D, XS, JS>();
-        default: return KernelSet{nullptr, nullptr, nullptr, nullptr, 0};
+        default: return KernelSet{nullptr, nullptr, nullptr, nullptr, 0, nullptr};
     }
 }
 

@@ -191,3 +191,24 @@ def test_coupling_storage_sizes_and_quantizer_validation():
         # the new storages pass validation and stop at the missing device
         rc = lib.chym_integrate(ctypes.byref(_prob(j_dtype=jt)), ctypes.byref(_run()), None)
         assert rc == L.CHYM_ENODEV
+
+
+def test_map_entry_point_validates_before_device():
+    lib = L.load()
+
+    def mp(**kw):
+        base = dict(n=16, d=2, j_dtype=L.CHYM_J_I8, reserved=0, j=0x1000, b=0.01, loss=0.01, kl=0.1, beta_b2=25.0,
+                    jmag=1.0, reserved_f=0.0)
+        base.update(kw)
+        return L.ChymMapProblem(**base)
+
+    run1 = _run(dt=1.0)
+    for kw, code in (({"b": 0.0}, L.CHYM_EINVAL), ({"b": 1.0}, L.CHYM_EINVAL), ({"loss": 1.0}, L.CHYM_EINVAL),
+                     ({"kl": 0.0}, L.CHYM_EINVAL), ({"beta_b2": -1.0}, L.CHYM_EINVAL), ({"n": 0}, L.CHYM_EINVAL),
+                     ({"d": 5}, L.CHYM_EINVAL), ({"j": None}, L.CHYM_EINVAL), ({"reserved_f": 1.0}, L.CHYM_EINVAL),
+                     ({"j_dtype": L.CHYM_J_F32}, L.CHYM_EUNSUPPORTED), ({"n": 113}, L.CHYM_EUNSUPPORTED)):
+        assert lib.chym_map_integrate(ctypes.byref(mp(**kw)), ctypes.byref(run1), None) == code, kw
+    # one round trip per step
+    assert lib.chym_map_integrate(ctypes.byref(mp()), ctypes.byref(_run(dt=0.5)), None) == L.CHYM_EINVAL
+    assert "dt must be 1" in lib.chym_last_error().decode()
+    assert lib.chym_map_integrate(None, ctypes.byref(run1), None) == L.CHYM_EINVAL
