@@ -75,6 +75,11 @@ extern "C" {
                          is exact in bf16 (and float32) as long as it is zero or at least 2^-126 in
                          magnitude, so the contraction sees the stored J exactly.  E4M3 0x7f / 0xff
                          and E8M0 0xff decode to NaN.  chym_quantize_fp8() writes this format. */
+#define CHYM_J_ELL 4  /* sparse rows (ELL), int32 [n + 1][2 w]: row 0 = {n, w, 0, ...}; row p + 1 = w columns
+                         q, then the w couplings J_pq as float32 bit patterns (pad unused entries with
+                         coupling 0); columns outside [0, n) are ignored.  8 w (n + 1) bytes.  Integrated
+                         by a gather kernel in float32 (both precision forms), n <= 4096; not for
+                         batches, plans, features or the map. */
 
 /* arithmetic of the J x contraction (the state and every other step are float32) */
 #define CHYM_PREC_F32 0  /* x fed to the matrix cores as an exact sum of three bf16 terms

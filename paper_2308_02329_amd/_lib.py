@@ -20,6 +20,7 @@ CHYM_J_I8 = 0
 CHYM_J_F32 = 1
 CHYM_J_BF16 = 2
 CHYM_J_FP8 = 3
+CHYM_J_ELL = 4
 CHYM_PREC_F32 = 0
 CHYM_PREC_BF16 = 1
 

@@ -12,13 +12,13 @@ import ctypes
 import torch
 
 from . import _lib as L
-from ._lib import (CHYM_J_BF16, CHYM_J_F32, CHYM_J_FP8, CHYM_J_I8, CHYM_KERNEL_AUTO, CHYM_KERNEL_LDSJ, CHYM_KERNEL_LDSJ1, CHYM_KERNEL_REGJ,
+from ._lib import (CHYM_J_BF16, CHYM_J_ELL, CHYM_J_F32, CHYM_J_FP8, CHYM_J_I8, CHYM_KERNEL_AUTO, CHYM_KERNEL_LDSJ, CHYM_KERNEL_LDSJ1, CHYM_KERNEL_REGJ,
                    CHYM_PREC_BF16, CHYM_PREC_F32, ChymError, ChymOut, ChymPlanEntry, ChymProblem, ChymRun)
 
 __all__ = ["chym_sign_words", "chym_features", "chym_mlp_forward", "chym_mlp_backward", "chym_mlp_adam",
            "chym_mlp_scratch_floats", "chym_to_bf16", "chym_integrate_workspace_size", "chym_version", "chym_last_error", "chym_integrate", "chym_readout", "chym_ising_energy",
            "chym_hs_energy", "chym_solve", "make_problem", "make_run", "spin_words", "ChymError",
-           "CHYM_J_I8", "CHYM_J_F32", "CHYM_J_BF16", "CHYM_J_FP8", "chym_map_integrate", "j_size", "chym_j_bytes", "chym_quantize_fp8", "CHYM_PREC_F32", "CHYM_PREC_BF16", "precision_code",
+           "CHYM_J_I8", "CHYM_J_F32", "CHYM_J_BF16", "CHYM_J_FP8", "CHYM_J_ELL", "ell_pack", "chym_map_integrate", "j_size", "chym_j_bytes", "chym_quantize_fp8", "CHYM_PREC_F32", "CHYM_PREC_BF16", "precision_code",
            "chym_batch_workspace_size", "chym_batch_create", "chym_batch_launch", "chym_batch_launch_nograph",
            "chym_batch_destroy", "ChymBatch", "chym_plan_set", "chym_plan_get", "chym_plan_autotune",
            "chym_plan_save", "chym_plan_load", "chym_split3_bf16", "CHYM_KERNEL_REGJ", "CHYM_KERNEL_LDSJ",
@@ -59,23 +59,54 @@ def _need(t, name, dtype, shape=None):
 
 
 def _jdtype(J) -> int:
-    """Storage type of J: int8 [n, n], float32 [n, n], bfloat16 [n, n], or
-    uint8 [n + 1, n] for FP8 (E4M3 rows, then the row of E8M0 exponents)."""
+    """Storage type of J: int8 [n, n], float32 [n, n], bfloat16 [n, n], uint8
+    [n + 1, n] for FP8 (E4M3 rows, then the row of E8M0 exponents), or int32
+    [n + 1, 2 w] for sparse rows (ELL, see ell_pack)."""
     t = {torch.int8: CHYM_J_I8, torch.float32: CHYM_J_F32, torch.bfloat16: CHYM_J_BF16,
-         torch.uint8: CHYM_J_FP8}.get(J.dtype)
+         torch.uint8: CHYM_J_FP8, torch.int32: CHYM_J_ELL}.get(J.dtype)
     if t is None:
-        raise TypeError("J must be int8, float32, bfloat16 or uint8 (FP8 with row exponents)")
+        raise TypeError("J must be int8, float32, bfloat16, uint8 (FP8 with row exponents) or int32 (ELL)")
     return t
 
 
 def j_size(J) -> int:
     """Hyperspin count n of a coupling tensor in any storage type."""
-    return int(J.shape[1])
+    return int(J.shape[0] - 1) if J.dtype == torch.int32 else int(J.shape[1])
 
 
 def _need_j(J, n):
+    if J.dtype == torch.int32:
+        if J.ndim != 2 or J.shape[0] != n + 1 or J.shape[1] < 2 or J.shape[1] % 2:
+            raise ValueError(f"sparse J must be int32 [{n + 1}, 2 w], got {tuple(J.shape)}")
+        return _need(J, "J", J.dtype)
     shape = (n + 1, n) if J.dtype == torch.uint8 else (n, n)
     return _need(J, "J", J.dtype, shape)
+
+
+def ell_pack(J, width=None):
+    """Host packing of a dense coupling matrix into the sparse-row (ELL)
+    storage: int32 [n + 1, 2 w], row 0 = (n, w, 0, ...), row p + 1 = the
+    nonzero columns of row p in ascending order, then their couplings as
+    float32 bit patterns; rows with fewer than w nonzeros are padded with
+    column p and coupling 0.  Returns a numpy array."""
+    import numpy as np
+
+    J = np.asarray(J)
+    n = J.shape[0]
+    nz = [np.flatnonzero(J[p]) for p in range(n)]
+    w = max(1, max((len(c) for c in nz), default=1)) if width is None else int(width)
+    if any(len(c) > w for c in nz):
+        raise ValueError("a row has more nonzeros than the width")
+    out = np.zeros((n + 1, 2 * w), dtype=np.int32)
+    out[0, 0], out[0, 1] = n, w
+    for p, c in enumerate(nz):
+        cols = np.full(w, p, dtype=np.int32)
+        vals = np.zeros(w, dtype=np.float32)
+        cols[:len(c)] = c
+        vals[:len(c)] = J[p, c].astype(np.float32)
+        out[p + 1, :w] = cols
+        out[p + 1, w:] = vals.view(np.int32)
+    return out
 
 
 def make_problem(J, d: int, eps: float, btil: float, eta: float) -> ChymProblem:

@@ -53,14 +53,19 @@ int check_device() {
 
 bool finite(float v) { return isfinite(v); }
 
+// dense storages
 bool valid_jdtype(int t) { return t == CHYM_J_I8 || t == CHYM_J_F32 || t == CHYM_J_BF16 || t == CHYM_J_FP8; }
+// dense or sparse rows
+bool valid_jdtype_any(int t) { return valid_jdtype(t) || t == CHYM_J_ELL; }
+constexpr int kEllMaxN = 4096;
 
 int validate_problem(const chym_problem *p) {
     if (!p) return fail(CHYM_EINVAL, "problem is NULL");
     if (p->n < 1) return fail(CHYM_EINVAL, "n = %d must be >= 1", p->n);
     if (p->d < 1 || p->d > 4) return fail(CHYM_EINVAL, "d = %d must be in 1..4", p->d);
-    if (!valid_jdtype(p->j_dtype))
-        return fail(CHYM_EINVAL, "j_dtype = %d is not CHYM_J_I8, CHYM_J_F32, CHYM_J_BF16 or CHYM_J_FP8", p->j_dtype);
+    if (!valid_jdtype_any(p->j_dtype))
+        return fail(CHYM_EINVAL, "j_dtype = %d is not CHYM_J_I8, CHYM_J_F32, CHYM_J_BF16, CHYM_J_FP8 or CHYM_J_ELL",
+                    p->j_dtype);
     if (!p->j) return fail(CHYM_EINVAL, "J is NULL");
     if (p->reserved != 0 || p->reserved_f != 0.0f) return fail(CHYM_EINVAL, "reserved fields must be 0");
     if (!finite(p->eps) || !finite(p->btil) || !finite(p->eta))
@@ -101,6 +106,7 @@ Variant make_variant(int n, int d, int precision, int j_dtype) {
 }
 
 Variant variant_of(const chym_problem *p, const chym_run *r) {
+    if (p->j_dtype == CHYM_J_ELL) return Variant{(p->n + 15) / 16, 1, 1, false};  // gather kernel, no staging
     return make_variant(p->n, p->d, r->precision, p->j_dtype);
 }
 
@@ -130,6 +136,11 @@ chym::IntegArgs make_args(const chym_problem *prob, const chym_run *run) {
 }
 
 int check_variant(const chym_problem *prob, const chym_run *run) {
+    if (prob->j_dtype == CHYM_J_ELL) {
+        if (prob->n > kEllMaxN || chym::ell_replicas_per_block(prob->n, prob->d) == 0)
+            return fail(CHYM_EUNSUPPORTED, "sparse couplings: n = %d must be <= %d", prob->n, kEllMaxN);
+        return CHYM_OK;
+    }
     const Variant v = variant_of(prob, run);
     if (v.slab && !chym::slab_variant_exists(v.tiles, prob->d, v.xs, v.js))
         return fail(CHYM_EUNSUPPORTED,
@@ -156,6 +167,11 @@ int integrate_impl(const chym_problem *prob, const chym_run *run, hipStream_t st
     rc = check_device();
     if (rc) return rc;
     const chym::IntegArgs a = make_args(prob, run);
+    if (prob->j_dtype == CHYM_J_ELL) {
+        hipError_t e = chym::launch_integrate_ell(a, stream);
+        if (e != hipSuccess) return hip_fail(e, "sparse integrate launch");
+        return CHYM_OK;
+    }
     if (v.slab) {
         hipError_t e = chym::launch_stage_jfrag(a, v.js, ws, stream);
         if (e == hipSuccess) e = chym::launch_integrate_slab(v.tiles, prob->d, v.xs, v.js, a, ws, stream);
@@ -180,7 +196,7 @@ int validate_sizes(int32_t n, int32_t d, int32_t r) {
 int validate_energy(int32_t n, int32_t r, const void *j, int32_t j_dtype, const uint64_t *spins, int32_t *e_i32) {
     if (n < 1 || r < 1) return fail(CHYM_EINVAL, "n and r must be >= 1");
     if (n > 2048) return fail(CHYM_EUNSUPPORTED, "n = %d > 2048", n);
-    if (!valid_jdtype(j_dtype)) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
+    if (!valid_jdtype_any(j_dtype)) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
     if (!j || !spins) return fail(CHYM_EINVAL, "J and spins must not be NULL");
     if (e_i32 && j_dtype != CHYM_J_I8) return fail(CHYM_EINVAL, "int32 energy needs integer J (CHYM_J_I8)");
     return CHYM_OK;
@@ -190,7 +206,7 @@ int validate_hs(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dtype,
     int rc = validate_sizes(n, d, r);
     if (rc) return rc;
     if (n > 2048 || n * d > 8192) return fail(CHYM_EUNSUPPORTED, "hyperspin energy needs n <= 2048, n*d <= 8192");
-    if (!valid_jdtype(j_dtype)) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
+    if (!valid_jdtype_any(j_dtype)) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
     if (!j || !x) return fail(CHYM_EINVAL, "J and x must not be NULL");
     return CHYM_OK;
 }
@@ -296,6 +312,8 @@ int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
         int rc = validate_problem(&tk.prob);
         if (!rc) rc = validate_run(&tk.run);
         if (!rc) rc = check_variant(&tk.prob, &tk.run);
+        if (!rc && tk.prob.j_dtype == CHYM_J_ELL)
+            rc = fail(CHYM_EUNSUPPORTED, "sparse couplings are not batched (use chym_integrate / chym_solve)");
         if (!rc) rc = validate_out(&tk.prob, &tk.run, &tk.out);
         if (rc) {
             std::string m = g_err;
@@ -479,6 +497,7 @@ int chym_map_integrate(const chym_map_problem *m, const chym_run *run, chym_stre
     if (!m) return fail(CHYM_EINVAL, "problem is NULL");
     if (m->n < 1) return fail(CHYM_EINVAL, "n = %d must be >= 1", m->n);
     if (m->d < 1 || m->d > 4) return fail(CHYM_EINVAL, "d = %d must be in 1..4", m->d);
+    if (m->j_dtype == CHYM_J_ELL) return fail(CHYM_EUNSUPPORTED, "the map form takes dense couplings");
     if (!valid_jdtype(m->j_dtype)) return fail(CHYM_EINVAL, "bad j_dtype %d", m->j_dtype);
     if (!m->j) return fail(CHYM_EINVAL, "J is NULL");
     if (m->reserved != 0 || m->reserved_f != 0.0f) return fail(CHYM_EINVAL, "reserved fields must be 0");
@@ -968,6 +987,7 @@ int chym_plan_autotune(int32_t n, int32_t d, int32_t precision, int32_t j_dtype,
 int chym_j_bytes(int32_t n, int32_t j_dtype, size_t *bytes) {
     if (!bytes) return fail(CHYM_EINVAL, "bytes is NULL");
     if (n < 1) return fail(CHYM_EINVAL, "n = %d must be >= 1", n);
+    if (j_dtype == CHYM_J_ELL) return fail(CHYM_EINVAL, "sparse couplings take 8 w (n + 1) bytes for row width w");
     if (!valid_jdtype(j_dtype)) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
     const size_t nn = (size_t)n * n;
     switch (j_dtype) {
@@ -1017,6 +1037,7 @@ int chym_features(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dtyp
     int rc = validate_sizes(n, d, r);
     if (rc) return rc;
     if ((long long)n * (d + 1) > 8192) return fail(CHYM_EUNSUPPORTED, "features need n * (d + 1) <= 8192");
+    if (j_dtype == CHYM_J_ELL) return fail(CHYM_EUNSUPPORTED, "features take dense couplings");
     if (!valid_jdtype(j_dtype)) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
     if (!j || !x || !prev_words || !features) return fail(CHYM_EINVAL, "pointers must not be NULL");
     if (checkpoint < 0 || 4 * checkpoint + 4 > CHYM_FEATURES)

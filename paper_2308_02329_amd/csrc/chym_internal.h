@@ -64,6 +64,19 @@ __device__ __forceinline__ int e4m3_row_exponent(float amax) {
     return e;
 }
 
+// Sparse (ELL) couplings, int32 [n + 1][2 w]: row 0 = {n, w, ...}; row p + 1
+// = w columns, then w float32 couplings (bit patterns).
+struct EllView {
+    const int *rows;
+    int w;
+    __device__ __forceinline__ const int *row(int p) const { return rows + (size_t)(p + 1) * 2 * w; }
+};
+// A header that does not describe an n-row matrix reads as no couplings.
+__device__ __forceinline__ EllView ell_view(const void *j, int n) {
+    const int *h = reinterpret_cast<const int *>(j);
+    return EllView{h, (h[0] == n && h[1] > 0) ? h[1] : 0};
+}
+
 // Coupling J_pq of an n x n matrix stored as j_dtype, as float (exact for
 // every storage type but float32 input, where it is the stored value).
 __device__ __forceinline__ float coupling(const void *j, int j_dtype, int n, int p, int q) {
@@ -119,6 +132,10 @@ hipError_t persistent_occupancy(int tiles, int d, int xs, int js, int kind, int 
 hipError_t launch_zero_counters(int *counters, int n, hipStream_t stream);
 // Synthetic timing problem for the autotuner.
 hipError_t launch_quantize_fp8(int n, const float *j, uint8_t *out, hipStream_t stream);
+// Sparse (ELL) couplings: replicas per block for n, d (0 if n is too large),
+// and the gather integrator.
+int ell_replicas_per_block(int n, int d);
+hipError_t launch_integrate_ell(const IntegArgs &a, hipStream_t stream);
 hipError_t launch_fill_probe(void *j, int j_dtype, int n, float *pump, int r, float *alpha, int na,
                              hipStream_t stream);
 hipError_t launch_fill_state(float *x, size_t nx, hipStream_t stream);

@@ -66,7 +66,22 @@ __device__ void ising_one(int n, int rep, const void *__restrict__ j, int j_dtyp
     const int lane = threadIdx.x & 63;
     const int w = (n + 63) >> 6;
     const uint64_t *s = spins + (size_t)rep * w;
-    if (j_dtype == CHYM_J_I8) {
+    if (j_dtype == CHYM_J_ELL) {
+        // lanes own rows p: E = -sum_p sigma_p sum_k val[p][k] sigma_{col[p][k]}
+        const EllView e = ell_view(j, n);
+        double acc = 0.0;
+        for (int p = lane; p < n; p += 64) {
+            const int *row = e.row(p);
+            double h = 0.0;
+            for (int k = 0; k < e.w; ++k) {
+                const int q = row[k];
+                if ((unsigned)q < (unsigned)n) h += (double)__int_as_float(row[e.w + k]) * (double)spin_of(s, q);
+            }
+            acc += (double)spin_of(s, p) * h;
+        }
+        acc = wave_sum(acc);
+        if (lane == 0 && e_f64) e_f64[rep] = -acc;
+    } else if (j_dtype == CHYM_J_I8) {
         const int8_t *J = reinterpret_cast<const int8_t *>(j);
         int acc = 0;
         for (int q = lane; q < n; q += 64) {
@@ -120,15 +135,31 @@ __device__ void hs_one(int n, int d, int r, int rep, const void *__restrict__ j,
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     double acc = 0.0;
-    for (int q = lane; q < n; q += 64) {
-        double h = 0.0;
-        for (int p = 0; p < n; ++p) {
-            double dot = 0.0;
-            for (int mu = 0; mu < d; ++mu) dot = dot + u[p * d + mu] * u[q * d + mu];
-            const double jv = (double)coupling(j, j_dtype, n, p, q);
-            h = h + jv * dot;
+    if (j_dtype == CHYM_J_ELL) {
+        const EllView e = ell_view(j, n);
+        for (int p = lane; p < n; p += 64) {
+            const int *row = e.row(p);
+            double h = 0.0;
+            for (int k = 0; k < e.w; ++k) {
+                const int q = row[k];
+                if ((unsigned)q >= (unsigned)n) continue;
+                double dot = 0.0;
+                for (int mu = 0; mu < d; ++mu) dot = dot + u[p * d + mu] * u[q * d + mu];
+                h = h + (double)__int_as_float(row[e.w + k]) * dot;
+            }
+            acc += h;
         }
-        acc += h;
+    } else {
+        for (int q = lane; q < n; q += 64) {
+            double h = 0.0;
+            for (int p = 0; p < n; ++p) {
+                double dot = 0.0;
+                for (int mu = 0; mu < d; ++mu) dot = dot + u[p * d + mu] * u[q * d + mu];
+                const double jv = (double)coupling(j, j_dtype, n, p, q);
+                h = h + jv * dot;
+            }
+            acc += h;
+        }
     }
     acc = wave_sum(acc);
     if (lane == 0) e_hs[rep] = -acc;
