@@ -10,20 +10,25 @@
 // continuous limit into the other buffer; one block barrier per step.
 // Units are ordered row-major with the replica fastest, so the lanes of a
 // wavefront read the same coupling row (broadcast) and contiguous state.
+// Blocks of 1024 threads (sixteen wavefronts per CU cover the LDS latency);
+// the coupling rows and the block's pumps are staged in LDS too when the
+// rows fit a fixed budget (read from global memory otherwise).
 #include "chym_internal.h"
 
 namespace chym {
 
 constexpr size_t kEllMaxLds = 159 * 1024;
+constexpr size_t kEllRowBudget = 32 * 1024;  // LDS for the coupling rows
+constexpr int kEllThreads = 1024;
 
 int ell_replicas_per_block(int n, int d) {
     for (int rb = 16; rb >= 1; rb >>= 1)
-        if (2 * (size_t)n * rb * d * sizeof(float) <= kEllMaxLds) return rb;
+        if (2 * (size_t)n * rb * d * sizeof(float) + kEllRowBudget + 64 <= kEllMaxLds) return rb;
     return 0;
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_integrate_ell(IntegArgs a, int lrb) {
+__global__ __launch_bounds__(kEllThreads) void k_integrate_ell(IntegArgs a, int lrb) {
     extern __shared__ __align__(16) float sm[];
     const int n = a.n;
     const int r = a.r;
@@ -32,7 +37,15 @@ __global__ __launch_bounds__(256) void k_integrate_ell(IntegArgs a, int lrb) {
     const int units = n << lrb;
     float *xa = sm;
     float *xb = sm + (size_t)units * D;
+    float *pl = xb + (size_t)units * D;                  // pumps of the block's replicas [16]
+    int *rl = reinterpret_cast<int *>(pl + 16);          // coupling rows [n][2 w], if they fit
     const EllView e = ell_view(a.j, n);
+    const bool staged = (size_t)n * 2 * e.w * sizeof(int) <= kEllRowBudget;
+    if (staged) {
+        const int *src = e.row(0);
+        for (int i = threadIdx.x; i < n * 2 * e.w; i += blockDim.x) rl[i] = src[i];
+    }
+    if (threadIdx.x < rb) pl[threadIdx.x] = rep0 + (int)threadIdx.x < r ? a.pump[rep0 + threadIdx.x] : 1.0f;
 
     for (int u = threadIdx.x; u < units; u += blockDim.x) {
         const int p = u >> lrb;
@@ -50,18 +63,17 @@ __global__ __launch_bounds__(256) void k_integrate_ell(IntegArgs a, int lrb) {
         float ga[D];
 #pragma unroll
         for (int mu = 0; mu < D; ++mu) ga[mu] = dte * al[mu];
-        for (int u = threadIdx.x; u < units; u += blockDim.x) {
-            const int p = u >> lrb;
+        // one (row, replica) unit; row = its coupling row (LDS or global)
+        auto unit = [&](int u, const int *__restrict__ row) __attribute__((always_inline)) {
             const int jr = u & (rb - 1);
             const int rep = rep0 + jr;
-            const float base = rep < r ? fmaf(a.dt, a.pump[rep] - 1.0f, 1.0f) : 0.0f;  // 1 + dt (r_i - 1)
+            const float base = rep < r ? fmaf(a.dt, pl[jr] - 1.0f, 1.0f) : 0.0f;  // 1 + dt (r_i - 1)
             float xv[D], G[D];
 #pragma unroll
             for (int mu = 0; mu < D; ++mu) {
                 xv[mu] = xa[u * D + mu];
                 G[mu] = 0.0f;
             }
-            const int *row = e.row(p);
             for (int kk = 0; kk < e.w; ++kk) {
                 const int q = row[kk];
                 if ((unsigned)q < (unsigned)n) {
@@ -83,6 +95,11 @@ __global__ __launch_bounds__(256) void k_integrate_ell(IntegArgs a, int lrb) {
                 const float y = xv[mu] * fmaf(ned, x2[mu], cc);
                 xb[u * D + mu] = fmaf(ga[mu], G[mu], y);
             }
+        };
+        if (staged) {
+            for (int u = threadIdx.x; u < units; u += blockDim.x) unit(u, rl + (size_t)(u >> lrb) * 2 * e.w);
+        } else {
+            for (int u = threadIdx.x; u < units; u += blockDim.x) unit(u, e.row(u >> lrb));
         }
         __syncthreads();
         float *t = xa;
@@ -105,7 +122,7 @@ hipError_t launch_integrate_ell(const IntegArgs &a, hipStream_t stream) {
     if (rb == 0) return hipErrorInvalidValue;
     int lrb = 0;
     while ((1 << lrb) < rb) ++lrb;
-    const size_t lds = 2 * (size_t)a.n * rb * a.d * sizeof(float);
+    const size_t lds = 2 * (size_t)a.n * rb * a.d * sizeof(float) + 16 * sizeof(float) + kEllRowBudget;
     const int blocks = (a.r + rb - 1) / rb;
     void (*fn)(IntegArgs, int) = a.d == 1 ? k_integrate_ell<1>
                                  : a.d == 2 ? k_integrate_ell<2>
@@ -116,7 +133,7 @@ hipError_t launch_integrate_ell(const IntegArgs &a, hipStream_t stream) {
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), lds, stream, a, lrb);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kEllThreads), lds, stream, a, lrb);
     return hipGetLastError();
 }
 
