@@ -191,6 +191,23 @@ typedef struct chym_map_problem {
 
 int chym_map_integrate(const chym_map_problem *prob, const chym_run *run, chym_stream_t stream);
 
+/* Many map problems, one persistent launch per kernel variant (row tiles,
+ * d, precision).  Paper: the statistics are gathered over N_g graphs x N_s
+ * pump values x N_r repetitions of the map, all independent (statistics
+ * paragraph, Figs. 3-4).  Each problem t is chym_map_integrate(&probs[t],
+ * &runs[t]); results are bit-identical to it.  The workspace (device, 256-byte
+ * aligned, size from chym_map_batch_workspace_size) receives the task table,
+ * the work list of (task, 16-replica group) items, longest run first, and
+ * one work counter per variant.  The host tables are copied on `stream`,
+ * which is synchronized once before the launches are queued; the launches
+ * then run asynchronously.  Calls that share a workspace must not overlap.
+ * Errors name the offending task; nothing is launched if any task is
+ * invalid. */
+int chym_map_batch_workspace_size(const chym_map_problem *probs, const chym_run *runs, int32_t n_tasks,
+                                  size_t *bytes);
+int chym_map_batch(const chym_map_problem *probs, const chym_run *runs, int32_t n_tasks, void *workspace,
+                   size_t ws_bytes, chym_stream_t stream);
+
 /* Sign readout of x (paper: the Ising spins are read at the end of a run).
  * spins [r][ceil(n/64)], extra_frac [r], diverged [r]; each may be NULL. */
 int chym_readout(int32_t n, int32_t d, int32_t r, const float *x, uint64_t *spins,

@@ -32,7 +32,7 @@ EXPORTS = (
     "chym_plan_autotune_workspace_size", "chym_plan_autotune", "chym_split3_bf16", "chym_j_bytes", "chym_quantize_fp8", "chym_plan_save",
     "chym_plan_load", "chym_integrate_workspace_size", "chym_integrate_ws", "chym_solve_ws",
     "chym_sign_words", "chym_features", "chym_mlp_scratch_floats", "chym_mlp_forward", "chym_mlp_backward",
-    "chym_mlp_adam", "chym_to_bf16", "chym_map_integrate",
+    "chym_mlp_adam", "chym_to_bf16", "chym_map_integrate", "chym_map_batch_workspace_size", "chym_map_batch",
 )
 
 CHYM_FEATURES = 32
@@ -95,6 +95,11 @@ def load():
     lib.chym_integrate.restype = ctypes.c_int
     lib.chym_map_integrate.argtypes = [P(ChymMapProblem), P(ChymRun), _vp]
     lib.chym_map_integrate.restype = ctypes.c_int
+    lib.chym_map_batch_workspace_size.argtypes = [P(ChymMapProblem), P(ChymRun), ctypes.c_int32,
+                                                  P(ctypes.c_size_t)]
+    lib.chym_map_batch_workspace_size.restype = ctypes.c_int
+    lib.chym_map_batch.argtypes = [P(ChymMapProblem), P(ChymRun), ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+    lib.chym_map_batch.restype = ctypes.c_int
     lib.chym_readout.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp]
     lib.chym_readout.restype = ctypes.c_int
     lib.chym_ising_energy.argtypes = [_i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp]

@@ -192,6 +192,40 @@ def chym_map_integrate(J, h, A, alpha, *, b, loss, kl, beta_b2, jmag, steps, sta
     return A
 
 
+def _map_task(t: dict):
+    A = t["A"]
+    n, r, d = A.shape
+    _need_j(t["J"], n)
+    run = make_run(n, d, t["h"], A, t["alpha"], 1.0, t["steps"], t.get("start_step", 0),
+                   t.get("precision", CHYM_PREC_F32))
+    prob = L.ChymMapProblem(n=n, d=d, j_dtype=_jdtype(t["J"]), reserved=0, j=_vp(t["J"]), b=float(t["b"]),
+                            loss=float(t["loss"]), kl=float(t["kl"]), beta_b2=float(t["beta_b2"]),
+                            jmag=float(t["jmag"]), reserved_f=0.0)
+    return prob, run
+
+
+def chym_map_batch(tasks, stream=None):
+    """Many chym_map_integrate calls in one launch per kernel variant.  tasks:
+    dicts with the keyword arguments of chym_map_integrate (J, h, A, alpha, b,
+    loss, kl, beta_b2, jmag, steps, [start_step, precision]); every A is
+    advanced in place."""
+    lib = L.load()
+    pairs = [_map_task(t) for t in tasks]
+    probs = (L.ChymMapProblem * len(pairs))(*[p for p, _ in pairs])
+    runs = (L.ChymRun * len(pairs))(*[r for _, r in pairs])
+    nbytes = ctypes.c_size_t(0)
+    L.check(lib.chym_map_batch_workspace_size(probs, runs, len(pairs), ctypes.byref(nbytes)),
+            "chym_map_batch_workspace_size")
+    dev = tasks[0]["A"].device
+    ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    L.check(lib.chym_map_batch(probs, runs, len(pairs), ctypes.c_void_p(ws.data_ptr() + off), int(nbytes.value),
+                               _stream(stream)), "chym_map_batch")
+    if stream is not None:
+        ws.record_stream(stream)
+    return ws  # keep alive until the launches have run (torch's allocator orders reuse on its stream)
+
+
 def chym_readout(x, spins=None, extra_frac=None, diverged=None, stream=None):
     lib = L.load()
     n, r, d = x.shape

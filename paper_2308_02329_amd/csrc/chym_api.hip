@@ -477,23 +477,15 @@ void release(chym_batch *b) {
     delete b;
 }
 
-}  // namespace
+// ------------------------------------------------------- round-trip map
+struct MapTask {
+    chym::IntegArgs a;
+    int tiles, xs;
+};
 
-extern "C" {
-
-int chym_version(void) { return CHYM_VERSION; }
-
-const char *chym_last_error(void) { return g_err.c_str(); }
-
-int chym_integrate(const chym_problem *prob, const chym_run *run, chym_stream_t stream) {
-    int rc = validate_problem(prob);
-    if (rc) return rc;
-    rc = validate_run(run);
-    if (rc) return rc;
-    return integrate_impl(prob, run, (hipStream_t)stream);
-}
-
-int chym_map_integrate(const chym_map_problem *m, const chym_run *run, chym_stream_t stream) {
+// Validate one map problem and its run and fill the kernel arguments:
+// A' = (1 - loss) [(1 - b) B - beta_b2 B S(B)] + (1 - loss) b jmag alpha (J B),  B = K(A) A.
+int map_setup(const chym_map_problem *m, const chym_run *run, MapTask *t) {
     if (!m) return fail(CHYM_EINVAL, "problem is NULL");
     if (m->n < 1) return fail(CHYM_EINVAL, "n = %d must be >= 1", m->n);
     if (m->d < 1 || m->d > 4) return fail(CHYM_EINVAL, "d = %d must be in 1..4", m->d);
@@ -511,15 +503,12 @@ int chym_map_integrate(const chym_map_problem *m, const chym_run *run, chym_stre
     if (run->dt != 1.0f) return fail(CHYM_EINVAL, "the map takes one round trip per step: dt must be 1");
     if (m->j_dtype == CHYM_J_F32)
         return fail(CHYM_EUNSUPPORTED, "the map form takes couplings exact in one bf16 term (I8, BF16, FP8)");
-    const int tiles = (m->n + 15) / 16;
-    const int xs = run->precision == CHYM_PREC_F32 ? 3 : 1;
-    if (tiles > std::min(chym::resident_tile_limit(m->d, xs, 1), chym::kMapMaxTiles))
-        return fail(CHYM_EUNSUPPORTED, "the map form runs n <= %d (n = %d, d = %d)",
-                    16 * std::min(chym::resident_tile_limit(m->d, xs, 1), chym::kMapMaxTiles), m->n, m->d);
-    if (run->steps == 0) return CHYM_OK;
-    rc = check_device();
-    if (rc) return rc;
-    chym::IntegArgs a;
+    t->tiles = (m->n + 15) / 16;
+    t->xs = run->precision == CHYM_PREC_F32 ? 3 : 1;
+    const int limit = std::min(chym::resident_tile_limit(m->d, t->xs, 1), chym::kMapMaxTiles);
+    if (t->tiles > limit)
+        return fail(CHYM_EUNSUPPORTED, "the map form runs n <= %d (n = %d, d = %d)", 16 * limit, m->n, m->d);
+    chym::IntegArgs &a = t->a;
     a.j = m->j;
     a.pump = run->pump;
     a.x = run->x;
@@ -531,18 +520,143 @@ int chym_map_integrate(const chym_map_problem *m, const chym_run *run, chym_stre
     a.start_step = run->start_step;
     a.j_dtype = m->j_dtype;
     a.dt = 1.0f;
-    // A' = (1 - loss) [(1 - b) B - beta_b2 B S(B)] + (1 - loss) b jmag alpha (J B),  B = K(A) A
     a.eps = (1.0f - m->loss) * m->b * m->jmag;
     a.btil = (1.0f - m->loss) * m->beta_b2;
     a.eta = 0.0f;
     a.kl = m->kl;
     a.c0 = (1.0f - m->loss) * (1.0f - m->b);
+    return CHYM_OK;
+}
+
+struct MapGroup {
+    int tiles, d, xs, item_off, n_items;
+};
+
+struct MapBatchLayout {
+    std::vector<chym::IntegArgs> args;
+    std::vector<int2> items;  // (task, 16-replica group), grouped by variant, longest task first
+    std::vector<MapGroup> groups;
+    size_t off_tasks, off_items, off_counters, total;
+};
+
+int map_batch_layout(const chym_map_problem *probs, const chym_run *runs, int32_t n_tasks, MapBatchLayout *L) {
+    if (n_tasks < 1) return fail(CHYM_EINVAL, "n_tasks = %d must be >= 1", n_tasks);
+    if (!probs || !runs) return fail(CHYM_EINVAL, "problems or runs is NULL");
+    std::map<std::tuple<int, int, int>, std::vector<int2>> by_variant;  // (tiles, d, xs)
+    L->args.resize(n_tasks);
+    for (int t = 0; t < n_tasks; ++t) {
+        MapTask mt;
+        int rc = map_setup(&probs[t], &runs[t], &mt);
+        if (rc) {
+            std::string m = g_err;
+            return fail(rc, "task %d: %s", t, m.c_str());
+        }
+        L->args[t] = mt.a;
+        auto &lst = by_variant[std::make_tuple(mt.tiles, probs[t].d, mt.xs)];
+        if (runs[t].steps == 0) continue;
+        for (int g = 0; g < (runs[t].r + 15) / 16; ++g) lst.push_back(make_int2(t, g));
+    }
+    L->items.clear();
+    L->groups.clear();
+    for (auto &kv : by_variant) {
+        auto &lst = kv.second;
+        if (lst.empty()) continue;
+        std::stable_sort(lst.begin(), lst.end(),
+                         [&](const int2 &a, const int2 &b) { return runs[a.x].steps > runs[b.x].steps; });
+        MapGroup g{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), (int)L->items.size(),
+                   (int)lst.size()};
+        L->items.insert(L->items.end(), lst.begin(), lst.end());
+        L->groups.push_back(g);
+    }
+    L->off_tasks = 0;
+    L->off_items = align_up(sizeof(chym::IntegArgs) * (size_t)n_tasks);
+    L->off_counters = L->off_items + align_up(sizeof(int2) * std::max<size_t>(1, L->items.size()));
+    L->total = L->off_counters + align_up(sizeof(int) * std::max<size_t>(1, L->groups.size()));
+    return CHYM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chym_version(void) { return CHYM_VERSION; }
+
+const char *chym_last_error(void) { return g_err.c_str(); }
+
+int chym_integrate(const chym_problem *prob, const chym_run *run, chym_stream_t stream) {
+    int rc = validate_problem(prob);
+    if (rc) return rc;
+    rc = validate_run(run);
+    if (rc) return rc;
+    return integrate_impl(prob, run, (hipStream_t)stream);
+}
+
+int chym_map_integrate(const chym_map_problem *m, const chym_run *run, chym_stream_t stream) {
+    MapTask t;
+    int rc = map_setup(m, run, &t);
+    if (rc) return rc;
+    if (run->steps == 0) return CHYM_OK;
+    rc = check_device();
+    if (rc) return rc;
     bool supported = false;
-    hipError_t e = chym::launch_integrate_map(tiles, m->d, xs, default_waves_per_block(), a, (hipStream_t)stream,
-                                              &supported);
+    hipError_t e = chym::launch_integrate_map(t.tiles, m->d, t.xs, default_waves_per_block(), t.a,
+                                              (hipStream_t)stream, &supported);
     if (!supported) return fail(CHYM_EUNSUPPORTED, "no map variant for n = %d, d = %d", m->n, m->d);
     if (e != hipSuccess) return hip_fail(e, "map integrate launch");
     return CHYM_OK;
+}
+
+int chym_map_batch_workspace_size(const chym_map_problem *probs, const chym_run *runs, int32_t n_tasks,
+                                  size_t *bytes) {
+    if (!bytes) return fail(CHYM_EINVAL, "bytes is NULL");
+    *bytes = 0;
+    MapBatchLayout L;
+    int rc = map_batch_layout(probs, runs, n_tasks, &L);
+    if (rc) return rc;
+    *bytes = L.total;
+    return CHYM_OK;
+}
+
+int chym_map_batch(const chym_map_problem *probs, const chym_run *runs, int32_t n_tasks, void *workspace,
+                   size_t ws_bytes, chym_stream_t stream) {
+    MapBatchLayout L;
+    int rc = map_batch_layout(probs, runs, n_tasks, &L);
+    if (rc) return rc;
+    if (L.items.empty()) return CHYM_OK;
+    if (!workspace) return fail(CHYM_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % kAlign) return fail(CHYM_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+    if (ws_bytes < L.total) return fail(CHYM_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+    rc = check_device();
+    if (rc) return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    char *ws = static_cast<char *>(workspace);
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // The host tables are temporaries: copy them on the stream and wait for
+    // the copy before they go out of scope.
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + L.off_tasks, L.args.data(), sizeof(chym::IntegArgs) * L.args.size(),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + L.off_items, L.items.data(), sizeof(int2) * L.items.size(), hipMemcpyHostToDevice,
+                           st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    int *counters = reinterpret_cast<int *>(ws + L.off_counters);
+    if (e == hipSuccess) e = chym::launch_zero_counters(counters, (int)L.groups.size(), st);
+    const chym::IntegArgs *tasks_d = reinterpret_cast<const chym::IntegArgs *>(ws + L.off_tasks);
+    const int2 *items_d = reinterpret_cast<const int2 *>(ws + L.off_items);
+    for (size_t gi = 0; gi < L.groups.size() && e == hipSuccess; ++gi) {
+        const MapGroup &g = L.groups[gi];
+        int per_cu = 0;
+        e = chym::map_persistent_occupancy(g.tiles, g.d, g.xs, &per_cu);
+        if (e != hipSuccess) break;
+        const int need = (g.n_items + kPersistentWaves - 1) / kPersistentWaves;
+        const int blocks = std::max(1, std::min(need, std::max(1, per_cu) * cus));
+        e = chym::launch_integrate_map_persistent(g.tiles, g.d, g.xs, blocks, tasks_d, items_d + g.item_off,
+                                                  g.n_items, counters + gi, st);
+    }
+    return e == hipSuccess ? CHYM_OK : hip_fail(e, "map batch launch");
 }
 
 int chym_readout(int32_t n, int32_t d, int32_t r, const float *x, uint64_t *spins, double *extra_frac,

@@ -121,6 +121,13 @@ hipError_t launch_integrate(int tiles, int d, int xs, int js, int waves_per_bloc
 constexpr int kMapMaxTiles = 7;
 hipError_t launch_integrate_map(int tiles, int d, int xs, int waves_per_block, const IntegArgs &a,
                                 hipStream_t stream, bool *supported);
+// Many map problems of one variant: a persistent grid of 256-thread blocks
+// whose wavefronts pop items (task, 16-replica group) from *counter (zero at
+// launch) until n_items are taken.
+bool map_variant_exists(int tiles, int d, int xs);
+hipError_t map_persistent_occupancy(int tiles, int d, int xs, int *blocks_per_cu);
+hipError_t launch_integrate_map_persistent(int tiles, int d, int xs, int blocks, const IntegArgs *tasks,
+                                           const int2 *items, int n_items, int *counter, hipStream_t stream);
 bool integrate_variant_exists(int tiles, int d, int xs, int js);
 // Persistent kernel kinds: J gathered into each wavefront's registers, work
 // items of 16 replicas; or J staged in LDS per block, work items of
@@ -130,12 +137,13 @@ constexpr int kKernelLdsJ = 1;   // two wavefronts per SIMD
 constexpr int kKernelLdsJ1 = 2;  // one wavefront per SIMD
 hipError_t persistent_occupancy(int tiles, int d, int xs, int js, int kind, int waves_per_block, int *blocks_per_cu);
 hipError_t launch_zero_counters(int *counters, int n, hipStream_t stream);
-// Synthetic timing problem for the autotuner.
+// FP8 (E4M3 + per-row power-of-two) packing of a float32 coupling matrix.
 hipError_t launch_quantize_fp8(int n, const float *j, uint8_t *out, hipStream_t stream);
 // Sparse (ELL) couplings: replicas per block for n, d (0 if n is too large),
 // and the gather integrator.
 int ell_replicas_per_block(int n, int d);
 hipError_t launch_integrate_ell(const IntegArgs &a, hipStream_t stream);
+// Synthetic timing problem for the autotuner.
 hipError_t launch_fill_probe(void *j, int j_dtype, int n, float *pump, int r, float *alpha, int na,
                              hipStream_t stream);
 hipError_t launch_fill_state(float *x, size_t nx, hipStream_t stream);

@@ -13,7 +13,7 @@ static KernelFn lookup(int tiles, int d, int xs, int js) {
     CHYM_PICK(3, 3, 1) CHYM_PICK(3, 1, 1) CHYM_PICK(3, 3, 3)
     CHYM_PICK(4, 3, 1) CHYM_PICK(4, 1, 1) CHYM_PICK(4, 3, 3)
 #undef CHYM_PICK
-    return KernelSet{nullptr, nullptr, nullptr, nullptr, 0, nullptr};
+    return KernelSet{nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr};
 }
 
 int resident_tile_limit(int d, int xs, int js) {
@@ -253,6 +253,23 @@ hipError_t launch_integrate_map(int tiles, int d, int xs, int waves_per_block, c
     const int reps_per_block = 16 * waves_per_block;
     const int blocks = (a.r + reps_per_block - 1) / reps_per_block;
     hipLaunchKernelGGL(fn.single_map, dim3(blocks), dim3(64 * waves_per_block), 0, stream, a);
+    return hipGetLastError();
+}
+
+bool map_variant_exists(int tiles, int d, int xs) { return lookup(tiles, d, xs, 1).persistent_map != nullptr; }
+
+hipError_t map_persistent_occupancy(int tiles, int d, int xs, int *blocks_per_cu) {
+    KernelFn fn = lookup(tiles, d, xs, 1);
+    *blocks_per_cu = 0;
+    if (!fn.persistent_map) return hipErrorInvalidDeviceFunction;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn.persistent_map, 256, 0);
+}
+
+hipError_t launch_integrate_map_persistent(int tiles, int d, int xs, int blocks, const IntegArgs *tasks,
+                                           const int2 *items, int n_items, int *counter, hipStream_t stream) {
+    KernelFn fn = lookup(tiles, d, xs, 1);
+    if (!fn.persistent_map) return hipErrorInvalidDeviceFunction;
+    hipLaunchKernelGGL(fn.persistent_map, dim3(blocks), dim3(256), 0, stream, tasks, items, n_items, counter);
     return hipGetLastError();
 }
 

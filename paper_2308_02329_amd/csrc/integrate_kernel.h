@@ -334,8 +334,9 @@ __global__ __launch_bounds__(256) void k_integrate_resident(IntegArgs a) {
 // Many problems of one variant: a persistent grid whose wavefronts pop work
 // items (problem, 16-replica group) from a counter until the list is empty.
 // Items are listed longest first by the host.  The counter must be zero at
-// launch; the host zeroes it with k_zero_counters in the same stream.
-template <int NT, int D, int XS, int JS>
+// launch; the host zeroes it with k_zero_counters in the same stream.  MAP
+// selects the round-trip map of Eq. (2) instead of its continuous limit.
+template <int NT, int D, int XS, int JS, bool MAP = false>
 __global__ __launch_bounds__(256) void k_integrate_persistent(const IntegArgs *__restrict__ tasks,
                                                               const int2 *__restrict__ items, int n_items,
                                                               int *__restrict__ counter) {
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(256) void k_integrate_persistent(const IntegArgs *_
         if (it >= n_items) break;
         const int2 w = items[it];
         const IntegArgs a = tasks[w.x];
-        integrate_group<NT, D, XS, JS, false>(a, w.y * 16, nullptr);
+        integrate_group<NT, D, XS, JS, false, MAP>(a, w.y * 16, nullptr);
     }
 }
 
@@ -394,6 +395,7 @@ struct KernelSet {
     void (*persistent_lds1)(const IntegArgs *, const int2 *, int, int *);  // one wavefront per SIMD
     size_t lds_bytes;
     void (*single_map)(IntegArgs);  // round-trip map form (single coupling term only)
+    void (*persistent_map)(const IntegArgs *, const int2 *, int, int *);  // same, many problems
 };
 
 // Largest row-tile count per (d, xs, js) that compiles without scratch
@@ -412,9 +414,10 @@ KernelSet variant_or_null() {
         return KernelSet{k_integrate_resident<NT, D, XS, JS>, k_integrate_persistent<NT, D, XS, JS>,
                          k_integrate_persistent_lds<NT, D, XS, JS, 2>, k_integrate_persistent_lds<NT, D, XS, JS, 1>,
                          lds_j_bytes<NT, JS>(),
-                         (JS == 1 && NT <= kMapMaxTiles) ? k_integrate_resident<NT, D, XS, JS, true> : nullptr};
+                         (JS == 1 && NT <= kMapMaxTiles) ? k_integrate_resident<NT, D, XS, JS, true> : nullptr,
+                         (JS == 1 && NT <= kMapMaxTiles) ? k_integrate_persistent<NT, D, XS, JS, true> : nullptr};
     else
-        return KernelSet{nullptr, nullptr, nullptr, nullptr, 0, nullptr};
+        return KernelSet{nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr};
 }
 
 // One translation unit per (D, XS, JS) instantiates all tile counts.
@@ -433,7 +436,7 @@ KernelSet lookup_tiles(int tiles) {
         case 10: return variant_or_null<10, D, XS, JS>();
         case 11: return variant_or_null<11, D, XS, JS>();
         case 12: return variant_or_null<12, D, XS, JS>();
-        default: return KernelSet{nullptr, nullptr, nullptr, nullptr, 0, nullptr};
+        default: return KernelSet{nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr};
     }
 }
 

@@ -214,6 +214,38 @@ def test_map_entry_point_validates_before_device():
     assert lib.chym_map_integrate(None, ctypes.byref(run1), None) == L.CHYM_EINVAL
 
 
+def test_map_batch_layout_and_validation():
+    lib = L.load()
+
+    def mp(**kw):
+        base = dict(n=40, d=2, j_dtype=L.CHYM_J_I8, reserved=0, j=0x1000, b=0.01, loss=0.01, kl=0.1, beta_b2=25.0,
+                    jmag=1.0, reserved_f=0.0)
+        base.update(kw)
+        return L.ChymMapProblem(**base)
+
+    probs = (L.ChymMapProblem * 3)(mp(), mp(n=16, d=1), mp(b=1.5))
+    runs = (L.ChymRun * 3)(_run(dt=1.0, r=40), _run(dt=1.0, r=17), _run(dt=1.0))
+    nbytes = ctypes.c_size_t(0)
+    assert lib.chym_map_batch_workspace_size(probs, runs, 3, ctypes.byref(nbytes)) == L.CHYM_EINVAL
+    assert "task 2" in lib.chym_last_error().decode() and "b must" in lib.chym_last_error().decode()
+    assert lib.chym_map_batch_workspace_size(probs, runs, 2, ctypes.byref(nbytes)) == L.CHYM_OK
+    # task table, work items (3 + 2 groups of 16 replicas), one counter per variant: 256-byte aligned areas
+    assert nbytes.value % 256 == 0 and nbytes.value >= 3 * 256
+    assert lib.chym_map_batch_workspace_size(probs, runs, 0, ctypes.byref(nbytes)) == L.CHYM_EINVAL
+    assert lib.chym_map_batch_workspace_size(None, runs, 1, ctypes.byref(nbytes)) == L.CHYM_EINVAL
+    # an invalid task fails before any device work or workspace check
+    assert lib.chym_map_batch(probs, runs, 3, None, 0, None) == L.CHYM_EINVAL
+    assert "task 2" in lib.chym_last_error().decode()
+    ell = (L.ChymMapProblem * 1)(mp(j_dtype=L.CHYM_J_ELL))
+    assert lib.chym_map_batch_workspace_size(ell, runs, 1, ctypes.byref(nbytes)) == L.CHYM_EUNSUPPORTED
+    import torch
+
+    if not torch.cuda.is_available():
+        # a valid batch without a workspace is refused before the device is touched
+        assert lib.chym_map_batch(probs, runs, 2, None, 0, None) == L.CHYM_EINVAL
+        assert "workspace" in lib.chym_last_error().decode()
+
+
 def test_sparse_couplings_validation():
     lib = L.load()
     b = ctypes.c_size_t(0)

@@ -120,3 +120,44 @@ def test_map_small_signal_gain_and_rejections():
     with pytest.raises(api.ChymError, match="map form runs"):
         api.chym_map_integrate(to_dev(big), hd, to_dev(np.zeros((120, r, 1), np.float32)), ad, b=B, loss=DD, kl=KL,
                                beta_b2=BB2, jmag=1.0, steps=1)
+
+
+def test_map_batch_equals_single_calls():
+    # several kernel variants in one call (row tiles, d, precision), ragged
+    # replica counts, different step counts within a variant, a zero-step task
+    specs = [(16, 2, 40, 700, True, "f32"), (40, 3, 33, 500, False, "f32"), (40, 3, 20, 900, True, "f32"),
+             (100, 1, 21, 300, False, "bf16"), (7, 2, 5, 0, False, "f32"), (33, 4, 18, 400, True, "f32"),
+             (112, 2, 16, 250, True, "f32")]
+    singles, tasks = [], []
+    for k, (n, d, r, steps, anneal, prec) in enumerate(specs):
+        J8, jmag, h, A0, alpha = setup(n, d, r, max(steps, 1), (73, k), anneal, kind="er" if k % 2 else "sk")
+        singles.append(run_gpu(J8, jmag, h, A0, alpha, steps, precision=prec).cpu().numpy())
+        tasks.append(dict(J=to_dev(J8), h=to_dev(h), A=to_dev(A0), alpha=to_dev(alpha), b=B, loss=DD, kl=KL,
+                          beta_b2=BB2, jmag=jmag, steps=steps, precision=prec))
+    ws = api.chym_map_batch(tasks)
+    torch.cuda.synchronize()
+    del ws
+    for k, (t, want) in enumerate(zip(tasks, singles)):
+        assert np.array_equal(t["A"].cpu().numpy(), want), k
+    # and against the oracle for one task of the batch
+    n, d, r, steps, anneal, _ = specs[2]
+    J8, jmag, h, A0, alpha = setup(n, d, r, steps, (73, 2), anneal, kind="sk")
+    Ao = run_oracle(J8, jmag, h, A0, alpha, steps)
+    assert np.abs(tasks[2]["A"].cpu().numpy() - Ao).max() <= 5e-4 * np.abs(Ao).max()
+
+
+def test_map_batch_repeat_and_errors():
+    n, d, r, steps = 24, 2, 48, 300
+    J8, jmag, h, A0, alpha = setup(n, d, r, steps, (74,), True)
+    want = run_gpu(J8, jmag, h, A0, alpha, steps).cpu().numpy()
+    for _ in range(2):  # the work counters start from zero on every call
+        t = dict(J=to_dev(J8), h=to_dev(h), A=to_dev(A0), alpha=to_dev(alpha), b=B, loss=DD, kl=KL, beta_b2=BB2,
+                 jmag=jmag, steps=steps)
+        api.chym_map_batch([t, dict(t, A=to_dev(A0))])
+        torch.cuda.synchronize()
+        assert np.array_equal(t["A"].cpu().numpy(), want)
+    bad = dict(t, b=1.5)
+    A_before = t["A"].clone()
+    with pytest.raises(api.ChymError, match="task 1"):
+        api.chym_map_batch([t, bad])
+    assert torch.equal(t["A"], A_before)  # nothing launched
