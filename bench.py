@@ -71,12 +71,16 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1, help="0 disables the oracle timing leg")
     ap.add_argument("--cpu-replicas", type=int, default=2000)
     ap.add_argument("--tts", type=int, default=1, help="0 skips the time-to-99%%-ground-state comparison")
-    ap.add_argument("--workload", type=str, default="sk100", choices=["sk100", "precision", "batched", "map", "sparse"],
+    ap.add_argument("--workload", type=str, default="sk100",
+                    choices=["sk100", "precision", "batched", "map", "sparse", "stats"],
                     help="sk100: the default throughput workload; precision: N=1000, D=4, 4096 replicas, "
                          "10000 steps with +-1, bf16 Gaussian and FP8 Gaussian couplings; batched: 10000 "
                          "solves of mixed N, D and graph family in one graph launch; map: the round-trip "
                          "map of Eq. (2) at the paper's parameters, N=100, D=3, 65536 replicas; sparse: "
-                         "3-regular and 20%% Erdos-Renyi couplings in sparse rows against the dense path")
+                         "3-regular and 20%% Erdos-Renyi couplings in sparse rows against the dense path; "
+                         "stats: the statistical harness's launches at N=100 (100 graphs, CIM and annealed "
+                         "CHYM, batched map)")
+    ap.add_argument("--round-trips", type=int, default=15000, help="stats workload: round trips per run")
     return ap.parse_args()
 
 
@@ -429,6 +433,64 @@ def run_sparse(args, torch, api, synth):
             "graphs": rows}
 
 
+def run_stats(args, torch, api, synth):
+    """The statistical harness at its largest size: 100 Erdos-Renyi 20% +-1
+    graphs at N = 100, each run as the CIM (D = 1, 51 pumps x 100 runs) and
+    as the annealed CHYM (D = 2, 21 pumps x 100 runs) with the round-trip
+    map, float32 form.  One step = both chym_map_batch calls plus the
+    readout and exact Ising energy of every run."""
+    from paper_2308_02329_amd import stats
+
+    n, n_graphs, n_rep, steps = 100, 100, 100, args.round_trips
+    graphs = [stats.graph(n, g, 2308) for g in range(n_graphs)]
+    machines = {d: stats.machine_tasks(graphs, d, n_rep, steps, 2308) for d in (1, 2)}
+    stream = torch.cuda.current_stream()
+    kms = {1: 0.0, 2: 0.0}
+    keep = []
+
+    def step(timed):
+        for d, tasks in machines.items():
+            for t in tasks:
+                t["A"].copy_(t["A0"])
+            if timed:
+                kms[d] += timed_events(torch, stream, lambda: keep.append(api.chym_map_batch(tasks)), 1)
+            else:
+                keep.append(api.chym_map_batch(tasks))
+            for t in tasks:
+                r = t["A"].shape[1]
+                if "spins" not in t:
+                    t["spins"] = torch.empty((r, api.spin_words(n)), dtype=torch.int64, device="cuda")
+                    t["e"] = torch.empty(r, dtype=torch.int32, device="cuda")
+                api.chym_readout(t["A"], t["spins"])
+                api.chym_ising_energy(t["J"], t["spins"], t["e"])
+
+    step(False)
+    torch.cuda.synchronize()
+    keep.clear()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    upd = {d: n * d * sum(t["A"].shape[1] for t in machines[d]) * steps for d in (1, 2)}
+    total = upd[1] + upd[2]
+    ms1 = kms[1] / args.steps
+    achieved = upd[1] * 2.0 * (n - 1) / (ms1 / 1e3) / 1e12
+    return {"metric": METRIC, "value": total / wall, "unit": "spin-component updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "ms_per_step": wall * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"statistical harness at N={n}: {n_graphs} Erdos-Renyi 20% +-1 graphs, CIM "
+                                   f"(D=1, 51 pumps x {n_rep} runs) and annealed CHYM (D=2, 21 x {n_rep}), {steps} "
+                                   f"round trips of the map each, kappa L=0.1, beta b^2=25 (CHYM) / 0 (CIM), "
+                                   f"b=d=0.01, f32 form, readout and exact energies",
+                       "n": n, "graphs": n_graphs, "runs": {"d1": 51 * n_rep, "d2": 21 * n_rep},
+                       "round_trips": steps, "precision": "f32"},
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                         "kernel": "k_integrate_persistent<7, 1, 3, 1, true>", "kernel_ms": ms1},
+            "map_batch_ms": {"d1": ms1, "d2": kms[2] / args.steps}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -442,7 +504,7 @@ def main():
 
         torch.cuda.set_device(0)
         fn = {"precision": run_precision, "batched": run_batched, "map": run_map,
-              "sparse": run_sparse}[args.workload]
+              "sparse": run_sparse, "stats": run_stats}[args.workload]
         print(json.dumps(fn(args, torch, api, synth), default=str), flush=True)
         return
 

@@ -146,29 +146,42 @@ def machine_inputs(J, d, dh, n_rep, steps, seed, g):
 
 
 # ------------------------------------------------------------ simulation
-def run_machine(graphs, d, n_rep, steps, seed, precision="f32", device="cuda"):
-    """Final Ising energies [graph][pump * rep] of all runs of one machine,
-    one chym_map_batch launch for every graph."""
+def machine_tasks(graphs, d, n_rep, steps, seed, precision="f32", device="cuda"):
+    """chym_map_batch tasks of every graph's runs on one machine; each task
+    also keeps its initial amplitudes as "A0"."""
     dev = torch.device(device)
-    tasks, keep = [], []
+    tasks = []
     for g, J in enumerate(graphs):
         jmag, h, A0, alpha, bb2 = machine_inputs(J, d, pumps(d), n_rep, steps, seed, g)
-        Jd = torch.from_numpy(J).to(dev)
-        t = dict(J=Jd, h=torch.from_numpy(h).to(dev), A=torch.from_numpy(A0).to(dev),
-                 alpha=torch.from_numpy(alpha).to(dev), b=B, loss=LOSS, kl=KL, beta_b2=bb2, jmag=jmag, steps=steps,
-                 precision=precision)
-        tasks.append(t)
-    ws = api.chym_map_batch(tasks)
+        A0d = torch.from_numpy(A0).to(dev)
+        tasks.append(dict(J=torch.from_numpy(J).to(dev), h=torch.from_numpy(h).to(dev), A=A0d.clone(), A0=A0d,
+                          alpha=torch.from_numpy(alpha).to(dev), b=B, loss=LOSS, kl=KL, beta_b2=bb2, jmag=jmag,
+                          steps=steps, precision=precision))
+    return tasks
+
+
+def final_energies(tasks):
+    """Sign readout and exact Ising energy of every task's final amplitudes."""
+    out = []
     for t in tasks:
         n, r, _ = t["A"].shape
-        spins = torch.empty((r, api.spin_words(n)), dtype=torch.int64, device=dev)
-        e = torch.empty(r, dtype=torch.int32, device=dev)
+        spins = torch.empty((r, api.spin_words(n)), dtype=torch.int64, device=t["A"].device)
+        e = torch.empty(r, dtype=torch.int32, device=t["A"].device)
         api.chym_readout(t["A"], spins)
         api.chym_ising_energy(t["J"], spins, e)
-        keep.append(e)
+        out.append(e)
     torch.cuda.synchronize()
+    return [e.cpu().numpy() for e in out]
+
+
+def run_machine(graphs, d, n_rep, steps, seed, precision="f32", device="cuda"):
+    """Final Ising energies [graph][pump * rep] of all runs of one machine:
+    one chym_map_batch call for every graph."""
+    tasks = machine_tasks(graphs, d, n_rep, steps, seed, precision, device)
+    ws = api.chym_map_batch(tasks)
+    energies = final_energies(tasks)
     del ws
-    return [e.cpu().numpy() for e in keep]
+    return energies
 
 
 def search_ground(graphs, n_rep=2000, steps=20000, seed=0, device="cuda"):
