@@ -72,14 +72,15 @@ def parse():
     ap.add_argument("--cpu-replicas", type=int, default=2000)
     ap.add_argument("--tts", type=int, default=1, help="0 skips the time-to-99%%-ground-state comparison")
     ap.add_argument("--workload", type=str, default="sk100",
-                    choices=["sk100", "precision", "batched", "map", "sparse", "stats"],
+                    choices=["sk100", "precision", "batched", "map", "sparse", "stats", "xy"],
                     help="sk100: the default throughput workload; precision: N=1000, D=4, 4096 replicas, "
                          "10000 steps with +-1, bf16 Gaussian and FP8 Gaussian couplings; batched: 10000 "
                          "solves of mixed N, D and graph family in one graph launch; map: the round-trip "
                          "map of Eq. (2) at the paper's parameters, N=100, D=3, 65536 replicas; sparse: "
                          "3-regular and 20%% Erdos-Renyi couplings in sparse rows against the dense path; "
                          "stats: the statistical harness's launches at N=100 (100 graphs, CIM and annealed "
-                         "CHYM, batched map)")
+                         "CHYM, batched map); xy: the XY-machine mode (D=2, no annealing, kappa L=1e-3) on 100 "
+                         "graphs at N=100 with hyperspin energies")
     ap.add_argument("--round-trips", type=int, default=15000, help="stats workload: round trips per run")
     return ap.parse_args()
 
@@ -491,6 +492,64 @@ def run_stats(args, torch, api, synth):
             "map_batch_ms": {"d1": ms1, "d2": kms[2] / args.steps}}
 
 
+def run_xy(args, torch, api, synth):
+    """The XY-machine mode: 100 Erdos-Renyi 20% +-1 graphs at N = 100, D = 2,
+    no annealing, kappa L = 1e-3, beta b^2 = 25, 4 pumps x 100 runs each,
+    20000 round trips of the map, float32 form.  One step = one
+    chym_map_batch call plus the hyperspin energy of every run."""
+    from paper_2308_02329_amd import stats, xy
+
+    n, n_graphs, n_rep, steps = 100, 100, 100, 20000
+    dh = (0.1, 0.25, 0.5, 1.0)
+    dev = torch.device("cuda:0")
+    tasks = []
+    for g in range(n_graphs):
+        J = stats.graph(n, g, 2308)
+        jmag, h, A0, alpha = xy.machine_inputs(J, n_rep, steps, dh, 2308, g)
+        A0d = torch.from_numpy(A0).to(dev)
+        tasks.append(dict(J=torch.from_numpy(J).to(dev), h=torch.from_numpy(h).to(dev), A=A0d.clone(), A0=A0d,
+                          alpha=torch.from_numpy(alpha).to(dev), b=xy.B, loss=xy.LOSS, kl=xy.KL, beta_b2=xy.BB2,
+                          jmag=jmag, steps=steps,
+                          e=torch.empty(A0.shape[1], dtype=torch.float64, device=dev)))
+    stream = torch.cuda.current_stream()
+    keep = []
+    kms = 0.0
+
+    def step(timed):
+        nonlocal kms
+        for t in tasks:
+            t["A"].copy_(t["A0"])
+        if timed:
+            kms += timed_events(torch, stream, lambda: keep.append(api.chym_map_batch(tasks)), 1)
+        else:
+            keep.append(api.chym_map_batch(tasks))
+        for t in tasks:
+            api.chym_hs_energy(t["J"], t["A"], t["e"])
+
+    step(False)
+    torch.cuda.synchronize()
+    keep.clear()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    runs = n_graphs * len(dh) * n_rep
+    upd = n * 2 * runs * steps
+    ms = kms / args.steps
+    achieved = upd * 2.0 * (n - 1) / (ms / 1e3) / 1e12
+    return {"metric": METRIC, "value": upd / wall, "unit": "spin-component updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "ms_per_step": wall * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"XY machine: {n_graphs} Erdos-Renyi 20% +-1 graphs at N={n}, D=2, no annealing, "
+                                   f"kappa L={xy.KL}, beta b^2={xy.BB2}, b=d={xy.B}, {len(dh)} pumps x {n_rep} runs, "
+                                   f"{steps} round trips of the map, f32 form, hyperspin energies",
+                       "n": n, "graphs": n_graphs, "runs": runs, "round_trips": steps, "precision": "f32"},
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                         "kernel": "k_integrate_persistent<7, 2, 3, 1, true>", "kernel_ms": ms}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -504,7 +563,7 @@ def main():
 
         torch.cuda.set_device(0)
         fn = {"precision": run_precision, "batched": run_batched, "map": run_map,
-              "sparse": run_sparse, "stats": run_stats}[args.workload]
+              "sparse": run_sparse, "stats": run_stats, "xy": run_xy}[args.workload]
         print(json.dumps(fn(args, torch, api, synth), default=str), flush=True)
         return
 
