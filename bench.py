@@ -38,7 +38,7 @@ PEAK_FP32_MATRIX_TFLOPS = 157.3
 # rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by the same counters on the
 # bench's own 4 GB state copy (profiles/integrate_persistent_sk100_d23_f32.md);
 # keyed by kernel and workload, valid for the kernels as they are now.
-TRAFFIC = {("k_integrate_persistent<7, 3, 3, 1>", 100, 1000, 2000): 4.922e9}
+TRAFFIC = {("k_integrate_persistent<7, 3, 3, 1, false>", 100, 1000, 2000): 4.921e9}
 
 
 def kernel_name(tiles, d, precision, plan):
@@ -48,7 +48,7 @@ def kernel_name(tiles, d, precision, plan):
         return f"k_integrate_persistent_lds<{tiles}, {d}, {xs}, 1, 2>"
     if kind == 3:
         return f"k_integrate_persistent_lds<{tiles}, {d}, {xs}, 1, 1>"
-    return f"k_integrate_persistent<{tiles}, {d}, {xs}, 1>"
+    return f"k_integrate_persistent<{tiles}, {d}, {xs}, 1, false>"  # false: the continuous-limit form
 
 
 def parse():
