@@ -155,7 +155,7 @@ def tts_leg():
     from paper_2308_02329_amd import learned
 
     rep = learned.experiment(log=None)
-    keep = ("workload", "tts99_median_ms", "instances_solved", "auc_heldout", "keep_fraction_heldout", "theta",
+    keep = ("workload", "tts99_median_ms", "instances_solved", "auc_heldout", "keep_fraction",
             "trajectories_train", "positives_heldout_bf16", "positives_heldout_f32", "updates_per_s", "seconds")
     def finite(v):
         if isinstance(v, dict):

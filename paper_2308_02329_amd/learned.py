@@ -3,8 +3,11 @@
 A run of the machine is cheap to start and expensive to finish.  From
 features of its first part (default: the first 10 % of the Euler steps,
 sampled at 8 checkpoints, see ``chym_features`` in include/chym.h) a small
-network predicts whether the run will end in the Ising ground state; runs
-predicted to fail are abandoned and restarted from fresh initial states.
+network predicts whether the run will end in the Ising ground state; at
+that checkpoint each pump's batch of runs keeps its highest-scored fraction
+and the others are abandoned and restarted from fresh initial states (a
+rank within the batch, not an absolute threshold: the network's scores are
+not calibrated across instances).
 Every kept run is still integrated to the end and judged by its exact Ising
 energy, so the method's answers are unchanged; only the cost per success
 changes.  The plain method (no restarts) is the fallback.
@@ -18,7 +21,7 @@ restart policy and the time-to-99%-success (TTS99) bookkeeping
 
 (t_attempt = GPU time per attempt; p >= 0.99 gives one attempt; p = 0 gives
 infinity).  With restarts an attempt costs the partial run, plus the rest of
-the run when kept, and succeeds when kept and successful.
+the run for the kept fraction, and succeeds when kept and successful.
 
 The ground-state energy of an instance is the best energy found by any run
 of it (a putative ground state; exact ones come from exhaustive search in
@@ -246,9 +249,11 @@ def auc(scores, labels):
     return float((ranks[labels].sum() - npos * (npos + 1) / 2) / (npos * nneg))
 
 
-def instance_tts(inst, egs, q=None, theta=0.0):
-    """Best-pump TTS99 (ms) of an instance, with the restart policy
-    'keep if q >= theta' when q is given."""
+def instance_tts(inst, egs, q=None, keep=1.0):
+    """Best-pump TTS99 (ms) of an instance.  With scores q, the restart
+    policy keeps, in every pump's batch of runs, the ceil(keep * n_ic) runs
+    with the highest scores at the checkpoint and restarts the others (ties
+    by run index); keep = 1 is the plain method."""
     e = inst["E"].cpu().numpy()
     succ = e == egs
     R = len(e)
@@ -259,38 +264,56 @@ def instance_tts(inst, egs, q=None, theta=0.0):
     for k in range(n_p):
         sl = slice(k * n_ic, (k + 1) * n_ic)
         s = succ[sl]
-        if q is None:
+        if q is None or keep >= 1.0:
             t = tts99(t_full, s.mean())
         else:
-            keep = q[sl] >= theta
-            cost = t_part + keep.mean() * (t_full - t_part)
-            t = tts99(cost, (keep & s).mean())
+            m = max(1, int(math.ceil(keep * n_ic)))
+            kept = np.zeros(n_ic, dtype=bool)
+            kept[np.argsort(-np.asarray(q[sl]), kind="stable")[:m]] = True
+            cost = t_part + (m / n_ic) * (t_full - t_part)
+            t = tts99(cost, (kept & s).mean())
         best = min(best, t)
     return best
 
 
-def evaluate(insts_plain, insts_learned, egs, net, theta):
+def evaluate(insts_plain, insts_learned, egs, net, keep):
     q_all = []
     rows = []
     for ip, il, g in zip(insts_plain, insts_learned, egs):
         q = torch.sigmoid(net.predict_raw(il["feats"])).cpu().numpy()
         q_all.append(q)
         rows.append(dict(index=ip["index"], egs=int(g), tts_plain_f32_ms=instance_tts(ip, g),
-                         tts_bf16_ms=instance_tts(il, g), tts_bf16_learned_ms=instance_tts(il, g, q, theta),
+                         tts_bf16_ms=instance_tts(il, g), tts_bf16_learned_ms=instance_tts(il, g, q, keep),
                          p_best_f32=float(max((ip["E"].cpu().numpy() == g)[k * ip["n_ic"]:(k + 1) * ip["n_ic"]].mean()
                                               for k in range(ip["n_pumps"])))))
     return rows, q_all
 
 
-def choose_theta(insts, egs, net, grid=None):
-    """Restart threshold minimizing the median best-pump TTS99 on insts."""
-    grid = np.concatenate([[0.0], np.geomspace(1e-4, 0.5, 40)]) if grid is None else grid
+def validation_score(tts, base):
+    """Score of a restart policy on validation instances: the geometric mean
+    of its best-pump TTS99 over the instances the plain method solves (base
+    finite), or inf if it loses any of them.  A median would let a policy
+    that kills every success of a minority of instances look best."""
+    tts = np.asarray(tts, dtype=np.float64)
+    ok = np.isfinite(np.asarray(base, dtype=np.float64))
+    if not ok.any() or not np.all(np.isfinite(tts[ok])):
+        return math.inf
+    return float(np.exp(np.mean(np.log(tts[ok]))))
+
+
+KEEP_GRID = (1.0, 0.7, 0.5, 0.35, 0.25, 0.18, 0.12, 0.08, 0.05, 0.03, 0.02, 0.01)
+
+
+def choose_keep(insts, egs, net, grid=KEEP_GRID):
+    """Kept fraction with the lowest validation_score on insts (1, never
+    restart, is always feasible).  Returns (keep, score in ms)."""
     qs = [torch.sigmoid(net.predict_raw(i["feats"])).cpu().numpy() for i in insts]
-    best = (math.inf, 0.0)
-    for th in grid:
-        med = float(np.median([instance_tts(i, g, q, th) for i, g, q in zip(insts, egs, qs)]))
-        if med < best[0]:
-            best = (med, float(th))
+    base = [instance_tts(i, g) for i, g in zip(insts, egs)]
+    best = (math.inf, 1.0)
+    for kf in grid:
+        sc = validation_score([instance_tts(i, g, q, kf) for i, g, q in zip(insts, egs, qs)], base)
+        if sc < best[0]:
+            best = (sc, float(kf))
     return best[1], best[0]
 
 
@@ -316,9 +339,10 @@ def experiment(n_train=50, n_val=10, n_test=20, n=100, d=3, n_ic=1000, n_pumps=2
     instances in both forms from the same initial states.  The putative
     ground state of an instance is the best energy of any of its runs,
     including a longer search (search_steps > 0).  The epoch and the
-    restart threshold are those with the lowest median TTS99 on the
-    validation instances; threshold 0 (never restart, the plain method) is
-    always a candidate.  Validation and held-out instances get n_ic_eval
+    kept fraction of the restart policy are those with the lowest
+    validation_score (geometric mean TTS99 over the validation instances,
+    no instance the plain method solves may be lost); keeping every run
+    (the plain method) is always a candidate.  Validation and held-out instances get n_ic_eval
     initial states per pump: success is rare enough that a best-pump
     TTS99 from fewer runs is mostly noise."""
     t0 = time.time()
@@ -349,25 +373,25 @@ def experiment(n_train=50, n_val=10, n_test=20, n=100, d=3, n_ic=1000, n_pumps=2
     xs = net.standardize(feats)
     t_fit = time.time()
     hist, val_curve = [], []
-    base_val = float(np.median([instance_tts(i, g) for i, g in zip(val, egs_val)]))
-    best = (base_val, 0.0, -1, net.state())  # never restart
+    base_tts = [instance_tts(i, g) for i, g in zip(val, egs_val)]
+    base_val = validation_score(base_tts, base_tts)
+    best = (base_val, 1.0, -1, net.state())  # never restart
     for ep in range(epochs):
         hist += net.fit(xs, labels, epochs=1, lr=lr, pos_frac=pos_frac, seed=seed * 1000 + ep)
-        th, med_val = choose_theta(val, egs_val, net)
-        val_curve.append(dict(epoch=ep, theta=th, tts99_val_ms=med_val))
+        kf, sc_val = choose_keep(val, egs_val, net)
+        val_curve.append(dict(epoch=ep, keep=kf, tts99_val_geomean_ms=sc_val))
         if log:
-            log(f"epoch {ep}: loss {hist[-1]:.4f} val TTS99 {med_val:.4f} ms (theta {th:.4g})")
-        if med_val < best[0]:
-            best = (med_val, th, ep, net.state())
+            log(f"epoch {ep}: loss {hist[-1]:.4f} val TTS99 (geometric mean) {sc_val:.4f} ms (keep {kf:.3g})")
+        if sc_val < best[0]:
+            best = (sc_val, kf, ep, net.state())
     net.load_state(best[3])
-    theta = best[1]
+    keep = best[1]
     torch.cuda.synchronize()
     t_fit = time.time() - t_fit
     a_train = auc(torch.sigmoid(net.predict_raw(feats)).cpu().numpy(), labels.cpu().numpy() > 0.5)
-    rows, qs = evaluate(test_f32, test_bf16, egs_test, net, theta)
+    rows, qs = evaluate(test_f32, test_bf16, egs_test, net, keep)
     lab = np.concatenate([(i["E"].cpu().numpy() == g) for i, g in zip(test_bf16, egs_test)])
     a = auc(np.concatenate(qs), lab)
-    keep = float(np.mean(np.concatenate(qs) >= theta))
 
     def med(key):
         return float(np.median([r[key] for r in rows]))
@@ -383,8 +407,8 @@ def experiment(n_train=50, n_val=10, n_test=20, n=100, d=3, n_ic=1000, n_pumps=2
         positives_heldout_bf16=float(lab.mean()),
         positives_heldout_f32=float(np.mean(np.concatenate([(i["E"].cpu().numpy() == g)
                                                             for i, g in zip(test_f32, egs_test)]))),
-        loss_history=hist, validation=val_curve, tts99_val_without_restart_ms=base_val, chosen_epoch=best[2],
-        train_seconds=t_fit, theta=theta, keep_fraction_heldout=keep, auc_train=a_train, auc_heldout=a,
+        loss_history=hist, validation=val_curve, tts99_val_geomean_without_restart_ms=base_val, chosen_epoch=best[2],
+        train_seconds=t_fit, keep_fraction=keep, auc_train=a_train, auc_heldout=a,
         tts99_median_ms=dict(plain_f32=med("tts_plain_f32_ms"), bf16=med("tts_bf16_ms"),
                              bf16_learned=med("tts_bf16_learned_ms")),
         instances_solved=dict(plain_f32=sum(math.isfinite(r["tts_plain_f32_ms"]) for r in rows),
