@@ -283,11 +283,34 @@ struct BatchLayout {
     std::vector<int2> items;      // (task, replica slab), grouped and sorted
     std::vector<size_t> jf_off;   // slab tasks: offset of the staged J in the workspace (else 0)
     std::vector<int> ncp;         // slab tasks: chunk count of the staging
-    size_t off_tasks, off_items, off_counters, off_score, off_first, off_jfp, off_ncp, off_jf, total;
+    std::vector<int> stage_list;  // slab tasks with one coupling term, then those with three
+    int n_stage1 = 0, n_stage3 = 0;
+    size_t off_tasks, off_items, off_counters, off_score, off_first, off_jfp, off_ncp, off_list, off_jf, total;
     int64_t total_replicas;
     int max_nd;
     bool any_readout, any_ising, any_hs;
 };
+
+// Offsets of the batch tables in the workspace for n_tasks tasks, n_items
+// work items and n_groups variant groups; the staged couplings of the
+// streamed-J tasks follow at off_jf.
+struct BatchTables {
+    size_t off_tasks, off_items, off_counters, off_score, off_first, off_jfp, off_ncp, off_list, off_jf;
+};
+
+BatchTables batch_tables(size_t n_tasks, size_t n_items, size_t n_groups) {
+    BatchTables T;
+    T.off_tasks = 0;
+    T.off_items = align_up(sizeof(chym::IntegArgs) * n_tasks);
+    T.off_counters = T.off_items + align_up(sizeof(int2) * std::max<size_t>(1, n_items));
+    T.off_score = T.off_counters + align_up(sizeof(int) * std::max<size_t>(1, n_groups));
+    T.off_first = T.off_score + align_up(sizeof(chym::ScoreArgs) * n_tasks);
+    T.off_jfp = T.off_first + align_up(sizeof(int64_t) * (n_tasks + 1));
+    T.off_ncp = T.off_jfp + align_up(sizeof(void *) * n_tasks);
+    T.off_list = T.off_ncp + align_up(sizeof(int) * n_tasks);
+    T.off_jf = T.off_list + align_up(sizeof(int) * n_tasks);
+    return T;
+}
 
 int validate_out(const chym_problem *prob, const chym_run *run, const chym_out *o) {
     const bool want_energy = o->e_ising || o->e_ising_f64;
@@ -375,16 +398,20 @@ int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
             L->max_nd = std::max(L->max_nd, tasks[t].prob.n * tasks[t].prob.d);
         }
     }
-    L->off_tasks = 0;
-    L->off_items = align_up(sizeof(chym::IntegArgs) * (size_t)n_tasks);
-    L->off_counters = L->off_items + align_up(sizeof(int2) * std::max<size_t>(1, L->items.size()));
-    L->off_score = L->off_counters + align_up(sizeof(int) * std::max<size_t>(1, L->groups.size()));
-    L->off_first = L->off_score + align_up(sizeof(chym::ScoreArgs) * (size_t)n_tasks);
-    L->off_jfp = L->off_first + align_up(sizeof(int64_t) * ((size_t)n_tasks + 1));
-    L->off_ncp = L->off_jfp + align_up(sizeof(void *) * (size_t)n_tasks);
-    L->off_jf = L->off_ncp + align_up(sizeof(int) * (size_t)n_tasks);
+    const BatchTables T = batch_tables((size_t)n_tasks, L->items.size(), L->groups.size());
+    L->off_tasks = T.off_tasks;
+    L->off_items = T.off_items;
+    L->off_counters = T.off_counters;
+    L->off_score = T.off_score;
+    L->off_first = T.off_first;
+    L->off_jfp = T.off_jfp;
+    L->off_ncp = T.off_ncp;
+    L->off_list = T.off_list;
+    L->off_jf = T.off_jf;
     L->jf_off.assign(n_tasks, 0);
     L->ncp.assign(n_tasks, 0);
+    L->stage_list.clear();
+    std::vector<int> three;
     size_t off = L->off_jf;
     for (int t = 0; t < n_tasks; ++t) {
         const Variant v = variant_of(&tasks[t].prob, &tasks[t].run);
@@ -392,7 +419,11 @@ int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
         L->jf_off[t] = off;
         L->ncp[t] = (v.tiles + 1) / 2;
         off += align_up(slab_ws_bytes(v));
+        (v.js == 3 ? three : L->stage_list).push_back(t);
     }
+    L->n_stage1 = (int)L->stage_list.size();
+    L->n_stage3 = (int)three.size();
+    L->stage_list.insert(L->stage_list.end(), three.begin(), three.end());
     L->total = off;
     return CHYM_OK;
 }
@@ -425,13 +456,13 @@ int issue_batch(const chym_batch *b, hipStream_t main, const std::vector<hipStre
     int *counters = reinterpret_cast<int *>(b->ws + L.off_counters);
     hipError_t e = chym::launch_zero_counters(counters, (int)L.groups.size(), main);
     if (e != hipSuccess) return hip_fail(e, "zero counters");
-    for (size_t t = 0; t < b->tasks.size(); ++t) {
-        if (!L.jf_off[t]) continue;
-        const chym_task &tk = b->tasks[t];
-        const Variant v = variant_of(&tk.prob, &tk.run);
-        e = chym::launch_stage_jfrag(make_args(&tk.prob, &tk.run), v.js, b->ws + L.jf_off[t], main);
-        if (e != hipSuccess) return hip_fail(e, "stage J");
-    }
+    // stage the couplings of every streamed-J task: one launch per coupling-term count
+    const int *list_d = reinterpret_cast<const int *>(b->ws + L.off_list);
+    const int *ncp_d = reinterpret_cast<const int *>(b->ws + L.off_ncp);
+    unsigned char *const *jfp_d = reinterpret_cast<unsigned char *const *>(b->ws + L.off_jfp);
+    e = chym::launch_stage_batched(1, tasks_d, list_d, L.n_stage1, ncp_d, jfp_d, main);
+    if (e == hipSuccess) e = chym::launch_stage_batched(3, tasks_d, list_d + L.n_stage1, L.n_stage3, ncp_d, jfp_d, main);
+    if (e != hipSuccess) return hip_fail(e, "stage J");
     const bool fork = branches && L.groups.size() > 1;
     if (fork) {
         e = hipEventRecord((*events)[0], main);
@@ -859,6 +890,9 @@ int chym_batch_create(const chym_task *tasks, int32_t n_tasks, void *workspace, 
         e = hipMemcpy(b->ws + L.off_jfp, jfp.data(), sizeof(void *) * n_tasks, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->ws + L.off_ncp, L.ncp.data(), sizeof(int) * n_tasks, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !L.stage_list.empty())
+        e = hipMemcpy(b->ws + L.off_list, L.stage_list.data(), sizeof(int) * L.stage_list.size(),
+                      hipMemcpyHostToDevice);
     // record the launch sequence as a graph with one branch per variant group
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     const size_t ng = b->layout.groups.size();
@@ -968,11 +1002,9 @@ ProbeLayout probe_layout(int n, int d, int r, int steps) {
     L.off_x = L.off_pump + align_up((size_t)r * 4);
     L.off_alpha = L.off_x + align_up((size_t)n * r * d * 4);
     L.off_batch = L.off_alpha + align_up((size_t)steps * d * 4);
-    // batch workspace of one task: its work list is largest with 16-replica items
-    // (same terms, in the same order, as plan_layout for one resident task)
-    L.batch_bytes = align_up(sizeof(chym::IntegArgs)) + align_up(sizeof(int2) * (size_t)((r + 15) / 16)) +
-                    align_up(sizeof(int)) + align_up(sizeof(chym::ScoreArgs)) + align_up(2 * sizeof(int64_t)) +
-                    align_up(sizeof(void *)) + align_up(sizeof(int));
+    // batch workspace of one resident task: its work list is largest with
+    // 16-replica items; no staged couplings follow the tables
+    L.batch_bytes = batch_tables(1, (size_t)((r + 15) / 16), 1).off_jf;
     L.total = L.off_batch + L.batch_bytes;
     return L;
 }

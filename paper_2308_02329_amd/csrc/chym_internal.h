@@ -180,6 +180,11 @@ size_t slab_lds_bytes(int tiles, int d, int xs);
 size_t slab_jfrag_bytes(int tiles, int js);
 bool slab_variant_exists(int tiles, int d, int xs, int js);
 hipError_t launch_stage_jfrag(const IntegArgs &a, int js, void *out, hipStream_t stream);
+// Stages the couplings of the tasks list[0 .. n) of a batch (all with js
+// coupling terms) into stages[task], ncps[task] chunks each; tasks, list,
+// ncps and stages are device arrays.
+hipError_t launch_stage_batched(int js, const IntegArgs *tasks, const int *list, int n, const int *ncps,
+                                unsigned char *const *stages, hipStream_t stream);
 hipError_t launch_integrate_slab(int tiles, int d, int xs, int js, const IntegArgs &a, const void *jfrag,
                                  hipStream_t stream);
 hipError_t slab_occupancy(int tiles, int d, int xs, int js, size_t lds, int *blocks_per_cu);

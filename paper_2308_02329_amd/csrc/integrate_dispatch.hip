@@ -60,9 +60,9 @@ bool slab_variant_exists(int tiles, int d, int xs, int js) {
 // Decides whether the couplings can be staged as E4M3 bytes: every row must
 // be a set of E4M3 values times one power of two (the row scale, chosen as
 // in the FP8 quantizer), checked element by element; FP8 storage always
-// qualifies.  Writes the header flag and the row scales.  One block of 1024
-// threads: wavefront w takes rows w, w + 16, ...
-__global__ __launch_bounds__(1024) void k_stage_prep(IntegArgs a, int tiles, unsigned char *__restrict__ stage) {
+// qualifies.  Writes the header flag and the row scales.  Run by one block
+// of 1024 threads: wavefront w takes rows w, w + 16, ...
+__device__ __forceinline__ void stage_prep_block(const IntegArgs &a, int tiles, unsigned char *__restrict__ stage) {
     __shared__ int s_ok;
     if (threadIdx.x == 0) s_ok = 1;
     __syncthreads();
@@ -103,6 +103,34 @@ __global__ __launch_bounds__(1024) void k_stage_prep(IntegArgs a, int tiles, uns
     if (!ok) atomicAnd(&s_ok, 0);
     __syncthreads();
     if (threadIdx.x == 0) *reinterpret_cast<int *>(stage) = (a.j_dtype == CHYM_J_FP8) ? 1 : s_ok;
+}
+
+__global__ __launch_bounds__(1024) void k_stage_prep(IntegArgs a, int tiles, unsigned char *__restrict__ stage) {
+    stage_prep_block(a, tiles, stage);
+}
+
+// The same for the tasks list[0 .. n) of a batch, one block each.
+__global__ __launch_bounds__(1024) void k_stage_prep_batched(const IntegArgs *__restrict__ tasks,
+                                                             const int *__restrict__ list,
+                                                             unsigned char *const *__restrict__ stages) {
+    const int t = list[blockIdx.x];
+    const IntegArgs a = tasks[t];
+    stage_prep_block(a, (a.n + 15) / 16, stages[t]);
+}
+
+hipError_t launch_stage_batched(int js, const IntegArgs *tasks, const int *list, int n, const int *ncps,
+                                unsigned char *const *stages, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    constexpr int kBlocksPerTask = 32;  // 8192 threads share a task's fragment slots
+    if (js == 3) {
+        hipLaunchKernelGGL(k_stage_jfrag_batched<3>, dim3(n * kBlocksPerTask), dim3(256), 0, stream, tasks, list,
+                           kBlocksPerTask, ncps, stages);
+    } else {
+        hipLaunchKernelGGL(k_stage_prep_batched, dim3(n), dim3(1024), 0, stream, tasks, list, stages);
+        hipLaunchKernelGGL(k_stage_jfrag_batched<1>, dim3(n * kBlocksPerTask), dim3(256), 0, stream, tasks, list,
+                           kBlocksPerTask, ncps, stages);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_stage_jfrag(const IntegArgs &a, int js, void *out, hipStream_t stream) {

@@ -321,16 +321,18 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
 
 // Stages J of one problem as A fragments: bf16 [tile][chunk][JS][64 lanes],
 // or (JS = 1 and the header flag set) E4M3 [tile][chunk][64 lanes] in the
-// same slot order.
+// same slot order.  Threads first, first + stride, ... of the launch share
+// the fragment slots.
 template <int JS>
-__global__ __launch_bounds__(256) void k_stage_jfrag(IntegArgs a, int ncp, unsigned char *__restrict__ stage) {
+__device__ __forceinline__ void stage_jfrag_part(const IntegArgs &a, int ncp, unsigned char *__restrict__ stage,
+                                                 int first, int stride) {
     const int nt = (a.n + 15) / 16;
     const int total = nt * ncp * 64;
     const bool f8 = JS == 1 && *reinterpret_cast<const int *>(stage) != 0;
     const float *scale = reinterpret_cast<const float *>(stage + kStageHeader);
     bf16x8 *out = reinterpret_cast<bf16x8 *>(stage + stage_frag_offset(nt));
     uint2 *out8 = reinterpret_cast<uint2 *>(stage + stage_frag_offset(nt));
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+    for (int idx = first; idx < total; idx += stride) {
         const int lane = idx & 63;
         const int c = (idx >> 6) % ncp;
         const int I = (idx >> 6) / ncp;
@@ -357,6 +359,23 @@ __global__ __launch_bounds__(256) void k_stage_jfrag(IntegArgs a, int ncp, unsig
             for (int t = 0; t < JS; ++t) out[((size_t)(I * ncp + c) * JS + t) * 64 + lane] = f[t];
         }
     }
+}
+
+template <int JS>
+__global__ __launch_bounds__(256) void k_stage_jfrag(IntegArgs a, int ncp, unsigned char *__restrict__ stage) {
+    stage_jfrag_part<JS>(a, ncp, stage, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+// The same for the tasks list[0 .. n) of a batch, bpt blocks per task:
+// task list[b / bpt] is staged into stages[task] with ncps[task] chunks.
+template <int JS>
+__global__ __launch_bounds__(256) void k_stage_jfrag_batched(const IntegArgs *__restrict__ tasks,
+                                                             const int *__restrict__ list, int bpt,
+                                                             const int *__restrict__ ncps,
+                                                             unsigned char *const *__restrict__ stages) {
+    const int t = list[blockIdx.x / bpt];
+    const IntegArgs a = tasks[t];
+    stage_jfrag_part<JS>(a, ncps[t], stages[t], (blockIdx.x % bpt) * blockDim.x + threadIdx.x, bpt * blockDim.x);
 }
 
 // The E4M3 path exists for single-term couplings; the flag is uniform.
