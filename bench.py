@@ -82,6 +82,8 @@ def parse():
                          "CHYM, batched map); xy: the XY-machine mode (D=2, no annealing, kappa L=1e-3) on 100 "
                          "graphs at N=100 with hyperspin energies")
     ap.add_argument("--round-trips", type=int, default=15000, help="stats workload: round trips per run")
+    ap.add_argument("--dense-3reg", action="store_true",
+                    help="batched workload: store the 3-regular couplings dense (matrix-core path)")
     return ap.parse_args()
 
 
@@ -251,7 +253,8 @@ def run_batched(args, torch, api, synth):
     """10000 solves in one graph launch: N uniform in {50, 100, 200, 400,
     800}, D uniform in {2, 3, 4}, SK +-1 or 3-regular +-1 (half each), one
     pump r ~ U[0.5, 2] per solve, 32 initial states, 5000 steps, BF16 form,
-    plans autotuned per resident (N, D) bucket."""
+    plans autotuned per resident (N, D) bucket.  The 3-regular couplings are
+    stored as sparse rows (the gather integrator) unless --dense-3reg."""
     dev = torch.device("cuda:0")
     g = np.random.default_rng(2308023294)
     n_solves, reps, steps = args.instances if args.instances != 1000 else 10000, 32, args.euler_steps
@@ -280,6 +283,7 @@ def run_batched(args, torch, api, synth):
         off += nn * nn
         flops += nn * reps * int(Ds[i]) * steps * (6.0 if fam[i] else 2.0 * (nn - 1))
     Jd = torch.from_numpy(Jh).to(dev)
+    sparse = fam & (not args.dense_3reg)
     x0 = synth.initial_states_torch(sum(xsz), 1, 1, seed=2308023294, device=dev).view(-1)
     x = torch.empty_like(x0)
     alphas = {dd: torch.from_numpy(synth.anneal_schedule(steps, dd)[0]).to(dev) for dd in (2, 3, 4)}
@@ -288,11 +292,16 @@ def run_batched(args, torch, api, synth):
     joff = xoff = 0
     for i in range(n_solves):
         nn, dd = int(Ns[i]), int(Ds[i])
-        tasks.append(dict(J=Jd[joff:joff + nn * nn].view(nn, nn), pump=pump_all[i * reps:(i + 1) * reps],
-                          x=x[xoff:xoff + nn * reps * dd].view(nn, reps, dd), alpha=alphas[dd], eps=float(eps[i]),
-                          btil=1.0, eta=2e-4, dt=args.dt, steps=steps, precision="bf16",
-                          spins=torch.empty((reps, api.spin_words(nn)), dtype=torch.int64, device=dev),
-                          e_ising=torch.empty(reps, dtype=torch.int32, device=dev)))
+        Ji = Jd[joff:joff + nn * nn].view(nn, nn)
+        t = dict(J=Ji, pump=pump_all[i * reps:(i + 1) * reps], x=x[xoff:xoff + nn * reps * dd].view(nn, reps, dd),
+                 alpha=alphas[dd], eps=float(eps[i]), btil=1.0, eta=2e-4, dt=args.dt, steps=steps, precision="bf16",
+                 spins=torch.empty((reps, api.spin_words(nn)), dtype=torch.int64, device=dev))
+        if sparse[i]:
+            t["J"] = torch.from_numpy(api.ell_pack(Jh[joff:joff + nn * nn].reshape(nn, nn))).to(dev)
+            t["e_ising_f64"] = torch.empty(reps, dtype=torch.float64, device=dev)
+        else:
+            t["e_ising"] = torch.empty(reps, dtype=torch.int32, device=dev)
+        tasks.append(t)
         joff += nn * nn
         xoff += nn * reps * dd
     t_setup = time.perf_counter()
@@ -320,8 +329,10 @@ def run_batched(args, torch, api, synth):
             "steps": args.steps, "warmup": 1, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
             "config": {"workload": f"{n_solves} solves in one graph launch: N in {{50,100,200,400,800}}, D in {{2,3,4}}, "
-                                   f"SK or 3-regular +-1, one pump per solve, {reps} initial states, {steps} steps, "
-                                   f"bf16 form", "solves": n_solves, "replicas_per_solve": reps,
+                                   f"SK or 3-regular +-1 (3-regular in "
+                                   f"{'dense' if args.dense_3reg else 'sparse'} rows), one pump per solve, {reps} "
+                                   f"initial states, {steps} steps, bf16 form", "solves": n_solves,
+                       "replicas_per_solve": reps,
                        "euler_steps": steps, "precision": "bf16"},
             "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,

@@ -78,8 +78,8 @@ extern "C" {
 #define CHYM_J_ELL 4  /* sparse rows (ELL), int32 [n + 1][2 w]: row 0 = {n, w, 0, ...}; row p + 1 = w columns
                          q, then the w couplings J_pq as float32 bit patterns (pad unused entries with
                          coupling 0); columns outside [0, n) are ignored.  8 w (n + 1) bytes.  Integrated
-                         by a gather kernel in float32 (both precision forms), n <= 4096; not for
-                         batches, plans, features or the map. */
+                         by a gather kernel in float32 (both precision forms), n <= 4096; batches take
+                         it (one group per d); not for plans, features or the map. */
 
 /* arithmetic of the J x contraction (the state and every other step are float32) */
 #define CHYM_PREC_F32 0  /* x fed to the matrix cores as an exact sum of three bf16 terms
@@ -244,11 +244,14 @@ int chym_solve_ws(const chym_problem *prob, const chym_run *run, int32_t ss_step
  * gathered over N_g graphs x N_s pump values x N_r runs, all independent
  * (statistics paragraph and Fig. 4).
  *
- * Tasks are grouped by kernel variant (row tiles, d, precision); each group
- * runs as one persistent kernel whose wavefronts pop (task, 16-replica
- * group) work items, longest first, from a counter in the workspace.  The
- * groups run as parallel branches of one HIP graph.  After integration every
- * task's non-NULL outputs are filled from its final state, as chym_solve does.
+ * Tasks are grouped by kernel variant (row tiles, d, precision, coupling
+ * storage); each group runs as one persistent kernel whose wavefronts (or
+ * blocks) pop (task, replica group) work items, longest first, from a
+ * counter in the workspace.  Sparse-row couplings (CHYM_J_ELL) form one
+ * group per d on the gather integrator; their Ising energies come out in
+ * e_ising_f64 (e_ising is for CHYM_J_I8 only).  The groups run as parallel
+ * branches of one HIP graph.  After integration every task's non-NULL
+ * outputs are filled from its final state, as chym_solve does.
  */
 typedef struct chym_task {
     chym_problem prob;

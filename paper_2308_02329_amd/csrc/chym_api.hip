@@ -94,6 +94,7 @@ int validate_run(const chym_run *r) {
 struct Variant {
     int tiles, xs, js;
     bool slab;
+    bool ell = false;  // sparse rows: the gather integrator
 };
 
 Variant make_variant(int n, int d, int precision, int j_dtype) {
@@ -106,7 +107,7 @@ Variant make_variant(int n, int d, int precision, int j_dtype) {
 }
 
 Variant variant_of(const chym_problem *p, const chym_run *r) {
-    if (p->j_dtype == CHYM_J_ELL) return Variant{(p->n + 15) / 16, 1, 1, false};  // gather kernel, no staging
+    if (p->j_dtype == CHYM_J_ELL) return Variant{(p->n + 15) / 16, 1, 1, false, true};  // gather kernel, no staging
     return make_variant(p->n, p->d, r->precision, p->j_dtype);
 }
 
@@ -275,7 +276,7 @@ struct Group {
     int kind, waves;  // launch plan of this variant (resident kernels)
     int item_off, n_items;
     int blocks;
-    size_t lds;  // slab kernels: LDS operand area
+    size_t lds;  // slab kernels: LDS operand area; gather kernel: the largest block's LDS
 };
 
 struct BatchLayout {
@@ -335,8 +336,6 @@ int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
         int rc = validate_problem(&tk.prob);
         if (!rc) rc = validate_run(&tk.run);
         if (!rc) rc = check_variant(&tk.prob, &tk.run);
-        if (!rc && tk.prob.j_dtype == CHYM_J_ELL)
-            rc = fail(CHYM_EUNSUPPORTED, "sparse couplings are not batched (use chym_integrate / chym_solve)");
         if (!rc) rc = validate_out(&tk.prob, &tk.run, &tk.out);
         if (rc) {
             std::string m = g_err;
@@ -344,10 +343,14 @@ int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
         }
         const Variant v = variant_of(&tk.prob, &tk.run);
         const VariantKey key = key_of(v, tk.prob.d);
-        auto &lst = by_variant[std::make_tuple((int)v.slab, v.tiles, tk.prob.d, v.xs, v.js)];
+        // group key (kind, tiles, d, xs, js): kind 0 resident, 1 streamed-J, 2 sparse rows (one group per d)
+        auto &lst = by_variant[v.ell ? std::make_tuple(2, 0, tk.prob.d, 0, 0)
+                                     : std::make_tuple((int)v.slab, v.tiles, tk.prob.d, v.xs, v.js)];
         if (tk.run.steps == 0) continue;
         int slab = 16;
-        if (!v.slab) {
+        if (v.ell) {
+            slab = chym::ell_replicas_per_block(tk.prob.n, tk.prob.d);
+        } else if (!v.slab) {
             const PlanValue pv = plan_for(key);
             slab = pv.kind != chym::kKernelRegJ ? 16 * pv.waves : 16;
         }
@@ -364,13 +367,18 @@ int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
             return tasks[a.x].run.steps > tasks[b.x].run.steps;
         });
         Group g;
-        g.v.slab = std::get<0>(kv.first) != 0;
+        g.v.ell = std::get<0>(kv.first) == 2;
+        g.v.slab = std::get<0>(kv.first) == 1;
         g.v.tiles = std::get<1>(kv.first);
         g.d = std::get<2>(kv.first);
         g.v.xs = std::get<3>(kv.first);
         g.v.js = std::get<4>(kv.first);
         g.lds = 0;
-        if (g.v.slab) {
+        if (g.v.ell) {
+            g.kind = -2;
+            g.waves = 16;
+            for (const int2 &it : lst) g.lds = std::max(g.lds, chym::ell_lds_bytes(tasks[it.x].prob.n, g.d));
+        } else if (g.v.slab) {
             g.kind = -1;
             g.waves = 4;
             g.lds = chym::slab_lds_bytes(g.v.tiles, g.d, g.v.xs);
@@ -475,7 +483,10 @@ int issue_batch(const chym_batch *b, hipStream_t main, const std::vector<hipStre
             e = hipStreamWaitEvent(s, (*events)[0], 0);
             if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
         }
-        if (g.v.slab)
+        if (g.v.ell)
+            e = chym::launch_integrate_ell_persistent(g.d, g.blocks, g.lds, tasks_d, items_d + g.item_off, g.n_items,
+                                                      counters + gi, s);
+        else if (g.v.slab)
             e = chym::launch_integrate_slab_persistent(
                 g.v.tiles, g.d, g.v.xs, g.v.js, g.lds, g.blocks, tasks_d, items_d + g.item_off, g.n_items,
                 counters + gi, reinterpret_cast<const void *const *>(b->ws + L.off_jfp),
@@ -847,10 +858,12 @@ int chym_batch_create(const chym_task *tasks, int32_t n_tasks, void *workspace, 
     for (Group &g : b->layout.groups) {
         int per_cu = 0;
         if (e == hipSuccess) {
-            if (g.v.slab) e = chym::slab_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, g.lds, &per_cu);
+            if (g.v.ell) e = chym::ell_persistent_occupancy(g.d, g.lds, &per_cu);
+            else if (g.v.slab) e = chym::slab_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, g.lds, &per_cu);
             else e = chym::persistent_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, g.kind, g.waves, &per_cu);
         }
-        const int need = (g.v.slab || g.kind != chym::kKernelRegJ) ? g.n_items : (g.n_items + g.waves - 1) / g.waves;
+        const int need = (g.v.ell || g.v.slab || g.kind != chym::kKernelRegJ) ? g.n_items
+                                                                              : (g.n_items + g.waves - 1) / g.waves;
         g.blocks = std::max(1, std::min(need, std::max(1, per_cu) * cus));
     }
     // task table and work list

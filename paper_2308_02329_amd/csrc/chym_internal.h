@@ -143,6 +143,14 @@ hipError_t launch_quantize_fp8(int n, const float *j, uint8_t *out, hipStream_t 
 // and the gather integrator.
 int ell_replicas_per_block(int n, int d);
 hipError_t launch_integrate_ell(const IntegArgs &a, hipStream_t stream);
+// LDS bytes of one block of the gather integrator for n, d; the persistent
+// form over many problems of one d (items: task, replica block of
+// ell_replicas_per_block(n, d) replicas), launched with the largest LDS
+// size of its tasks.
+size_t ell_lds_bytes(int n, int d);
+hipError_t ell_persistent_occupancy(int d, size_t lds, int *blocks_per_cu);
+hipError_t launch_integrate_ell_persistent(int d, int blocks, size_t lds, const IntegArgs *tasks, const int2 *items,
+                                           int n_items, int *counter, hipStream_t stream);
 // Synthetic timing problem for the autotuner.
 hipError_t launch_fill_probe(void *j, int j_dtype, int n, float *pump, int r, float *alpha, int na,
                              hipStream_t stream);

@@ -12,7 +12,8 @@
 // wavefront read the same coupling row (broadcast) and contiguous state.
 // Blocks of 1024 threads (sixteen wavefronts per CU cover the LDS latency);
 // the coupling rows and the block's pumps are staged in LDS too when the
-// rows fit a fixed budget (read from global memory otherwise).
+// rows fit a fixed budget (read from global memory otherwise).  A persistent
+// form takes (task, replica block) items of many problems from a counter.
 #include "chym_internal.h"
 
 namespace chym {
@@ -21,19 +22,31 @@ constexpr size_t kEllMaxLds = 159 * 1024;
 constexpr size_t kEllRowBudget = 32 * 1024;  // LDS for the coupling rows
 constexpr int kEllThreads = 1024;
 
-int ell_replicas_per_block(int n, int d) {
+__host__ __device__ inline int ell_rb(int n, int d) {
     for (int rb = 16; rb >= 1; rb >>= 1)
         if (2 * (size_t)n * rb * d * sizeof(float) + kEllRowBudget + 64 <= kEllMaxLds) return rb;
     return 0;
 }
 
+int ell_replicas_per_block(int n, int d) { return ell_rb(n, d); }
+
+__host__ __device__ inline int ell_log2(int rb) {
+    int l = 0;
+    while ((1 << l) < rb) ++l;
+    return l;
+}
+
+size_t ell_lds_bytes(int n, int d) {
+    return 2 * (size_t)n * ell_rb(n, d) * d * sizeof(float) + 16 * sizeof(float) + kEllRowBudget;
+}
+
+// Integrates replicas rep0 .. rep0 + 2^lrb - 1 of problem a; called by all
+// threads of the block (block barriers inside).
 template <int D>
-__global__ __launch_bounds__(kEllThreads) void k_integrate_ell(IntegArgs a, int lrb) {
-    extern __shared__ __align__(16) float sm[];
+__device__ __forceinline__ void ell_block(const IntegArgs &a, int rep0, int lrb, float *sm) {
     const int n = a.n;
     const int r = a.r;
     const int rb = 1 << lrb;
-    const int rep0 = blockIdx.x * rb;
     const int units = n << lrb;
     float *xa = sm;
     float *xb = sm + (size_t)units * D;
@@ -117,12 +130,39 @@ __global__ __launch_bounds__(kEllThreads) void k_integrate_ell(IntegArgs a, int 
     }
 }
 
+template <int D>
+__global__ __launch_bounds__(kEllThreads) void k_integrate_ell(IntegArgs a, int lrb) {
+    extern __shared__ __align__(16) float sm[];
+    ell_block<D>(a, blockIdx.x << lrb, lrb, sm);
+}
+
+// Many problems of one D: blocks pop (task, replica block) items from the
+// counter (zero at launch) until n_items are taken; a task's block size is
+// ell_rb(n, D), as for its single launch, so the results are the same.
+template <int D>
+__global__ __launch_bounds__(kEllThreads) void k_integrate_ell_persistent(const IntegArgs *__restrict__ tasks,
+                                                                          const int2 *__restrict__ items,
+                                                                          int n_items, int *__restrict__ counter) {
+    extern __shared__ __align__(16) float sm[];
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();  // the previous item's LDS use is over
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= n_items) break;
+        const int2 w = items[it];
+        const IntegArgs a = tasks[w.x];
+        const int lrb = ell_log2(ell_rb(a.n, D));
+        ell_block<D>(a, w.y << lrb, lrb, sm);
+    }
+}
+
 hipError_t launch_integrate_ell(const IntegArgs &a, hipStream_t stream) {
-    const int rb = ell_replicas_per_block(a.n, a.d);
+    const int rb = ell_rb(a.n, a.d);
     if (rb == 0) return hipErrorInvalidValue;
-    int lrb = 0;
-    while ((1 << lrb) < rb) ++lrb;
-    const size_t lds = 2 * (size_t)a.n * rb * a.d * sizeof(float) + 16 * sizeof(float) + kEllRowBudget;
+    const int lrb = ell_log2(rb);
+    const size_t lds = ell_lds_bytes(a.n, a.d);
     const int blocks = (a.r + rb - 1) / rb;
     void (*fn)(IntegArgs, int) = a.d == 1 ? k_integrate_ell<1>
                                  : a.d == 2 ? k_integrate_ell<2>
@@ -134,6 +174,38 @@ hipError_t launch_integrate_ell(const IntegArgs &a, hipStream_t stream) {
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(kEllThreads), lds, stream, a, lrb);
+    return hipGetLastError();
+}
+
+typedef void (*EllPersistentFn)(const IntegArgs *, const int2 *, int, int *);
+
+static EllPersistentFn ell_persistent_fn(int d) {
+    return d == 1 ? k_integrate_ell_persistent<1>
+           : d == 2 ? k_integrate_ell_persistent<2>
+           : d == 3 ? k_integrate_ell_persistent<3>
+                    : k_integrate_ell_persistent<4>;
+}
+
+static hipError_t ell_persistent_prepare(EllPersistentFn fn, size_t lds) {
+    if (lds <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+}
+
+hipError_t ell_persistent_occupancy(int d, size_t lds, int *blocks_per_cu) {
+    EllPersistentFn fn = ell_persistent_fn(d);
+    *blocks_per_cu = 0;
+    hipError_t e = ell_persistent_prepare(fn, lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kEllThreads, lds);
+}
+
+hipError_t launch_integrate_ell_persistent(int d, int blocks, size_t lds, const IntegArgs *tasks, const int2 *items,
+                                           int n_items, int *counter, hipStream_t stream) {
+    EllPersistentFn fn = ell_persistent_fn(d);
+    hipError_t e = ell_persistent_prepare(fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kEllThreads), lds, stream, tasks, items, n_items, counter);
     return hipGetLastError();
 }
 

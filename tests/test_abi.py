@@ -254,10 +254,21 @@ def test_sparse_couplings_validation():
                               None) == L.CHYM_EUNSUPPORTED
     assert lib.chym_features(16, 2, 4, 0x1000, L.CHYM_J_ELL, 0x2000, 0x3000, 0x4000, 0, None) == L.CHYM_EUNSUPPORTED
     assert lib.chym_ising_energy(16, 4, 0x1000, L.CHYM_J_ELL, 0x2000, 0x3000, None, None) == L.CHYM_EINVAL
+    # batches take sparse rows (no staging area: the tables only), up to the gather kernel's n
     tasks = (L.ChymTask * 1)(L.ChymTask(prob=_prob(j_dtype=L.CHYM_J_ELL), run=_run()))
     nbytes = ctypes.c_size_t(0)
-    assert lib.chym_batch_workspace_size(tasks, 1, ctypes.byref(nbytes)) == L.CHYM_EUNSUPPORTED
-    assert "not batched" in lib.chym_last_error().decode()
+    assert lib.chym_batch_workspace_size(tasks, 1, ctypes.byref(nbytes)) == L.CHYM_OK
+    dense = (L.ChymTask * 1)(L.ChymTask(prob=_prob(), run=_run()))
+    nb2 = ctypes.c_size_t(0)
+    assert lib.chym_batch_workspace_size(dense, 1, ctypes.byref(nb2)) == L.CHYM_OK
+    assert 0 < nbytes.value <= nb2.value
+    big = (L.ChymTask * 1)(L.ChymTask(prob=_prob(n=5000, j_dtype=L.CHYM_J_ELL), run=_run()))
+    assert lib.chym_batch_workspace_size(big, 1, ctypes.byref(nbytes)) == L.CHYM_EUNSUPPORTED
+    assert "task 0" in lib.chym_last_error().decode()
+    # the exact int32 energy is for int8 couplings only
+    out = L.ChymOut(spins=0x5000, e_ising=0x6000)
+    ell_i32 = (L.ChymTask * 1)(L.ChymTask(prob=_prob(j_dtype=L.CHYM_J_ELL), run=_run(), out=out))
+    assert lib.chym_batch_workspace_size(ell_i32, 1, ctypes.byref(nbytes)) != L.CHYM_OK
 
 
 def test_ell_pack_layout():

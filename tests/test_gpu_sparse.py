@@ -87,3 +87,34 @@ def test_sparse_header_mismatch_reads_as_uncoupled():
     xo = oracle.ode_run(np.zeros_like(case.J), case.pump, case.x0, steps=case.steps, alpha=case.alpha,
                         **case.params())
     assert np.abs(xg - xo).max() <= 1e-5
+
+
+def test_sparse_tasks_in_a_batch_equal_solo_runs():
+    # sparse rows of several sizes and d (one gather group per d), ragged
+    # replica counts, a task past the rows' LDS budget, and dense tasks in the
+    # same batch; every task must equal its own single call bit for bit
+    specs = [(120, 3, 48, "reg3", True), (400, 2, 40, "reg3", True), (64, 4, 21, "er", True),
+             (800, 3, 20, "reg3", True), (40, 1, 16, "sk", True), (100, 3, 33, "sk", False),
+             (48, 2, 17, "reg3", False)]
+    tasks, want, cases = [], [], []
+    for k, (n, d, r, kind, sparse) in enumerate(specs):
+        case = Case(n, d, r, 300, key=(84, k), kind=kind, sigma=0.05)
+        Jd = ell_dev(case.J) if sparse else to_dev(case.J)
+        want.append(run(case, Jd).cpu().numpy())
+        _, pump, x0, alpha = case.gpu_inputs()
+        tasks.append(dict(J=Jd, pump=pump, x=x0, alpha=alpha, steps=case.steps, precision="f32", **case.params(),
+                          spins=torch.empty((r, api.spin_words(n)), dtype=torch.int64, device="cuda"),
+                          e_ising_f64=torch.empty(r, dtype=torch.float64, device="cuda")))
+        cases.append(case)
+    plan = api.chym_batch_create(tasks)
+    for rep in range(2):  # the work counters restart from zero on every launch
+        for t, case in zip(tasks, cases):
+            t["x"].copy_(to_dev(case.x0))
+        plan.launch()
+        torch.cuda.synchronize()
+        for k, (t, w, case) in enumerate(zip(tasks, want, cases)):
+            assert np.array_equal(t["x"].cpu().numpy(), w), (rep, k)
+            sig = unpack_spins(t["spins"].cpu().numpy(), case.n)
+            np.testing.assert_array_equal(sig, oracle.readout(w))
+            np.testing.assert_array_equal(t["e_ising_f64"].cpu().numpy(), oracle.ising_energy(case.J, sig))
+    plan.destroy()
