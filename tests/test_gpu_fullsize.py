@@ -1,0 +1,130 @@
+"""Parity at the benchmarked sizes, in the launch configuration bench.py
+times: the default workload (1000 SK +-1 instances, N = 100, D in {2, 3},
+100 initial states x 20 pumps each, 5000 Euler steps, float32 form, one
+batched graph launch per D with autotuned plans, then the batched scoring
+launch).  The oracle integrates sampled (instance, replica) pairs one by
+one from the same initial states.
+
+Bar on the final amplitudes: the float32-form bar of 1e-4 holds over 2000
+steps (the other parity tests).  Over 5000 steps the anneal drives the
+amplitudes through pitchfork bifurcations, which amplify rounding-level
+differences, so the bar is derived from the dynamics: s is the largest
+distance the oracle's own float64 run moves when its state is perturbed by
+one float32 ulp (relative 2^-24, random signs) at step 0, T/4, T/2 or
+3T/4.  A float32 step rounds the contraction (a sum of N = 100 exact
+products, error within ~sqrt(N) = 10 ulp) and the update (a few ulp): at
+most 16 ulp per step; such errors from the T steps add like a random walk,
+each growing at most like a one-ulp perturbation, so the bar is
+max(1e-4, 16 sqrt(T) s).  The sign readout and the integer Ising energies
+of the sampled runs are exact."""
+import argparse
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2308_02329_amd import api, synth
+
+torch = pytest.importorskip("torch")
+from gpu_helpers import unpack_spins  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def test_default_workload_sampled_against_oracle():
+    import bench
+
+    args = argparse.Namespace(instances=1000, n=100, dims="2,3", ics=100, pumps=20, euler_steps=5000, dt=0.01,
+                              precision="f32")
+    for d in (2, 3):  # as the bench does before building its plans
+        api.chym_plan_autotune(args.n, d, args.precision, torch.int8, steps=400)
+    dev = torch.device("cuda:0")
+    wl = bench.build_workload(args, torch, synth, api, dev)
+    wl["x"].copy_(wl["x0"])
+    for d in wl["dims"]:
+        wl["plans"][d].launch()
+    wl["score_plan"].launch()
+    torch.cuda.synchronize()
+    n, R, steps = args.n, wl["R"], args.euler_steps
+    sizes = [n * R * d for d in wl["dims"]]
+    per_inst = sum(sizes)
+    reps = np.array([0, 57, 999, 1000, 1342, 1999])  # pumps 0.5 .. 2.0 (replica // 100 = pump index)
+    worst = 0.0
+    for i in (0, 411, 999):
+        outs = {d: o for (ii, d, o) in wl["outs"] if ii == i}
+        for di, d in enumerate(wl["dims"]):
+            off = i * per_inst + sum(sizes[:di])
+            x0 = wl["x0"][off:off + sizes[di]].view(n, R, d)[:, reps, :].cpu().numpy()
+            xg = wl["x"][off:off + sizes[di]].view(n, R, d)[:, reps, :].cpu().numpy()
+            al, _ = synth.anneal_schedule(steps, d)
+            kw = dict(eps=float(wl["eps"][i]), btil=1.0, eta=2e-4, dt=args.dt, steps=steps, alpha=al)
+            xo = oracle.ode_run(wl["Js"][i], wl["pumps"][reps], x0, **kw)
+            sens = np.zeros(len(reps))
+            for k in (0, steps // 4, steps // 2, 3 * steps // 4):
+                kk = dict(kw, steps=k)
+                xk = oracle.ode_run(wl["Js"][i], wl["pumps"][reps], x0, **kk) if k else x0.astype(np.float64)
+                sgn = np.where(synth.rng(7, i, d, k).random(xk.shape) < 0.5, -1.0, 1.0)
+                kp = dict(kw, steps=steps - k, start_step=k)
+                xp = oracle.ode_run(wl["Js"][i], wl["pumps"][reps], xk * (1.0 + sgn * 2.0 ** -24), **kp)
+                sens = np.maximum(sens, np.abs(xp - xo).max(axis=(0, 2)))  # per sampled run
+            bar = np.maximum(1e-4, 16.0 * np.sqrt(steps) * sens)
+            err = np.abs(xg - xo).max(axis=(0, 2))
+            fmt = {"float_kind": lambda v: f"{v:.1e}"}
+            print(f"instance {i} d={d}: |x_gpu - x_oracle| per run {np.array2string(err, formatter=fmt)}, "
+                  f"bar {np.array2string(bar, formatter=fmt)}")
+            worst = max(worst, float((err / bar).max()))
+            assert np.all(err <= bar), (i, d, err, bar)
+            sig = unpack_spins(outs[d]["spins"][reps].cpu().numpy(), n)
+            np.testing.assert_array_equal(sig, oracle.readout(xg))
+            np.testing.assert_array_equal(sig, oracle.readout(xo))
+            np.testing.assert_array_equal(outs[d]["e_ising"][reps].cpu().numpy().astype(np.float64),
+                                          oracle.ising_energy(wl["Js"][i], sig))
+            np.testing.assert_allclose(outs[d]["e_hs"][reps].cpu().numpy(), oracle.hs_energy(wl["Js"][i], xg),
+                                       rtol=1e-12, atol=1e-9)
+            assert not outs[d]["diverged"].cpu().numpy().any()
+    print(f"largest |x_gpu - x_oracle| / bar over the samples: {worst:.2f}")
+    for p in list(wl["plans"].values()) + [wl["score_plan"]]:
+        p.destroy()
+
+
+def test_precision_workload_full_size_properties():
+    """N = 1000, D = 4, 4096 replicas, 10000 steps (the precision workload):
+    +-1 couplings give bit-identical runs whether stored as int8, bf16 or
+    FP8; Gaussian FP8 couplings give the same run as their decoded values
+    stored as bf16 (every decoded value is exact in bf16).  (The float32
+    form does not run at this shape: its three-term operand of 16 replicas
+    needs 384 KB of LDS; the bf16 form's error against the oracle is the
+    precision report's subject, not a bar.)"""
+    import oracle.fp8 as ofp8
+
+    dev = torch.device("cuda:0")
+    n, d, R, steps = 1000, 4, 4096, 10000
+    pumps = torch.from_numpy(synth.pump_grid(256, np.linspace(0.5, 2.0, 16))).to(dev)
+    alpha = torch.from_numpy(synth.anneal_schedule(steps, d)[0]).to(dev)
+    sk = synth.sk_pm1(n, 3, 0)
+    x0 = synth.initial_states_torch(n, R, d, seed=2308023293, device=dev)
+    x = torch.empty_like(x0)
+    eps_sk = float(np.float32(0.5 / synth.lambda_max(sk)))
+    skf = torch.from_numpy(sk.astype(np.float32)).to(dev)
+    ws = torch.empty(api.chym_integrate_workspace_size(skf.to(torch.bfloat16), x, precision="bf16") + 256,
+                     dtype=torch.uint8, device=dev)
+
+    def run(J, eps):
+        x.copy_(x0)
+        api.chym_integrate(J, pumps, x, alpha, eps=eps, btil=1.0, eta=2e-4, dt=0.01, steps=steps,
+                           precision="bf16", workspace=ws)
+        torch.cuda.synchronize()
+        return x.cpu().numpy()
+
+    ref = run(torch.from_numpy(sk).to(dev), eps_sk)
+    assert np.array_equal(run(skf.to(torch.bfloat16), eps_sk), ref)
+    assert np.array_equal(run(api.chym_quantize_fp8(skf), eps_sk), ref)
+
+    ga = synth.gaussian_j(n, 3, 1).astype(np.float32)
+    eps_g = float(np.float32(0.5 / synth.lambda_max(ga)))
+    q = api.chym_quantize_fp8(torch.from_numpy(ga).to(dev))
+    qb = q.cpu().numpy().reshape(n + 1, n)
+    dec = ofp8.decode(qb[:n], qb[n]).astype(np.float32)
+    dec_bf16 = torch.from_numpy(dec).to(dev).to(torch.bfloat16)
+    assert np.array_equal(dec_bf16.float().cpu().numpy(), dec)  # exact in bf16
+    assert np.array_equal(run(q, eps_g), run(dec_bf16, eps_g))
