@@ -128,3 +128,70 @@ def test_precision_workload_full_size_properties():
     dec_bf16 = torch.from_numpy(dec).to(dev).to(torch.bfloat16)
     assert np.array_equal(dec_bf16.float().cpu().numpy(), dec)  # exact in bf16
     assert np.array_equal(run(q, eps_g), run(dec_bf16, eps_g))
+
+
+def test_map_workload_full_size_sampled_against_oracle():
+    """The map workload as bench.py times it (SK N = 100, D = 3, 65 536
+    replicas, pumps 1.1 .. 2 h_th, 2000 round trips with the anneal, float32
+    form, one launch); sampled replicas against the oracle's literal map,
+    to the map's bar of 5e-4 of the amplitude scale (derived in
+    test_gpu_map.py), with identical readout."""
+    import math
+
+    dev = torch.device("cuda:0")
+    n, d, R, steps = 100, 3, 65536, 2000
+    b = dd = 0.01
+    kl, bb2 = 0.1, 25.0
+    J = synth.sk_pm1(n, 6, 0)
+    jmag = float(np.float32(0.5 / synth.lambda_max(J) * (b + dd) / b))
+    hth = -math.log((1 - b) * (1 - dd)) / kl
+    h = (np.linspace(1.1, 2.0, R) * hth).astype(np.float32)
+    A0 = synth.initial_states_torch(n, R, d, seed=2308023295, device=dev) * (100.0 * math.sqrt((b + dd) / bb2))
+    alpha = synth.anneal_schedule(steps, d)[0]
+    A = A0.clone()
+    api.chym_map_integrate(torch.from_numpy(J).to(dev), torch.from_numpy(h).to(dev), A,
+                           torch.from_numpy(alpha).to(dev), b=b, loss=dd, kl=kl, beta_b2=bb2, jmag=jmag, steps=steps)
+    torch.cuda.synchronize()
+    reps = np.array([0, 1, 12345, 32768, 50001, 65535])
+    Ag = A[:, reps, :].cpu().numpy().astype(np.float64)
+    Ao = oracle.map_run(jmag * J.astype(np.float64), h[reps].astype(np.float64),
+                        A0[:, reps, :].cpu().numpy().astype(np.float64), b, dd, kl, bb2 / b ** 2, steps, alpha)
+    scale = np.abs(Ao).max()
+    err = np.abs(Ag - Ao).max()
+    print(f"map, 65536 replicas: sampled max |dA| = {err:.2e} of scale {scale:.2e}")
+    assert err <= 5e-4 * scale, (err, scale)
+    np.testing.assert_array_equal(oracle.readout(Ag), oracle.readout(Ao))
+
+
+def test_stats_launch_full_size_equals_single_calls():
+    """The statistical harness's largest launch (100 graphs at N = 100, the
+    CIM with 51 x 100 runs each, 15 000 round trips, one chym_map_batch
+    call): sampled graphs equal their own chym_map_integrate calls bit for
+    bit, and sampled runs of them match the oracle's literal map (final
+    Ising energy identical for at least 5 of 6 sampled runs: a run ending
+    near a sign change may be read differently in float32 and float64)."""
+    from paper_2308_02329_amd import stats
+
+    n, n_graphs, n_rep, steps = 100, 100, 100, 15000
+    graphs = [stats.graph(n, g, 2308) for g in range(n_graphs)]
+    tasks = stats.machine_tasks(graphs, 1, n_rep, steps, 2308)
+    ws = api.chym_map_batch(tasks)
+    torch.cuda.synchronize()
+    del ws
+    agree = 0
+    for g in (0, 57, 99):
+        t = tasks[g]
+        single = t["A0"].clone()
+        api.chym_map_integrate(t["J"], t["h"], single, t["alpha"], b=t["b"], loss=t["loss"], kl=t["kl"],
+                               beta_b2=t["beta_b2"], jmag=t["jmag"], steps=steps)
+        torch.cuda.synchronize()
+        assert torch.equal(single, t["A"]), g
+        reps = np.array([0, 2550])
+        J = graphs[g]
+        Ao = oracle.map_run(t["jmag"] * J.astype(np.float64), t["h"][reps].cpu().numpy().astype(np.float64),
+                            t["A0"][:, reps, :].cpu().numpy().astype(np.float64), stats.B, stats.LOSS, stats.KL, 0.0,
+                            steps, t["alpha"].cpu().numpy())
+        eg = oracle.ising_energy(J, oracle.readout(t["A"][:, reps, :].cpu().numpy()))
+        eo = oracle.ising_energy(J, oracle.readout(Ao))
+        agree += int(np.sum(eg == eo))
+    assert agree >= 5, agree
