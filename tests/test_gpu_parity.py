@@ -223,9 +223,12 @@ def test_batched_equals_solo_bit_exact(graph):
             api.chym_integrate(Jd, pump, xs, alpha, steps=s, **c.params())
         solo.append(xs)
     b = api.chym_batch_create(tasks)
-    for rep in range(2):
+    for rep in range(4):  # replays of one graph, eager work between them, every replay checked
         for t, c in zip(tasks, cases):
             t["x"].copy_(to_dev(c.x0))
+            t["spins"].fill_(-1)  # sentinels: a replay that skips a write is caught
+            t["e_ising"].fill_(123456789)
+            t["e_hs"].fill_(float("nan"))
         b.launch() if graph else b.launch_nograph()
         torch.cuda.synchronize()
         for t, c, xs in zip(tasks, cases, solo):

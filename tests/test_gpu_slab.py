@@ -83,11 +83,26 @@ def test_mixed_batch_with_slab_tasks_equals_solo():
         tasks.append(dict(J=Jd, pump=pump, x=x, alpha=alpha, steps=s, precision=prec, **c.params()))
         solo.append(run_gpu(c, prec).cpu().numpy())
     b = api.chym_batch_create(tasks)
-    for _ in range(2):
+    for _ in range(3):  # graph replays with eager work between them
         for t, c in zip(tasks, cases):
             t["x"].copy_(to_dev(c.x0))
         b.launch()
         torch.cuda.synchronize()
         for t, ref in zip(tasks, solo):
             assert np.array_equal(t["x"].cpu().numpy(), ref)
+    # couplings are read at launch time: new values in a streamed-J task's J
+    # buffer are staged again by the next replay
+    c2 = Case(300, 3, 20, 120, key=(45,), sigma=0.03)  # same shape as task 1, other couplings
+    tasks[1]["J"].copy_(to_dev(c2.J))
+    for t, c in zip(tasks, cases):
+        t["x"].copy_(to_dev(c.x0))
+    b.launch()
+    torch.cuda.synchronize()
+    Jd, pump, _, alpha = cases[1].gpu_inputs()
+    x1 = to_dev(cases[1].x0)
+    api.chym_integrate(to_dev(c2.J), pump, x1, alpha, steps=cases[1].steps, precision="bf16", **cases[1].params())
+    assert np.array_equal(tasks[1]["x"].cpu().numpy(), x1.cpu().numpy())
+    assert not np.array_equal(x1.cpu().numpy(), solo[1])
+    for k in (0, 2, 3, 4):
+        assert np.array_equal(tasks[k]["x"].cpu().numpy(), solo[k])
     b.destroy()
