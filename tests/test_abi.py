@@ -285,3 +285,20 @@ def test_ell_pack_layout():
     assert list(e[3, 2:].view(np.float32)) == [0.0, 0.0]
     with pytest.raises(ValueError):
         api.ell_pack(J, width=1)
+
+
+def test_streamed_j_size_limits():
+    """Largest n per d and form that validates: the streamed-J operand of 16
+    replicas (d x terms x 1 KB per 32-row chunk) must fit in 159 KB of LDS and
+    the block's eight wavefronts take at most 8 row tiles each."""
+    lib = L.load()
+
+    def ok(n, d, prec):
+        prob = _prob(n=n, d=d)
+        run = _run(r=16, precision=prec)
+        nb = ctypes.c_size_t(0)
+        return lib.chym_integrate_workspace_size(ctypes.byref(prob), ctypes.byref(run), ctypes.byref(nb)) == L.CHYM_OK
+
+    for d, f32_max in ((1, 1024), (2, 832), (3, 544), (4, 416)):
+        assert ok(f32_max, d, L.CHYM_PREC_F32) and not ok(f32_max + 1, d, L.CHYM_PREC_F32), d
+        assert ok(1024, d, L.CHYM_PREC_BF16) and not ok(1025, d, L.CHYM_PREC_BF16), d
