@@ -32,8 +32,9 @@ def run(case, Jd, precision="f32", x=None, steps=None):
 
 @pytest.mark.parametrize("n,d,r,kind", [(16, 2, 37, "reg3"), (50, 3, 5, "reg3"), (200, 4, 40, "reg3"),
                                         (800, 3, 20, "reg3"), (100, 2, 33, "er"), (40, 1, 16, "sk"),
-                                        (64, 4, 3, "er")])
+                                        (64, 4, 3, "er"), (300, 2, 20, "er")])
 def test_sparse_parity_with_oracle(n, d, r, kind):
+    # (300, 2, 20, "er"): about 60 nonzeros per row, rows past the LDS budget, read from global memory
     case = Case(n, d, r, 500, key=(80, n, d), kind=kind, sigma=0.05)
     xg = run(case, ell_dev(case.J)).cpu().numpy()
     xo = oracle.ode_run(case.J, case.pump, case.x0, steps=case.steps, alpha=case.alpha, **case.params())
@@ -95,7 +96,7 @@ def test_sparse_tasks_in_a_batch_equal_solo_runs():
     # same batch; every task must equal its own single call bit for bit
     specs = [(120, 3, 48, "reg3", True), (400, 2, 40, "reg3", True), (64, 4, 21, "er", True),
              (800, 3, 20, "reg3", True), (40, 1, 16, "sk", True), (100, 3, 33, "sk", False),
-             (48, 2, 17, "reg3", False)]
+             (48, 2, 17, "reg3", False), (300, 2, 20, "er", True)]
     tasks, want, cases = [], [], []
     for k, (n, d, r, kind, sparse) in enumerate(specs):
         case = Case(n, d, r, 300, key=(84, k), kind=kind, sigma=0.05)
