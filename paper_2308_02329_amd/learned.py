@@ -8,7 +8,7 @@ that checkpoint each pump's batch of runs keeps its highest-scored fraction
 and the others are abandoned and restarted from fresh initial states (a
 rank within the batch, not an absolute threshold: the network's scores are
 not calibrated across instances).
-Every kept run is still integrated to the end and judged by its exact Ising
+Every kept run is still integrated to the end and scored by its exact Ising
 energy, so the method's answers are unchanged; only the cost per success
 changes.  The plain method (no restarts) is the fallback.
 

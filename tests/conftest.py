@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped (not failed) when no GPU is present, so the CPU
-    # suite can run everything else; on a GPU machine they run.
+    # suite can run everything else; on a machine with the GPU they run.
     try:
         import torch
 
