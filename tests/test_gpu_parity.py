@@ -43,7 +43,7 @@ def compare_trajectory(case, chunk, precision="f32"):
     return worst, x.cpu().numpy(), xo
 
 
-def test_config1_trajectory_and_scores():
+def test_n16_d2_640_runs_trajectory_and_scores():
     """N=16 SK, D=2, 64 initial states x 10 pumps, 2000 steps with the anneal."""
     case = Case(16, 2, 640, 2000, key=(0, 0), pumps=synth.pump_grid(64, np.linspace(0.5, 2.0, 10)))
     worst, xg, xo = compare_trajectory(case, 100)

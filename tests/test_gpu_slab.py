@@ -50,7 +50,7 @@ def test_slab_parity_f32(n, d, r, steps, kind):
     assert err <= 1e-4, err
 
 
-def test_slab_bf16_at_config3_shape():
+def test_slab_bf16_at_n1000_d4():
     """N = 1000, D = 4, bf16 form (the precision workload's shape, few
     replicas): error against the oracle bounded loosely, readout exact."""
     case = Case(1000, 4, 16, 60, key=(42,), sigma=0.05)
