@@ -274,30 +274,43 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0, co
                     }
                     split8<XS>(v8, bx[mu], negk);
                 }
-                bf16x8 af[JS][NT];
-#pragma unroll
-                for (int I = 0; I < NT; ++I)
-#pragma unroll
-                    for (int t = 0; t < JS; ++t) {
-                        if constexpr (JLDS)
-                            af[t][I] = jl[((t * NT + I) * NC + c) * 64 + lane];
-                        else
-                            af[t][I] = jr[JLDS ? 0 : t][JLDS ? 0 : I][JLDS ? 0 : c];
-                    }
-                // term pairs (J term, state term), smallest first; consecutive
-                // instructions write different accumulators
+                // term pairs (J term, state term), smallest first
                 constexpr int NP = JS == 1 ? XS : 6;
                 constexpr int pj[6] = {JS == 1 ? 0 : 2, JS == 1 ? 0 : 1, 0, JS == 1 ? 0 : 1, 0, 0};
                 constexpr int px[6] = {JS == 1 ? XS - 1 : 0, JS == 1 ? (XS > 1 ? XS - 2 : 0) : 1,
                                        JS == 1 ? 0 : 2, 0, 1, 0};
+                // row tiles in groups of TG, each accumulator taking its term
+                // pairs in the order above whatever TG is: with D >= 3 one tile
+                // at a time (its J fragments are the only ones live, and its D
+                // accumulators separate two products into one accumulator),
+                // which lets the two-wavefronts-per-SIMD kernel keep its state
+                // in registers; with D <= 2 all tiles at once (measured faster:
+                // 2 D accumulators between dependent products are too few)
+                constexpr int TG = D >= 3 ? 1 : NT;
 #pragma unroll
-                for (int q = 0; q < NP; ++q)
+                for (int I0 = 0; I0 < NT; I0 += TG) {
+                    bf16x8 af[TG][JS];
 #pragma unroll
-                    for (int I = 0; I < NT; ++I)
+                    for (int i = 0; i < TG; ++i) {
+                        const int I = I0 + i < NT ? I0 + i : I0;  // past the end: unused
 #pragma unroll
-                        for (int mu = 0; mu < D; ++mu)
-                            acc[I][mu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[pj[q]][I], bx[mu].t[px[q]],
-                                                                                acc[I][mu], 0, 0, 0);
+                        for (int t = 0; t < JS; ++t) {
+                            if constexpr (JLDS)
+                                af[i][t] = jl[((t * NT + I) * NC + c) * 64 + lane];
+                            else
+                                af[i][t] = jr[JLDS ? 0 : t][JLDS ? 0 : I][JLDS ? 0 : c];
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < NP; ++q)
+#pragma unroll
+                        for (int i = 0; i < TG; ++i)
+#pragma unroll
+                            for (int mu = 0; mu < D; ++mu)
+                                if (I0 + i < NT)
+                                    acc[I0 + i][mu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                        af[i][pj[q]], bx[mu].t[px[q]], acc[I0 + i][mu], 0, 0, 0);
+                }
     
             }
 
