@@ -37,11 +37,9 @@ PEAK_FP32_MATRIX_TFLOPS = 157.3
 # HBM bytes per launch of the dominant kernel on the default workload, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by the same counters on the
 # bench's own 4 GB state copy (profiles/integrate_persistent_sk100_d23_f32.md);
-# keyed by kernel and workload, valid for the kernels as they are now.  The
-# two-wavefronts-per-SIMD kernel spills registers at D = 3: its scratch
-# stores make most of its figure.
+# keyed by kernel and workload, valid for the kernels as they are now.
 TRAFFIC = {("k_integrate_persistent<7, 3, 3, 1, false>", 100, 1000, 2000): 4.921e9,
-           ("k_integrate_persistent_lds<7, 3, 3, 1, 2>", 100, 1000, 2000): 5.866e11}
+           ("k_integrate_persistent_lds<7, 3, 3, 1, 2>", 100, 1000, 2000): 1.031e10}
 
 
 def kernel_name(tiles, d, precision, plan):

@@ -214,6 +214,16 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0, co
     const float ned = -(a.dt * a.eta);
     const float dte = a.dt * a.eps;
 
+    // D = 3 with J in LDS: the state (NT * 12 registers), the accumulators
+    // (as many) and the three split terms of every component (36) leave no
+    // room at two wavefronts per SIMD, and the compiler spills.  There the
+    // local part is formed after the contraction from x, which stays whole
+    // (no separate y while x is live), one component is split at a time, and
+    // a scheduling barrier closes every chunk, so that nothing is hoisted
+    // into an earlier chunk.  The arithmetic and every summation order are
+    // unchanged, so the result is bit-identical.
+    constexpr bool CO = JLDS && D == 3 && !MAP;
+
     for (int k = 0; k < a.steps; ++k) {
             if constexpr (JLDS) {
                 // keep the J fragments in LDS: reload them every step instead of
@@ -223,7 +233,11 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0, co
             const float *al = a.alpha + (size_t)(a.start_step + k) * D;
             float ga[D];
 #pragma unroll
-            for (int mu = 0; mu < D; ++mu) ga[mu] = dte * al[mu];
+            for (int mu = 0; mu < D; ++mu) {
+                // wave-uniform: kept in scalar registers
+                const float w = dte * al[mu];
+                ga[mu] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(w)));
+            }
 
             // The update is x <- y + dt eps alpha_mu G with the local part
             // y = x (1 + dt (r-1) - dt btil S - dt eta x^2).  y is formed tile by
@@ -242,7 +256,7 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0, co
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int I = 2 * c + h;
-                    if (I < NT) {
+                    if (I < NT && !CO) {
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
                             if constexpr (MAP) {
@@ -262,56 +276,89 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0, co
                         }
                     }
                 }
-                // B operands of chunk c straight from the lane's own registers
-                XSplit<XS> bx[D];
+                if constexpr (CO) {
+                    // one component at a time: split, and its products for every
+                    // row tile (the J fragment reads of the D components are the
+                    // same loads, which the compiler merges)
+                    constexpr int NP = JS == 1 ? XS : 6;
+                    constexpr int pj[6] = {JS == 1 ? 0 : 2, JS == 1 ? 0 : 1, 0, JS == 1 ? 0 : 1, 0, 0};
+                    constexpr int px[6] = {JS == 1 ? XS - 1 : 0, JS == 1 ? (XS > 1 ? XS - 2 : 0) : 1,
+                                           JS == 1 ? 0 : 2, 0, 1, 0};
 #pragma unroll
-                for (int mu = 0; mu < D; ++mu) {
-                    float v8[8];
+                    for (int mu = 0; mu < D; ++mu) {
+                        XSplit<XS> bm;
+                        {
+                            float v8[8];
 #pragma unroll
-                    for (int s = 0; s < 8; ++s) {
-                        const int tile = 2 * c + (s >> 2);
-                        v8[s] = (tile < NT) ? x[tile < NT ? tile : 0][mu][s & 3] : 0.0f;
-                    }
-                    split8<XS>(v8, bx[mu], negk);
-                }
-                // term pairs (J term, state term), smallest first
-                constexpr int NP = JS == 1 ? XS : 6;
-                constexpr int pj[6] = {JS == 1 ? 0 : 2, JS == 1 ? 0 : 1, 0, JS == 1 ? 0 : 1, 0, 0};
-                constexpr int px[6] = {JS == 1 ? XS - 1 : 0, JS == 1 ? (XS > 1 ? XS - 2 : 0) : 1,
-                                       JS == 1 ? 0 : 2, 0, 1, 0};
-                // row tiles in groups of TG, each accumulator taking its term
-                // pairs in the order above whatever TG is: with D >= 3 one tile
-                // at a time (its J fragments are the only ones live, and its D
-                // accumulators separate two products into one accumulator),
-                // which lets the two-wavefronts-per-SIMD kernel keep its state
-                // in registers; with D <= 2 all tiles at once (measured faster:
-                // 2 D accumulators between dependent products are too few)
-                constexpr int TG = D >= 3 ? 1 : NT;
-#pragma unroll
-                for (int I0 = 0; I0 < NT; I0 += TG) {
-                    bf16x8 af[TG][JS];
-#pragma unroll
-                    for (int i = 0; i < TG; ++i) {
-                        const int I = I0 + i < NT ? I0 + i : I0;  // past the end: unused
-#pragma unroll
-                        for (int t = 0; t < JS; ++t) {
-                            if constexpr (JLDS)
-                                af[i][t] = jl[((t * NT + I) * NC + c) * 64 + lane];
-                            else
-                                af[i][t] = jr[JLDS ? 0 : t][JLDS ? 0 : I][JLDS ? 0 : c];
+                            for (int s = 0; s < 8; ++s) {
+                                const int tile = 2 * c + (s >> 2);
+                                v8[s] = (tile < NT) ? x[tile < NT ? tile : 0][mu][s & 3] : 0.0f;
+                            }
+                            split8<XS>(v8, bm, negk);
                         }
+                        bf16x8 af[NT][JS];
+#pragma unroll
+                        for (int I = 0; I < NT; ++I)
+#pragma unroll
+                            for (int t = 0; t < JS; ++t) af[I][t] = jl[((t * NT + I) * NC + c) * 64 + lane];
+#pragma unroll
+                        for (int q = 0; q < NP; ++q)
+#pragma unroll
+                            for (int I = 0; I < NT; ++I)
+                                acc[I][mu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[I][pj[q]], bm.t[px[q]],
+                                                                                     acc[I][mu], 0, 0, 0);
                     }
+                    __builtin_amdgcn_sched_barrier(0);
+                } else {
+                    // term pairs (J term, state term), smallest first
+                    constexpr int NP = JS == 1 ? XS : 6;
+                    constexpr int pj[6] = {JS == 1 ? 0 : 2, JS == 1 ? 0 : 1, 0, JS == 1 ? 0 : 1, 0, 0};
+                    constexpr int px[6] = {JS == 1 ? XS - 1 : 0, JS == 1 ? (XS > 1 ? XS - 2 : 0) : 1,
+                                           JS == 1 ? 0 : 2, 0, 1, 0};
+                    // B operands of chunk c straight from the lane's own registers
+                    XSplit<XS> bx[D];
 #pragma unroll
-                    for (int q = 0; q < NP; ++q)
+                    for (int mu = 0; mu < D; ++mu) {
+                        float v8[8];
 #pragma unroll
-                        for (int i = 0; i < TG; ++i)
+                        for (int s = 0; s < 8; ++s) {
+                            const int tile = 2 * c + (s >> 2);
+                            v8[s] = (tile < NT) ? x[tile < NT ? tile : 0][mu][s & 3] : 0.0f;
+                        }
+                        split8<XS>(v8, bx[mu], negk);
+                    }
+                    // row tiles in groups of TG, each accumulator taking its term
+                    // pairs in the order above whatever TG is: with D >= 3 one tile
+                    // at a time (its J fragments are the only ones live, and its D
+                    // accumulators separate two products into one accumulator);
+                    // with D <= 2 all tiles at once (measured faster: 2 D
+                    // accumulators between dependent products are too few)
+                    constexpr int TG = D >= 3 ? 1 : NT;
 #pragma unroll
-                            for (int mu = 0; mu < D; ++mu)
-                                if (I0 + i < NT)
-                                    acc[I0 + i][mu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                        af[i][pj[q]], bx[mu].t[px[q]], acc[I0 + i][mu], 0, 0, 0);
+                    for (int I0 = 0; I0 < NT; I0 += TG) {
+                        bf16x8 af[TG][JS];
+#pragma unroll
+                        for (int i = 0; i < TG; ++i) {
+                            const int I = I0 + i < NT ? I0 + i : I0;  // past the end: unused
+#pragma unroll
+                            for (int t = 0; t < JS; ++t) {
+                                if constexpr (JLDS)
+                                    af[i][t] = jl[((t * NT + I) * NC + c) * 64 + lane];
+                                else
+                                    af[i][t] = jr[JLDS ? 0 : t][JLDS ? 0 : I][JLDS ? 0 : c];
+                            }
+                        }
+#pragma unroll
+                        for (int q = 0; q < NP; ++q)
+#pragma unroll
+                            for (int i = 0; i < TG; ++i)
+#pragma unroll
+                                for (int mu = 0; mu < D; ++mu)
+                                    if (I0 + i < NT)
+                                        acc[I0 + i][mu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                            af[i][pj[q]], bx[mu].t[px[q]], acc[I0 + i][mu], 0, 0, 0);
+                    }
                 }
-    
             }
 
 #pragma unroll
@@ -319,7 +366,21 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0, co
 #pragma unroll
                 for (int mu = 0; mu < D; ++mu)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) x[I][mu][v] = fmaf(ga[mu], acc[I][mu][v], y[I][mu][v]);
+                    for (int v = 0; v < 4; ++v) {
+                        if (CO && mu == 0) {
+                            // the local part, as in the chunks of the other variants
+                            float x2[D];
+#pragma unroll
+                            for (int m = 0; m < D; ++m) x2[m] = x[I][m][v] * x[I][m][v];
+                            float S = x2[0];
+#pragma unroll
+                            for (int m = 1; m < D; ++m) S = S + x2[m];
+                            const float cc = fmaf(nbd, S, base);
+#pragma unroll
+                            for (int m = 0; m < D; ++m) y[I][m][v] = x[I][m][v] * fmaf(ned, x2[m], cc);
+                        }
+                        x[I][mu][v] = fmaf(ga[mu], acc[I][mu][v], y[I][mu][v]);
+                    }
     }
 
     // ---- store ----
