@@ -106,6 +106,84 @@ __device__ void ising_one(int n, int rep, const void *__restrict__ j, int j_dtyp
     }
 }
 
+// Ising energy of up to 64 replicas of one problem with int8 couplings, one
+// replica per lane (lanes with mine = false compute nothing and store
+// nothing); W >= ceil(n / 64) spin words per replica, n <= 64 W.  Row p of J
+// is read 64 columns at a time, one column per lane, and the ballots of
+// J = +1 and J = -1 over the wavefront give the row's masks P and M for those
+// columns.  With sigma_q = 2 b_q - 1 (b the spin bit) the +-1 entries add
+// 2 popc(b & P) - popc(P) - 2 popc(b & M) + popc(M) to sum_q J_pq sigma_q,
+// and the entries of other magnitude (ballot X) are added one by one: the
+// result is the exact int32 energy, the same as the row walk of ising_one.
+template <int W>
+__device__ void ising_lanes(int n, int rep, bool mine, const int8_t *__restrict__ J,
+                            const uint64_t *__restrict__ spins, int32_t *__restrict__ e_i32,
+                            double *__restrict__ e_f64) {
+    const int lane = threadIdx.x & 63;
+    const int w = (n + 63) >> 6;
+    uint64_t b[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) b[k] = (mine && k < w) ? spins[(size_t)rep * w + k] : 0ull;
+    int acc = 0;
+#pragma unroll
+    for (int kp = 0; kp < W; ++kp) {
+        const int pend = min(64, n - 64 * kp);
+        for (int pp = 0; pp < pend; ++pp) {
+            const int8_t *row = J + (size_t)(64 * kp + pp) * n;
+            int h = 0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                if (64 * k >= n) break;
+                const int q = 64 * k + lane;
+                const int v = q < n ? (int)row[q] : 0;
+                const uint64_t P = __ballot(v == 1);
+                const uint64_t M = __ballot(v == -1);
+                uint64_t X = __ballot(v > 1 || v < -1);
+                h += 2 * (__popcll(b[k] & P) - __popcll(b[k] & M)) - (__popcll(P) - __popcll(M));
+                while (X) {
+                    const int t = __ffsll((unsigned long long)X) - 1;
+                    X &= X - 1;
+                    const int jv = __shfl(v, t, 64);
+                    h += ((b[k] >> t) & 1ull) ? jv : -jv;
+                }
+            }
+            acc += ((b[kp] >> pp) & 1ull) ? h : -h;
+        }
+    }
+    if (mine) {
+        if (e_i32) e_i32[rep] = -acc;
+        if (e_f64) e_f64[rep] = -(double)acc;
+    }
+}
+
+// Largest n of the lane-per-replica path (16 spin words).
+constexpr int kIsingLanesMaxN = 1024;
+
+__device__ __forceinline__ void ising_lanes_any(int n, int rep, bool mine, const int8_t *J, const uint64_t *spins,
+                                                int32_t *e_i32, double *e_f64) {
+    const int w = (n + 63) >> 6;
+    if (w <= 1) ising_lanes<1>(n, rep, mine, J, spins, e_i32, e_f64);
+    else if (w <= 2) ising_lanes<2>(n, rep, mine, J, spins, e_i32, e_f64);
+    else if (w <= 4) ising_lanes<4>(n, rep, mine, J, spins, e_i32, e_f64);
+    else if (w <= 8) ising_lanes<8>(n, rep, mine, J, spins, e_i32, e_f64);
+    else ising_lanes<16>(n, rep, mine, J, spins, e_i32, e_f64);
+}
+
+__device__ __forceinline__ bool ising_by_lanes(int n, int j_dtype) {
+    return j_dtype == CHYM_J_I8 && n <= kIsingLanesMaxN;
+}
+
+// One problem, int8 couplings, n <= kIsingLanesMaxN: wavefront w takes
+// replicas 64 w .. 64 w + 63.
+__global__ __launch_bounds__(256) void k_ising_energy_lanes(int n, int r, const int8_t *__restrict__ J,
+                                                            const uint64_t *__restrict__ spins,
+                                                            int32_t *__restrict__ e_i32, double *__restrict__ e_f64) {
+    const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (wave * 64 >= r) return;
+    const int rep = wave * 64 + (threadIdx.x & 63);
+    ising_lanes_any(n, rep, rep < r, J, spins, e_i32, e_f64);
+}
+
 __global__ __launch_bounds__(256) void k_ising_energy(int n, int r, const void *__restrict__ j, int j_dtype,
                                                       const uint64_t *__restrict__ spins,
                                                       int32_t *__restrict__ e_i32, double *__restrict__ e_f64) {
@@ -197,15 +275,33 @@ __global__ __launch_bounds__(256) void k_readout_batched(const ScoreArgs *__rest
     }
 }
 
+// Each wavefront takes 64 consecutive global replicas at a time and walks the
+// tasks they belong to: int8 problems with n <= kIsingLanesMaxN one replica
+// per lane, the others one replica per wavefront.
 __global__ __launch_bounds__(256) void k_ising_batched(const ScoreArgs *__restrict__ t, const int64_t *__restrict__ first,
                                                        int n_tasks) {
     const int64_t total = first[n_tasks];
+    const int lane = threadIdx.x & 63;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g < total; g += waves) {
-        const int k = __builtin_amdgcn_readfirstlane(task_of(first, n_tasks, g));
-        const ScoreArgs &a = t[k];
-        if (!a.e_i32 && !a.e_f64) continue;
-        ising_one(a.n, (int)(g - first[k]), a.j, a.j_dtype, a.spins, a.e_i32, a.e_f64);
+    for (int64_t g0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; g0 < total;
+         g0 += waves * 64) {
+        const int64_t g1 = min(g0 + 64, total);  // end of this group
+        const int k0 = __builtin_amdgcn_readfirstlane(task_of(first, n_tasks, g0));
+        const int k1 = __builtin_amdgcn_readfirstlane(task_of(first, n_tasks, g1 - 1));
+        for (int k = k0; k <= k1; ++k) {
+            const ScoreArgs &a = t[k];
+            if (!a.e_i32 && !a.e_f64) continue;
+            const int64_t lo = max(first[k], g0), hi = min(first[k + 1], g1);
+            if (ising_by_lanes(a.n, a.j_dtype)) {
+                const int64_t g = g0 + lane;
+                const bool mine = g >= lo && g < hi;
+                ising_lanes_any(a.n, mine ? (int)(g - first[k]) : 0, mine, reinterpret_cast<const int8_t *>(a.j),
+                                a.spins, a.e_i32, a.e_f64);
+            } else {
+                for (int64_t g = lo; g < hi; ++g)
+                    ising_one(a.n, (int)(g - first[k]), a.j, a.j_dtype, a.spins, a.e_i32, a.e_f64);
+            }
+        }
     }
 }
 
@@ -237,6 +333,13 @@ hipError_t launch_readout(int n, int d, int r, const float *x, uint64_t *spins, 
 hipError_t launch_ising_energy(int n, int r, const void *j, int j_dtype, const uint64_t *spins, int32_t *e_i32,
                                double *e_f64, hipStream_t stream) {
     const int waves = 4;
+    if (j_dtype == CHYM_J_I8 && n <= kIsingLanesMaxN) {
+        const int grid = (r + 64 * waves - 1) / (64 * waves);
+        if (grid == 0) return hipSuccess;
+        hipLaunchKernelGGL(k_ising_energy_lanes, dim3(grid), dim3(64 * waves), 0, stream, n, r,
+                           reinterpret_cast<const int8_t *>(j), spins, e_i32, e_f64);
+        return hipGetLastError();
+    }
     const int grid = (r + waves - 1) / waves;
     hipLaunchKernelGGL(k_ising_energy, dim3(grid), dim3(64 * waves), 0, stream, n, r, j, j_dtype, spins, e_i32,
                        e_f64);
@@ -262,7 +365,7 @@ hipError_t launch_score_batched(const ScoreArgs *tasks, const int64_t *first, in
         if (e != hipSuccess) return e;
     }
     if (any_ising) {
-        int grid = (int)std::min<int64_t>((total_replicas + 3) / 4, grid_cap);
+        int grid = (int)std::min<int64_t>((total_replicas + 255) / 256, grid_cap);
         hipLaunchKernelGGL(k_ising_batched, dim3(grid), dim3(256), 0, stream, tasks, first, n_tasks);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
