@@ -192,6 +192,42 @@ __global__ __launch_bounds__(256) void k_ising_energy(int n, int r, const void *
     ising_one(n, rep, j, j_dtype, spins, e_i32, e_f64);
 }
 
+// Dense part of E_hs for one replica with int8 couplings: sum over the
+// lane's columns q of sum_p J_pq (u_p . u_q), u in LDS [n][D].  Four rows at
+// a time into four partial sums (independent chains).
+template <int D>
+__device__ double hs_dense_i8(int n, const int8_t *__restrict__ J, const double *u) {
+    const int lane = threadIdx.x & 63;
+    double acc = 0.0;
+#pragma unroll 1
+    for (int q = lane; q < n; q += 64) {
+        double uq[D];
+#pragma unroll
+        for (int mu = 0; mu < D; ++mu) uq[mu] = u[q * D + mu];
+        double h[4] = {0.0, 0.0, 0.0, 0.0};
+        int p = 0;
+#pragma unroll 1
+        for (; p + 4 <= n; p += 4) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                double dot = 0.0;
+#pragma unroll
+                for (int mu = 0; mu < D; ++mu) dot = fma(u[(p + i) * D + mu], uq[mu], dot);
+                h[i] = fma((double)J[(size_t)(p + i) * n + q], dot, h[i]);
+            }
+        }
+#pragma unroll 1
+        for (; p < n; ++p) {
+            double dot = 0.0;
+#pragma unroll
+            for (int mu = 0; mu < D; ++mu) dot = fma(u[p * D + mu], uq[mu], dot);
+            h[0] = fma((double)J[(size_t)p * n + q], dot, h[0]);
+        }
+        acc += (h[0] + h[1]) + (h[2] + h[3]);
+    }
+    return acc;
+}
+
 // Hyperspin energy of one replica by one wavefront, u = its private LDS
 // area [n][d].  The unit vectors u_p = x_p / |x_p| (0 for a zero hyperspin)
 // are formed in float64, then E_hs = -sum_q sum_p J_pq (u_p . u_q) with
@@ -226,6 +262,14 @@ __device__ void hs_one(int n, int d, int r, int rep, const void *__restrict__ j,
                 h = h + (double)__int_as_float(row[e.w + k]) * dot;
             }
             acc += h;
+        }
+    } else if (j_dtype == CHYM_J_I8) {
+        const int8_t *J8 = reinterpret_cast<const int8_t *>(j);
+        switch (d) {
+            case 1: acc = hs_dense_i8<1>(n, J8, u); break;
+            case 2: acc = hs_dense_i8<2>(n, J8, u); break;
+            case 3: acc = hs_dense_i8<3>(n, J8, u); break;
+            default: acc = hs_dense_i8<4>(n, J8, u); break;
         }
     } else {
         for (int q = lane; q < n; q += 64) {
