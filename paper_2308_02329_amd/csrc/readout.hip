@@ -349,19 +349,50 @@ __global__ __launch_bounds__(256) void k_ising_batched(const ScoreArgs *__restri
     }
 }
 
-// LDS: one [max n*d] float64 area per wavefront.
+// Replicas per block pass of k_hs_batched, and the LDS area for one int8
+// coupling matrix (n <= 128) staged once per block pass and task.
+constexpr int kHsBlockReplicas = 64;
+constexpr int kHsJBytes = 128 * 128;
+
+// LDS: one [max n*d] float64 area per wavefront, then (jl_bytes > 0) an int8
+// J area of jl_bytes.  Each block takes kHsBlockReplicas consecutive global
+// replicas at a time and walks the tasks they span; an int8 task with
+// n * n <= jl_bytes is read from the block's LDS copy of J instead of global
+// memory.  Block-uniform control flow around the barriers: the pass, the
+// task and its LDS decision are the same for every thread of the block.
 __global__ __launch_bounds__(256) void k_hs_batched(const ScoreArgs *__restrict__ t, const int64_t *__restrict__ first,
-                                                    int n_tasks, int max_nd) {
+                                                    int n_tasks, int max_nd, int jl_bytes) {
     extern __shared__ double u_all[];
-    double *u = u_all + (size_t)(threadIdx.x >> 6) * max_nd;
+    const int nw = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6;
+    double *u = u_all + (size_t)wave * max_nd;
+    int8_t *jl = reinterpret_cast<int8_t *>(u_all + (size_t)nw * max_nd);
     const int64_t total = first[n_tasks];
-    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g < total; g += waves) {
-        const int k = __builtin_amdgcn_readfirstlane(task_of(first, n_tasks, g));
-        const ScoreArgs &a = t[k];
-        if (!a.e_hs) continue;
-        hs_one(a.n, a.d, a.r, (int)(g - first[k]), a.j, a.j_dtype, a.x, a.e_hs, u);
-        __builtin_amdgcn_wave_barrier();  // u is rewritten by the next replica
+    for (int64_t b0 = (int64_t)blockIdx.x * kHsBlockReplicas; b0 < total;
+         b0 += (int64_t)gridDim.x * kHsBlockReplicas) {
+        const int64_t b1 = min(b0 + (int64_t)kHsBlockReplicas, total);
+        int k = __builtin_amdgcn_readfirstlane(task_of(first, n_tasks, b0));
+        for (int64_t s0 = b0; s0 < b1; ++k) {
+            const int64_t s1 = min(first[k + 1], b1);
+            if (s1 <= s0) continue;  // empty task
+            const ScoreArgs &a = t[k];
+            if (a.e_hs) {
+                const bool staged = a.j_dtype == CHYM_J_I8 && a.n * a.n <= jl_bytes;
+                if (staged) {
+                    __syncthreads();  // the previous task's readers are done
+                    const int8_t *J = reinterpret_cast<const int8_t *>(a.j);
+                    for (int i = threadIdx.x; i < a.n * a.n; i += blockDim.x) jl[i] = J[i];
+                    __syncthreads();
+                }
+                for (int64_t g = s0 + wave; g < s1; g += nw) {
+                    // two call sites, so that the staged one reads J with LDS instructions
+                    if (staged) hs_one(a.n, a.d, a.r, (int)(g - first[k]), jl, a.j_dtype, a.x, a.e_hs, u);
+                    else hs_one(a.n, a.d, a.r, (int)(g - first[k]), a.j, a.j_dtype, a.x, a.e_hs, u);
+                    __builtin_amdgcn_wave_barrier();  // u is rewritten by the next replica
+                }
+            }
+            s0 = s1;
+        }
     }
 }
 
@@ -416,9 +447,12 @@ hipError_t launch_score_batched(const ScoreArgs *tasks, const int64_t *first, in
     }
     if (any_hs) {
         const int waves = max_nd <= 2048 ? 4 : 1;
-        const size_t lds = sizeof(double) * (size_t)max_nd * waves;
-        int grid = (int)std::min<int64_t>((total_replicas + waves - 1) / waves, grid_cap);
-        hipLaunchKernelGGL(k_hs_batched, dim3(grid), dim3(64 * waves), lds, stream, tasks, first, n_tasks, max_nd);
+        const size_t lds_u = sizeof(double) * (size_t)max_nd * waves;
+        const int jl_bytes = lds_u + kHsJBytes <= 64 * 1024 ? kHsJBytes : 0;
+        const size_t lds = lds_u + (size_t)jl_bytes;
+        int grid = (int)std::min<int64_t>((total_replicas + kHsBlockReplicas - 1) / kHsBlockReplicas, grid_cap);
+        hipLaunchKernelGGL(k_hs_batched, dim3(grid), dim3(64 * waves), lds, stream, tasks, first, n_tasks, max_nd,
+                           jl_bytes);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
