@@ -33,8 +33,6 @@ def test_int8_energy_exact(n, r):
     rng = np.random.default_rng(n * 1000 + r)
     sig = rng.choice(np.array([-1, 1], dtype=np.int8), size=(r, n))
     spins = to_dev(pack_spins(sig))
-    want = oracle.ising_energy(np.zeros((n, n), dtype=np.int8), sig)  # shape check of the oracle call
-    assert want.shape == (r,)
     for J in (mixed_j(n, 7 + n), np.sign(mixed_j(n, 8 + n)).astype(np.int8)):
         want = oracle.ising_energy(J, sig)
         e32 = torch.full((r,), 123456789, dtype=torch.int32, device="cuda")
