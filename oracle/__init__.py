@@ -16,7 +16,11 @@ Parity status of each routine (how it is pinned, see tests/test_oracle_*):
                     eigendecomposition / matrix products, D = 1 reduction to
                     the CIM, gauge / Z2 / O(D) covariance, Eq. (2) limit.
 * map_run        -- pinned: small-signal gain, K against RK4 of the
-                    coupled-mode equations, convergence to ode_run.
+                    coupled-mode equations, convergence to ode_run, the
+                    annealing weight alpha_{mu,tau} by the linearised map's
+                    closed form (eigendecomposition, alpha per component)
+                    and by explicit products (non-symmetric J, alpha per
+                    round trip started mid-table), split runs.
 * readout, ising_energy, bruteforce_gs -- pinned by exhaustive enumeration
                     in pure Python and by the spin-flip symmetry.
 * hs_energy      -- pinned: D = 1 equals the Ising energy, two-spin closed

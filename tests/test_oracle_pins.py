@@ -394,3 +394,78 @@ def test_map_converges_to_ode_first_order():
     assert errs[2] < 0.03
     for e1, e2 in zip(errs, errs[1:]):
         assert 1.6 < e1 / e2 < 2.5
+
+
+# ------------------------- the map's annealing weight C_jl -> alpha_{mu,tau} C_jl
+def _small_signal_map_matrix(J, h, b, dd, kl, a_mu):
+    """Eq. (2) linearised at vanishing amplitude with beta = 0: the medium
+    multiplies by its small-signal gain exp(kL h), the coupler mixes
+    (1-b) B + b alpha_mu J B, the loss keeps (1-d).  Written from the
+    equation, not from the oracle."""
+    n = J.shape[0]
+    return (1.0 - dd) * math.exp(kl * h) * ((1.0 - b) * np.eye(n) + b * a_mu * J)
+
+
+def test_map_linear_closed_form_alpha_per_component():
+    """beta = 0 and amplitudes <= 1e-8, so K = exp(kL h) to first order
+    (the depletion term is (kL A)^2 / 2 ~ 1e-18 relative): the map is then
+    linear per component, A_k = M_mu^k A_0 with a different alpha for every
+    component, computed by eigendecomposition of the symmetric J.  A wrong
+    component or step index of alpha, a dropped (1-b) or (1-d), or the
+    coupling applied to A instead of B = K A fails."""
+    n, r, d = 9, 3, 3
+    J = synth.sk_pm1(n, 104, 0).astype(np.float64) * 0.3
+    g = np.random.default_rng(11)
+    A0 = g.standard_normal((n, r, d)) * 1e-9
+    b, dd, kl = 0.02, 0.01, 0.1
+    h = np.array([0.05, 0.2, 0.31])        # below and near the uncoupled threshold
+    avec = np.array([1.0, 0.6, -0.35])
+    k = 120
+    A = oracle.map_run(J, h, A0, b, dd, kl, 7.0, k, np.tile(avec, (k, 1)))
+    # beta enters only through B S(B) ~ 1e-18 relative at these amplitudes
+    assert np.abs(A).max() < 1e-7
+    w, V = np.linalg.eigh(J)
+    for i in range(r):
+        for mu in range(d):
+            lam = (1.0 - dd) * math.exp(kl * h[i]) * ((1.0 - b) + b * avec[mu] * w)
+            ref = V @ (lam ** k * (V.T @ A0[:, i, mu]))
+            np.testing.assert_allclose(A[:, i, mu], ref, rtol=1e-10, atol=1e-22)
+
+
+def test_map_asymmetric_coupling_time_varying_alpha():
+    """Non-symmetric couplings and an alpha that changes with the round trip
+    and the component, started in the middle of the table: the coupling must
+    be sum_l J_pl B_l (row p) and round trip tau must use alpha row tau.
+    Reference: explicit products of the small-signal map matrices."""
+    n, r, d = 7, 2, 2
+    g = np.random.default_rng(12)
+    J = g.standard_normal((n, n)) * 0.4
+    A0 = g.standard_normal((n, r, d)) * 1e-9
+    b, dd, kl = 0.03, 0.02, 0.1
+    h = np.array([0.1, 0.45])
+    start, k = 17, 60
+    tab = np.stack([np.cos(0.07 * np.arange(start + k)), np.linspace(1.0, -0.5, start + k)], axis=1)
+    A = oracle.map_run(J, h, A0, b, dd, kl, 0.0, k, tab, start_step=start)
+    for i in range(r):
+        for mu in range(d):
+            v = A0[:, i, mu].copy()
+            for s in range(start, start + k):
+                v = _small_signal_map_matrix(J, h[i], b, dd, kl, tab[s, mu]) @ v
+            np.testing.assert_allclose(A[:, i, mu], v, rtol=1e-10, atol=1e-22)
+
+
+def test_map_split_run_with_alpha_table_equals_full_run():
+    """The round trips of one call equal those of two calls that resume at
+    start_step, with an annealing table that changes every round trip."""
+    n, r, d = 6, 3, 3
+    J = synth.sk_pm1(n, 105, 0).astype(np.float64) * 0.05
+    A0 = np.random.default_rng(13).standard_normal((n, r, d)) * 0.05
+    steps = 90
+    tab, _ = synth.anneal_schedule(steps, d)
+    h = np.array([0.3, 0.5, 0.9])
+    full = oracle.map_run(J, h, A0, 0.01, 0.01, 0.1, 25.0 / 0.01 ** 2, steps, tab)
+    half = oracle.map_run(J, h, A0, 0.01, 0.01, 0.1, 25.0 / 0.01 ** 2, 40, tab)
+    rest = oracle.map_run(J, h, half, 0.01, 0.01, 0.1, 25.0 / 0.01 ** 2, 50, tab, start_step=40)
+    np.testing.assert_array_equal(rest, full)
+    # the table's last rows are zero for the extra components: the anneal acted
+    assert tab[-1, 1:].max() == 0.0 and tab[0].min() == 1.0
