@@ -49,8 +49,14 @@ int slab_tpw_for(int tiles) {
 
 size_t slab_lds_bytes(int tiles, int d, int xs) { return (size_t)((tiles + 1) / 2) * d * xs * 64 * sizeof(bf16x8); }
 
+// The fragments, plus two chunks of padding: the streamed-J kernel's
+// prefetch ring refills two chunks ahead unconditionally, so for the last
+// tile it loads (and discards) up to two chunks past the staged data.  Its
+// offset travels in the scalar operand of the buffer load, which the range
+// check of the buffer resource does not cover; the padding keeps those loads
+// inside the workspace.
 size_t slab_jfrag_bytes(int tiles, int js) {
-    return stage_frag_offset(tiles) + (size_t)tiles * ((tiles + 1) / 2) * js * 64 * sizeof(bf16x8);
+    return stage_frag_offset(tiles) + ((size_t)tiles * ((tiles + 1) / 2) + kSlabRingChunks) * js * 64 * sizeof(bf16x8);
 }
 
 bool slab_variant_exists(int tiles, int d, int xs, int js) {

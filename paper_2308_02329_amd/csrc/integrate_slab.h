@@ -40,6 +40,9 @@ namespace chym {
 //   [256 + S, ...)     fragments: bf16 [tile][chunk][JS][64 lanes] x 16 B, or
 //                      E4M3 [tile][chunk][64 lanes] x 8 B
 constexpr size_t kStageHeader = 256;
+// chunks of J fragments the streamed-J kernel keeps in flight (its prefetch
+// ring); the staging carries that many chunks of padding after the last tile
+constexpr int kSlabRingChunks = 2;
 __host__ __device__ inline size_t stage_scale_bytes(int tiles) { return ((size_t)tiles * 64 + 255) / 256 * 256; }
 __host__ __device__ inline size_t stage_frag_offset(int tiles) { return kStageHeader + stage_scale_bytes(tiles); }
 
@@ -118,7 +121,7 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
     // tiles accumulated together (register budget: 256 per lane at two
     // wavefronts per SIMD, 512 at one)
     constexpr int GS = W == 8 ? (D >= 3 ? 2 : 4) : (D >= 3 ? 4 : 8);
-    constexpr int RD = 2;  // chunks of J fragments in flight (more spills at D = 4)
+    constexpr int RD = kSlabRingChunks;  // chunks of J fragments in flight (more spills at D = 4)
     constexpr int NG = TPW / GS;        // groups of owned tiles
     const int n = a.n;
     const int r = a.r;
@@ -253,10 +256,12 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
                                                                                 acc[i][mu], 0, 0, 0);
             };
             // RD chunks per iteration; the refill of each ring slot is
-            // unconditional (a buffer load past the staged data returns 0 and
-            // is never used), so the slot's next value is always the load
-            // itself and stays in the register the load writes.  The last
-            // ncp % RD chunks are peeled off.
+            // unconditional (past the tile's last chunk it loads the next
+            // tile's fragments, or for the last tile the RD chunks of padding
+            // that slab_jfrag_bytes adds to the staging, and never uses them),
+            // so the slot's next value is always the load itself and stays in
+            // the register the load writes.  The last ncp % RD chunks are
+            // peeled off.
             auto take = [&](int sl, int cnext, bf16x8 (&af)[GS][JS]) __attribute__((always_inline)) {
                 if constexpr (F8) {
 #pragma unroll
