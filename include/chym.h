@@ -285,6 +285,18 @@ int chym_batch_launch_nograph(const chym_batch *plan, chym_stream_t stream);
  * workspace is not touched.  Waits for the plan's outstanding launches. */
 int chym_batch_destroy(chym_batch *plan);
 
+/* One-shot batched solve: the work of chym_batch_create + one
+ * chym_batch_launch_nograph + chym_batch_destroy, without a HIP graph and
+ * without keeping a plan.  The task table is copied into the caller's
+ * workspace (size from chym_batch_workspace_size, 256-byte aligned) on
+ * `stream`, which is synchronized once before the launches are queued; the
+ * launches then run asynchronously on `stream`.  Results are those of the
+ * plan's launches, bit for bit (and so those of one chym_solve per task).
+ * Calls that share a workspace must not overlap.  Errors name the offending
+ * task; nothing is launched if any task is invalid. */
+int chym_solve_batched(const chym_task *tasks, int32_t n_tasks, void *workspace, size_t ws_bytes,
+                       chym_stream_t stream);
+
 /* ------------------------------------------------------------------------
  * Learned early restart.  A small network predicts, from features of the
  * first part of a run, whether the run will reach the Ising ground state;
@@ -389,13 +401,6 @@ int chym_plan_autotune(int32_t n, int32_t d, int32_t precision, int32_t j_dtype,
                        void *workspace, size_t ws_bytes, chym_plan_entry *best, chym_plan_entry *cand,
                        int32_t max_cand, int32_t *n_cand, chym_stream_t stream);
 
-/* The three-term bf16 split that the float32 form feeds to the matrix
- * cores, exposed for verification: for each of the n floats of x (device),
- * hi[i], mid[i], lo[i] (device, bf16 bit patterns) satisfy
- * hi = round-to-nearest-even bf16 of x and hi + mid + lo == x exactly when
- * |x| >= 2^-100 (the residual terms are then normal floats; below that they
- * may be flushed to zero, an error of at most 2^-8 |x|).  n must be a
- * multiple of 8; hi, mid and lo 16-byte aligned. */
 /* Bytes of a coupling matrix of n hyperspins stored as j_dtype. */
 int chym_j_bytes(int32_t n, int32_t j_dtype, size_t *bytes);
 
@@ -409,6 +414,13 @@ int chym_j_bytes(int32_t n, int32_t j_dtype, size_t *bytes);
  * flagged as diverged.  Deterministic; no host synchronization. */
 int chym_quantize_fp8(int32_t n, const float *j, uint8_t *out, chym_stream_t stream);
 
+/* The three-term bf16 split that the float32 form feeds to the matrix
+ * cores, exposed for verification: for each of the n floats of x (device),
+ * hi[i], mid[i], lo[i] (device, bf16 bit patterns) satisfy
+ * hi = round-to-nearest-even bf16 of x and hi + mid + lo == x exactly when
+ * |x| >= 2^-100 (the residual terms are then normal floats; below that they
+ * may be flushed to zero, an error of at most 2^-8 |x|).  n must be a
+ * multiple of 8; hi, mid and lo 16-byte aligned. */
 int chym_split3_bf16(const float *x, int64_t n, uint16_t *hi, uint16_t *mid, uint16_t *lo, chym_stream_t stream);
 
 /* Write the plan table to / merge it from a text file (one entry per line:

@@ -28,8 +28,9 @@ CHYM_PREC_BF16 = 1
 EXPORTS = (
     "chym_version", "chym_last_error", "chym_integrate", "chym_readout", "chym_ising_energy",
     "chym_hs_energy", "chym_solve", "chym_batch_workspace_size", "chym_batch_create",
-    "chym_batch_launch", "chym_batch_launch_nograph", "chym_batch_destroy", "chym_plan_set", "chym_plan_get",
-    "chym_plan_autotune_workspace_size", "chym_plan_autotune", "chym_split3_bf16", "chym_j_bytes", "chym_quantize_fp8", "chym_plan_save",
+    "chym_batch_launch", "chym_batch_launch_nograph", "chym_batch_destroy", "chym_solve_batched", "chym_plan_set",
+    "chym_plan_get", "chym_plan_autotune_workspace_size", "chym_plan_autotune", "chym_split3_bf16", "chym_j_bytes",
+    "chym_quantize_fp8", "chym_plan_save",
     "chym_plan_load", "chym_integrate_workspace_size", "chym_integrate_ws", "chym_solve_ws",
     "chym_sign_words", "chym_features", "chym_mlp_scratch_floats", "chym_mlp_forward", "chym_mlp_backward",
     "chym_mlp_adam", "chym_to_bf16", "chym_map_integrate", "chym_map_batch_workspace_size", "chym_map_batch",
@@ -137,6 +138,8 @@ def _load_batch(lib):
     lib.chym_batch_workspace_size.restype = ctypes.c_int
     lib.chym_batch_create.argtypes = [P(ChymTask), _i32, _vp, ctypes.c_size_t, P(_vp)]
     lib.chym_batch_create.restype = ctypes.c_int
+    lib.chym_solve_batched.argtypes = [P(ChymTask), _i32, _vp, ctypes.c_size_t, _vp]
+    lib.chym_solve_batched.restype = ctypes.c_int
     lib.chym_batch_launch.argtypes = [_vp, _vp]
     lib.chym_batch_launch.restype = ctypes.c_int
     lib.chym_batch_launch_nograph.argtypes = [_vp, _vp]

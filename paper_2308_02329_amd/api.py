@@ -366,6 +366,24 @@ def chym_batch_create(tasks, device=None) -> ChymBatch:
     return ChymBatch(list(tasks), handle, ws, arr)
 
 
+def chym_solve_batched(tasks, stream=None):
+    """One-shot batched solve (no graph, no plan kept): the tasks as for
+    chym_batch_create, integrated and scored in one call on the stream.
+    Returns the workspace tensor, which must stay alive until the launches
+    have run (torch's allocator orders its reuse on the stream)."""
+    lib = L.load()
+    arr = (L.ChymTask * len(tasks))(*[_task_struct(t) for t in tasks])
+    nbytes = ctypes.c_size_t(0)
+    L.check(lib.chym_batch_workspace_size(arr, len(tasks), ctypes.byref(nbytes)), "chym_batch_workspace_size")
+    ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=tasks[0]["x"].device)
+    off = (-ws.data_ptr()) % 256
+    L.check(lib.chym_solve_batched(arr, len(tasks), ctypes.c_void_p(ws.data_ptr() + off), int(nbytes.value),
+                                   _stream(stream)), "chym_solve_batched")
+    if stream is not None:
+        ws.record_stream(stream)
+    return ws
+
+
 def chym_batch_launch(batch: ChymBatch, stream=None):
     L.check(L.load().chym_batch_launch(batch.handle, _stream(stream)), "chym_batch_launch")
 

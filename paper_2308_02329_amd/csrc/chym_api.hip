@@ -1,5 +1,7 @@
 // C ABI of libchym: argument validation, device checks and dispatch.  The
-// kernels live in integrate_resident.hip and readout.hip.
+// kernels live in the integrate_*.hip units (through integrate_kernel.h,
+// integrate_slab.h and integrate_dispatch.hip), integrate_ell.hip,
+// readout.hip, features.hip and quantize.hip.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -619,6 +621,144 @@ int map_batch_layout(const chym_map_problem *probs, const chym_run *runs, int32_
 
 }  // namespace
 
+namespace {
+
+// Validates the tasks, writes the task table and the work list into the
+// caller's workspace (copies on `upload`, which is then synchronized, so the
+// host tables may go away) and, when `want_graph` is set, records the launch
+// sequence as a HIP graph with one branch per variant group.
+int batch_build(const chym_task *tasks, int32_t n_tasks, void *workspace, size_t ws_bytes, bool want_graph,
+                hipStream_t upload, chym_batch **plan) {
+    if (!plan) return fail(CHYM_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    BatchLayout L;
+    int rc = plan_layout(tasks, n_tasks, &L);
+    if (rc) return rc;
+    if (!workspace) return fail(CHYM_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % kAlign) return fail(CHYM_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+    if (ws_bytes < L.total) return fail(CHYM_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+    rc = check_device();
+    if (rc) return rc;
+    chym_batch *b = new (std::nothrow) chym_batch;
+    if (!b) return fail(CHYM_ENOMEM, "out of host memory");
+    b->tasks.assign(tasks, tasks + n_tasks);
+    b->layout = L;
+    b->ws = static_cast<char *>(workspace);
+    hipError_t e = hipGetDevice(&b->device);
+    // occupancy-sized persistent grids
+    int cus = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    b->cus = cus;
+    for (Group &g : b->layout.groups) {
+        int per_cu = 0;
+        if (e == hipSuccess) {
+            if (g.v.ell) e = chym::ell_persistent_occupancy(g.d, g.lds, &per_cu);
+            else if (g.v.slab) e = chym::slab_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, g.lds, &per_cu);
+            else e = chym::persistent_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, g.kind, g.waves, &per_cu);
+        }
+        const int need = (g.v.ell || g.v.slab || g.kind != chym::kKernelRegJ) ? g.n_items
+                                                                              : (g.n_items + g.waves - 1) / g.waves;
+        g.blocks = std::max(1, std::min(need, std::max(1, per_cu) * cus));
+    }
+    // task table and work list
+    std::vector<chym::IntegArgs> targs(n_tasks);
+    for (int t = 0; t < n_tasks; ++t) targs[t] = make_args(&tasks[t].prob, &tasks[t].run);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws + L.off_tasks, targs.data(), sizeof(chym::IntegArgs) * n_tasks,
+                           hipMemcpyHostToDevice, upload);
+    if (e == hipSuccess && !L.items.empty())
+        e = hipMemcpyAsync(b->ws + L.off_items, L.items.data(), sizeof(int2) * L.items.size(), hipMemcpyHostToDevice,
+                           upload);
+    std::vector<chym::ScoreArgs> sargs(n_tasks);
+    std::vector<int64_t> first(n_tasks + 1, 0);
+    for (int t = 0; t < n_tasks; ++t) {
+        const chym_task &tk = tasks[t];
+        chym::ScoreArgs &sa = sargs[t];
+        sa.x = tk.run.x;
+        sa.j = tk.prob.j;
+        sa.spins = tk.out.spins;
+        sa.e_i32 = tk.out.e_ising;
+        sa.e_f64 = tk.out.e_ising_f64;
+        sa.e_hs = tk.out.e_hs;
+        sa.extra = tk.out.extra_frac;
+        sa.diverged = tk.out.diverged;
+        sa.n = tk.prob.n;
+        sa.d = tk.prob.d;
+        sa.r = tk.run.r;
+        sa.j_dtype = tk.prob.j_dtype;
+        first[t + 1] = first[t] + tk.run.r;
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws + L.off_score, sargs.data(), sizeof(chym::ScoreArgs) * n_tasks, hipMemcpyHostToDevice,
+                           upload);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws + L.off_first, first.data(), sizeof(int64_t) * (n_tasks + 1), hipMemcpyHostToDevice,
+                           upload);
+    std::vector<const void *> jfp(n_tasks, nullptr);
+    for (int t = 0; t < n_tasks; ++t)
+        if (L.jf_off[t]) jfp[t] = b->ws + L.jf_off[t];
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws + L.off_jfp, jfp.data(), sizeof(void *) * n_tasks, hipMemcpyHostToDevice, upload);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws + L.off_ncp, L.ncp.data(), sizeof(int) * n_tasks, hipMemcpyHostToDevice, upload);
+    if (e == hipSuccess && !L.stage_list.empty())
+        e = hipMemcpyAsync(b->ws + L.off_list, L.stage_list.data(), sizeof(int) * L.stage_list.size(),
+                           hipMemcpyHostToDevice, upload);
+    if (e == hipSuccess) e = hipStreamSynchronize(upload);  // the host tables are locals
+    if (e != hipSuccess) {
+        release(b);
+        return hip_fail(e, "batch table upload");
+    }
+    if (!want_graph) {
+        *plan = b;
+        return CHYM_OK;
+    }
+    // record the launch sequence as a graph with one branch per variant group
+    e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    const size_t ng = b->layout.groups.size();
+    for (size_t i = 0; e == hipSuccess && ng > 1 && i < ng; ++i) {
+        hipStream_t s;
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e == hipSuccess) b->side.push_back(s);
+    }
+    for (size_t i = 0; e == hipSuccess && ng > 1 && i < ng + 1; ++i) {
+        hipEvent_t ev;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) b->events.push_back(ev);
+    }
+    if (e != hipSuccess) {
+        release(b);
+        return hip_fail(e, "batch setup");
+    }
+    e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        release(b);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    rc = issue_batch(b, b->cap, &b->side, &b->events);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
+    b->graph = graph;
+    if (rc) {
+        std::string m = g_err;
+        release(b);
+        return fail(rc, "%s", m.c_str());
+    }
+    if (e2 != hipSuccess) {
+        release(b);
+        return hip_fail(e2, "hipStreamEndCapture");
+    }
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        release(b);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    *plan = b;
+    return CHYM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int chym_version(void) { return CHYM_VERSION; }
@@ -835,119 +975,18 @@ int chym_batch_workspace_size(const chym_task *tasks, int32_t n_tasks, size_t *b
 
 int chym_batch_create(const chym_task *tasks, int32_t n_tasks, void *workspace, size_t ws_bytes,
                       chym_batch **plan) {
-    if (!plan) return fail(CHYM_EINVAL, "plan is NULL");
-    *plan = nullptr;
-    BatchLayout L;
-    int rc = plan_layout(tasks, n_tasks, &L);
+    return batch_build(tasks, n_tasks, workspace, ws_bytes, true, nullptr, plan);
+}
+
+int chym_solve_batched(const chym_task *tasks, int32_t n_tasks, void *workspace, size_t ws_bytes,
+                       chym_stream_t stream) {
+    chym_batch *b = nullptr;
+    int rc = batch_build(tasks, n_tasks, workspace, ws_bytes, false, (hipStream_t)stream, &b);
     if (rc) return rc;
-    if (!workspace) return fail(CHYM_EINVAL, "workspace is NULL");
-    if ((uintptr_t)workspace % kAlign) return fail(CHYM_EINVAL, "workspace must be %zu-byte aligned", kAlign);
-    if (ws_bytes < L.total) return fail(CHYM_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
-    rc = check_device();
-    if (rc) return rc;
-    chym_batch *b = new (std::nothrow) chym_batch;
-    if (!b) return fail(CHYM_ENOMEM, "out of host memory");
-    b->tasks.assign(tasks, tasks + n_tasks);
-    b->layout = L;
-    b->ws = static_cast<char *>(workspace);
-    hipError_t e = hipGetDevice(&b->device);
-    // occupancy-sized persistent grids
-    int cus = 0;
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
-    b->cus = cus;
-    for (Group &g : b->layout.groups) {
-        int per_cu = 0;
-        if (e == hipSuccess) {
-            if (g.v.ell) e = chym::ell_persistent_occupancy(g.d, g.lds, &per_cu);
-            else if (g.v.slab) e = chym::slab_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, g.lds, &per_cu);
-            else e = chym::persistent_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, g.kind, g.waves, &per_cu);
-        }
-        const int need = (g.v.ell || g.v.slab || g.kind != chym::kKernelRegJ) ? g.n_items
-                                                                              : (g.n_items + g.waves - 1) / g.waves;
-        g.blocks = std::max(1, std::min(need, std::max(1, per_cu) * cus));
-    }
-    // task table and work list
-    std::vector<chym::IntegArgs> targs(n_tasks);
-    for (int t = 0; t < n_tasks; ++t) targs[t] = make_args(&tasks[t].prob, &tasks[t].run);
-    if (e == hipSuccess)
-        e = hipMemcpy(b->ws + L.off_tasks, targs.data(), sizeof(chym::IntegArgs) * n_tasks, hipMemcpyHostToDevice);
-    if (e == hipSuccess && !L.items.empty())
-        e = hipMemcpy(b->ws + L.off_items, L.items.data(), sizeof(int2) * L.items.size(), hipMemcpyHostToDevice);
-    std::vector<chym::ScoreArgs> sargs(n_tasks);
-    std::vector<int64_t> first(n_tasks + 1, 0);
-    for (int t = 0; t < n_tasks; ++t) {
-        const chym_task &tk = tasks[t];
-        chym::ScoreArgs &sa = sargs[t];
-        sa.x = tk.run.x;
-        sa.j = tk.prob.j;
-        sa.spins = tk.out.spins;
-        sa.e_i32 = tk.out.e_ising;
-        sa.e_f64 = tk.out.e_ising_f64;
-        sa.e_hs = tk.out.e_hs;
-        sa.extra = tk.out.extra_frac;
-        sa.diverged = tk.out.diverged;
-        sa.n = tk.prob.n;
-        sa.d = tk.prob.d;
-        sa.r = tk.run.r;
-        sa.j_dtype = tk.prob.j_dtype;
-        first[t + 1] = first[t] + tk.run.r;
-    }
-    if (e == hipSuccess)
-        e = hipMemcpy(b->ws + L.off_score, sargs.data(), sizeof(chym::ScoreArgs) * n_tasks, hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(b->ws + L.off_first, first.data(), sizeof(int64_t) * (n_tasks + 1), hipMemcpyHostToDevice);
-    std::vector<const void *> jfp(n_tasks, nullptr);
-    for (int t = 0; t < n_tasks; ++t)
-        if (L.jf_off[t]) jfp[t] = b->ws + L.jf_off[t];
-    if (e == hipSuccess)
-        e = hipMemcpy(b->ws + L.off_jfp, jfp.data(), sizeof(void *) * n_tasks, hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(b->ws + L.off_ncp, L.ncp.data(), sizeof(int) * n_tasks, hipMemcpyHostToDevice);
-    if (e == hipSuccess && !L.stage_list.empty())
-        e = hipMemcpy(b->ws + L.off_list, L.stage_list.data(), sizeof(int) * L.stage_list.size(),
-                      hipMemcpyHostToDevice);
-    // record the launch sequence as a graph with one branch per variant group
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
-    const size_t ng = b->layout.groups.size();
-    for (size_t i = 0; e == hipSuccess && ng > 1 && i < ng; ++i) {
-        hipStream_t s;
-        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-        if (e == hipSuccess) b->side.push_back(s);
-    }
-    for (size_t i = 0; e == hipSuccess && ng > 1 && i < ng + 1; ++i) {
-        hipEvent_t ev;
-        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-        if (e == hipSuccess) b->events.push_back(ev);
-    }
-    if (e != hipSuccess) {
-        release(b);
-        return hip_fail(e, "batch setup");
-    }
-    e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) {
-        release(b);
-        return hip_fail(e, "hipStreamBeginCapture");
-    }
-    rc = issue_batch(b, b->cap, &b->side, &b->events);
-    hipGraph_t graph = nullptr;
-    hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
-    b->graph = graph;
-    if (rc) {
-        std::string m = g_err;
-        release(b);
-        return fail(rc, "%s", m.c_str());
-    }
-    if (e2 != hipSuccess) {
-        release(b);
-        return hip_fail(e2, "hipStreamEndCapture");
-    }
-    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        release(b);
-        return hip_fail(e, "hipGraphInstantiate");
-    }
-    *plan = b;
-    return CHYM_OK;
+    rc = issue_batch(b, (hipStream_t)stream, nullptr, nullptr);
+    // the plan is host data only; the queued kernels hold their arguments
+    release(b);
+    return rc;
 }
 
 int chym_batch_launch(const chym_batch *plan, chym_stream_t stream) {
