@@ -32,12 +32,18 @@ sys.path.insert(0, ROOT)
 METRIC = "spin-comp updates/s; TTS99 to Ising GS: plain FP32 vs BF16+learned stop"
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak (TFLOP/s)
 PEAK_FP32_MATRIX_TFLOPS = 157.3
+# float32 vector peak without packed float32 instructions (the library is
+# built without them): 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz.
+PEAK_FP32_VECTOR_UNPACKED_TFLOPS = 78.6
 
 
 # HBM bytes per launch of the dominant kernel on the default workload, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by the same counters on the
 # bench's own 4 GB state copy (profiles/integrate_persistent_sk100_d23_f32.md);
 # keyed by kernel and workload, valid for the kernels as they are now.
+TRAFFIC_SOURCE = ("profiles/integrate_persistent_sk100_d23_f32.md: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE "
+                  "of this kernel on this workload, scaled by the same counters on a copy of known size; "
+                  "not measured in this run")
 TRAFFIC = {("k_integrate_persistent<7, 3, 3, 1, false>", 100, 1000, 2000): 4.921e9,
            ("k_integrate_persistent_lds<7, 3, 3, 1, 2>", 100, 1000, 2000): 1.031e10}
 
@@ -72,6 +78,11 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1, help="0 disables the oracle timing leg")
     ap.add_argument("--cpu-replicas", type=int, default=2000)
     ap.add_argument("--tts", type=int, default=1, help="0 skips the time-to-99%%-ground-state comparison")
+    ap.add_argument("--success", type=int, default=1,
+                    help="0 skips the success statistics of the default workload (untimed: a batched search for "
+                         "each instance's putative ground state, then P_Ising per pump, E - E_GS and TTS99)")
+    ap.add_argument("--success-out", type=str, default="",
+                    help="write the per-instance success tables of the default workload to this .npz file")
     ap.add_argument("--workload", type=str, default="sk100",
                     choices=["sk100", "precision", "batched", "map", "sparse", "stats", "xy"],
                     help="sk100: the default throughput workload; precision: N=1000, D=4, 4096 replicas, "
@@ -147,9 +158,57 @@ def cpu_baseline(args, synth, wl):
         oracle.ode_run(J, wl["pumps"][:rs], x0[:, :, :d], float(wl["eps"][0]), 1.0, 2e-4, args.dt, steps, al)
         ups += n * rs * d * steps
     sec = time.perf_counter() - t0
-    return {"value": ups / sec, "unit": "spin-component updates/s", "cores": oracle.max_threads(), "kind": "oracle",
+    return {"value": ups / sec, "unit": "spin-component updates/s", "cores": oracle.max_threads(),
+            "cpu_model": host_cpu_model(), "kind": "oracle",
             "sample": f"instance 0, D in {wl['dims']}, replicas 0..{rs - 1} of {wl['R']}, {steps} steps, "
                       f"{ups:.3e} updates in {sec:.2f} s"}
+
+
+def success_leg(args, wl, kern_ms):
+    """Success statistics of the default workload's last step (untimed):
+    the putative ground state of every instance is the best energy of its
+    4000 benchmarked runs and of 2000 longer annealed runs (BF16 form,
+    20 000 steps, pumps 1..2, one batched launch); then, per D, P_Ising per
+    pump, E - E_GS per instance and the best-pump TTS99 at the measured GPU
+    time per run (stats.success_report)."""
+    import torch
+
+    from paper_2308_02329_amd import stats
+
+    t0 = time.perf_counter()
+    n, R, inst = args.n, wl["R"], args.instances
+    energies = {d: [None] * inst for d in wl["dims"]}
+    for i, d, o in wl["outs"]:
+        energies[d][i] = o["e_ising"].cpu().numpy()
+    search = stats.search_ground([wl["Js"][i] for i in range(inst)], n_rep=2000, steps=20000, seed=2308023292)
+    egs = [min([search[i]] + [int(energies[d][i].min()) for d in wl["dims"]]) for i in range(inst)]
+    torch.cuda.synchronize()
+    out = {"egs_source": "best of the benchmarked runs and 2000 BF16 runs x 20000 steps per instance",
+           "egs_from_search": int(sum(search[i] == egs[i] for i in range(inst))),
+           "pumps": np.linspace(0.5, 2.0, args.pumps).tolist()}
+    for d in wl["dims"]:
+        t_run = kern_ms[d] / args.steps / (inst * R)
+        out[str(d)] = stats.success_report(energies[d], egs, args.pumps, args.ics, n, t_run_ms=t_run)
+    if args.success_out:
+        tab = {f"P_d{d}": np.array([stats.figures(e, g, args.pumps, args.ics, n)["P"]
+                                    for e, g in zip(energies[d], egs)]) for d in wl["dims"]}
+        tab.update({f"dE_d{d}": np.array([(e.astype(np.int64) - g).mean() for e, g in zip(energies[d], egs)])
+                    for d in wl["dims"]})
+        np.savez_compressed(args.success_out, egs=np.array(egs), **tab)
+    out["seconds"] = time.perf_counter() - t0
+    return out
+
+
+def host_cpu_model() -> str:
+    """Model name of the host CPU (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def tts_leg():
@@ -444,8 +503,9 @@ def run_sparse(args, torch, api, synth):
             "config": {"workload": f"sparse rows: 3-regular +-1 N in (200, 400, 800) and 20% Erdos-Renyi +-1 N=100, "
                                    f"D={d}, {R} replicas, {steps} Euler steps with the anneal, float32 gather",
                        "d": d, "replicas": R, "euler_steps": steps},
-            "roofline": {"bound": "alu", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
-                         "frac": achieved / 157.3, "traffic": None,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_UNPACKED_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_UNPACKED_TFLOPS, "traffic": None,
+                         "peak_note": "float32 vector ALU without packed float32 (not used by the library)",
                          "kernel": "k_integrate_ell<3> (3-regular N=800)", "kernel_ms": r0["ms"]["sparse_f32"]},
             "graphs": rows}
 
@@ -642,6 +702,7 @@ def main():
     kname = kernel_name((n + 15) // 16, dk, args.precision, plan)
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_BF16_TFLOPS, "traffic": TRAFFIC.get((kname, args.n, args.instances, R)),
+            "traffic_source": TRAFFIC_SOURCE if (kname, args.n, args.instances, R) in TRAFFIC else None,
             "kernel": kname, "kernel_ms": kern_ms[dk] / args.steps}
 
     # run statistics of the last step (not timed)
@@ -662,6 +723,8 @@ def main():
            "diverged_runs": diverged,
            "plans": {str(d): api.chym_plan_get(args.n, d, args.precision, torch.int8) for d in dims},
            "autotune": plans}
+    if args.success:
+        res["success"] = success_leg(args, wl, kern_ms)
     if args.cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args, synth, wl)
     if args.tts:

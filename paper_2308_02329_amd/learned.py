@@ -40,7 +40,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from . import api, synth
+from . import api, stats, synth
 
 N_CKPT = 8
 N_FEAT = L.CHYM_FEATURES
@@ -217,13 +217,7 @@ def generate(n_inst, n=200, d=3, n_ic=1000, n_pumps=20, steps=5000, dt=0.01, pre
 
 
 # -------------------------------------------------------------- accounting
-def tts99(cost, p):
-    """Time to 99 % success from cost per attempt and success per attempt."""
-    if p <= 0.0:
-        return math.inf
-    if p >= 0.99:
-        return cost
-    return cost * math.log(0.01) / math.log1p(-p)
+tts99 = stats.tts99
 
 
 def auc(scores, labels):

@@ -75,6 +75,53 @@ def figures(energies, egs, n_pumps, n_rep, n):
     }
 
 
+def tts99(cost, p):
+    """Time to 99 % success from the cost per attempt and the success
+    probability per attempt: cost ln(0.01) / ln(1 - p); one attempt when
+    p >= 0.99, infinite when p = 0."""
+    if p <= 0.0:
+        return math.inf
+    if p >= 0.99:
+        return cost
+    return cost * math.log(0.01) / math.log1p(-p)
+
+
+def _quantiles(v):
+    """Median and quartiles (linear interpolation) of values that may be
+    infinite; a quantile that involves an infinite value is None (JSON has
+    no infinity)."""
+    v = np.asarray(v, dtype=np.float64)
+    if not v.size:
+        return {"q25": None, "median": None, "q75": None}
+    big = 1e300
+    q = np.percentile(np.where(np.isfinite(v), v, big), [25, 50, 75])
+    cvt = lambda z: None if z >= 1e299 else float(z)  # noqa: E731
+    return {"q25": cvt(q[0]), "median": cvt(q[1]), "q75": cvt(q[2])}
+
+
+def success_report(energies, egs, n_pumps, n_rep, n, t_run_ms=None):
+    """Success statistics of a workload of many instances (statistics
+    paragraph: P_Ising over the pump scan and the deviation of the final
+    energy, here per instance): energies[i] holds the final Ising energies
+    of instance i's runs, pump-major (n_pumps x n_rep), egs[i] its
+    ground-state energy.  Returns the success probability per pump averaged
+    over the instances, and over the instances the quartiles of the
+    best-pump success P_max, of the mean deviation E - E_GS (raw and per
+    spin), the fraction of instances with a success, and, with the GPU time
+    per run t_run_ms, the quartiles of the best-pump TTS99 (infinite for an
+    unsolved instance, reported as None)."""
+    f = [figures(e, g, n_pumps, n_rep, n) for e, g in zip(energies, egs)]
+    P = np.array([x["P"] for x in f], dtype=np.float64)
+    pmax = P.max(axis=1)
+    de = np.array([x["dE"] for x in f], dtype=np.float64)
+    out = {"instances": len(f), "P_per_pump_mean": P.mean(axis=0).tolist(), "P_max": _quantiles(pmax),
+           "solved_fraction": float((pmax > 0).mean()), "dE": _quantiles(de), "dE_per_n": _quantiles(de / n)}
+    if t_run_ms is not None:
+        out["t_run_ms"] = float(t_run_ms)
+        out["tts99_ms"] = _quantiles([tts99(t_run_ms, p) for p in pmax])
+    return out
+
+
 def histogram(energies, egs):
     """H_E as {E - E_GS: fraction of the runs}."""
     d, c = np.unique(np.asarray(energies, dtype=np.int64) - egs, return_counts=True)

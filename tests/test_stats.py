@@ -89,3 +89,33 @@ def test_map_parameters_sit_at_the_thresholds():
     # the CIM: no nonlocal loss, no anneal
     _, _, _, a1, b1 = stats.machine_inputs(J, 1, stats.pumps(1), 2, 50, 1, 0)
     assert b1 == 0.0 and np.all(a1 == 1.0)
+
+
+def test_success_report_hand_worked():
+    """Two instances, 2 pumps x 4 runs each, E_GS -10 and -6."""
+    e0 = [-10, -10, -6, -2, -6, -6, -6, -6]      # P = (0.5, 0), deviations 0 0 4 8 4 4 4 4
+    e1 = [-2, -2, -2, -2, -6, -2, -2, -2]       # P = (0, 0.25), deviations 4 4 4 4 0 4 4 4
+    rep = stats.success_report([e0, e1], [-10, -6], 2, 4, n=4, t_run_ms=2.0)
+    assert rep["instances"] == 2
+    assert rep["P_per_pump_mean"] == [0.25, 0.125]
+    assert rep["solved_fraction"] == 1.0
+    # quartiles of (0.25, 0.5) by linear interpolation
+    assert rep["P_max"] == {"q25": 0.3125, "median": 0.375, "q75": 0.4375}
+    assert rep["dE"]["q25"] == pytest.approx(28 / 8) and rep["dE"]["q75"] == pytest.approx(28 / 8)
+    assert rep["dE_per_n"]["median"] == pytest.approx(28 / 8 / 4)
+    # best-pump TTS99: 2 ms per run, p = 0.5 and 0.25
+    t_a, t_b = 2.0 * math.log(0.01) / math.log(0.75), 2.0 * math.log(0.01) / math.log(0.5)
+    assert rep["tts99_ms"]["median"] == pytest.approx((t_a + t_b) / 2)
+    assert rep["tts99_ms"]["q25"] == pytest.approx(t_b + 0.25 * (t_a - t_b))
+    # an unsolved instance has an infinite TTS99, reported as None; it does not count as solved
+    rep2 = stats.success_report([e0, e1, [-2] * 8, [-2] * 8], [-10, -6, -6, -6], 2, 4, n=4, t_run_ms=2.0)
+    assert rep2["solved_fraction"] == 0.5
+    assert rep2["tts99_ms"]["median"] is None and rep2["tts99_ms"]["q75"] is None
+    assert rep2["tts99_ms"]["q25"] == pytest.approx(t_b + 0.75 * (t_a - t_b))
+
+
+def test_tts99_is_the_attempt_count_closed_form():
+    assert stats.tts99(2.0, 0.0) == math.inf
+    assert stats.tts99(2.0, 0.995) == 2.0
+    for k in (1.5, 10.0, 1000.0):
+        assert stats.tts99(3.0, 1.0 - 0.01 ** (1.0 / k)) == pytest.approx(3.0 * k, rel=1e-12)
