@@ -161,6 +161,19 @@ int chym_integrate_workspace_size(const chym_problem *prob, const chym_run *run,
 int chym_integrate_ws(const chym_problem *prob, const chym_run *run, void *workspace, size_t ws_bytes,
                       chym_stream_t stream);
 
+/* chym_integrate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * every size chym_integrate_ws takes, with no workspace argument.  The
+ * streamed-J integrator's staged couplings go into a static device array of
+ * the library (6.06 MiB, enough for n = 1024 with couplings in three bf16
+ * terms; one copy per GPU, held until the process ends); sizes whose staging
+ * would not fit are refused with CHYM_EUNSUPPORTED.  The call itself
+ * allocates nothing.  All calls on one GPU share its array: calls that
+ * overlap on one GPU (concurrent streams, or host threads) race and must be
+ * serialized by the caller; consecutive calls on one stream are ordered and
+ * safe.  Results are bit-identical to chym_integrate_ws. */
+int chym_integrate_noalloc(const chym_problem *prob, const chym_run *run, chym_stream_t stream);
+
 /* The round-trip map of Eq. (2) itself, one step per round trip (the
  * paper's own simulation model; chym_integrate integrates its continuous
  * limit).  For every parametric oscillator j = (p, mu):

@@ -34,6 +34,7 @@ EXPORTS = (
     "chym_plan_load", "chym_integrate_workspace_size", "chym_integrate_ws", "chym_solve_ws",
     "chym_sign_words", "chym_features", "chym_mlp_scratch_floats", "chym_mlp_forward", "chym_mlp_backward",
     "chym_mlp_adam", "chym_to_bf16", "chym_map_integrate", "chym_map_batch_workspace_size", "chym_map_batch",
+    "chym_integrate_noalloc",
 )
 
 CHYM_FEATURES = 32
@@ -115,6 +116,8 @@ def load():
     lib.chym_integrate_workspace_size.restype = ctypes.c_int
     lib.chym_integrate_ws.argtypes = [P(ChymProblem), P(ChymRun), _vp, ctypes.c_size_t, _vp]
     lib.chym_integrate_ws.restype = ctypes.c_int
+    lib.chym_integrate_noalloc.argtypes = [P(ChymProblem), P(ChymRun), _vp]
+    lib.chym_integrate_noalloc.restype = ctypes.c_int
     _load_batch(lib)
     _load_plan(lib)
     _load_learned(lib)

@@ -178,6 +178,18 @@ def chym_integrate(J, pump, x, alpha, *, eps, btil, eta, dt, steps, start_step=0
     return x
 
 
+def chym_integrate_noalloc(J, pump, x, alpha, *, eps, btil, eta, dt, steps, start_step=0,
+                           precision=CHYM_PREC_F32, stream=None):
+    """chym_integrate for every size, with the streamed-J staging in the
+    library's static device scratch (no workspace, no allocation)."""
+    n, r, d = x.shape
+    prob = make_problem(J, d, eps, btil, eta)
+    run = make_run(n, d, pump, x, alpha, dt, steps, start_step, precision)
+    L.check(L.load().chym_integrate_noalloc(ctypes.byref(prob), ctypes.byref(run), _stream(stream)),
+            "chym_integrate_noalloc")
+    return x
+
+
 def chym_map_integrate(J, h, A, alpha, *, b, loss, kl, beta_b2, jmag, steps, start_step=0,
                        precision=CHYM_PREC_F32, stream=None):
     """Advance the amplitudes A [n, r, d] (float32, in place) by ``steps``

@@ -189,6 +189,44 @@ int integrate_impl(const chym_problem *prob, const chym_run *run, hipStream_t st
     return CHYM_OK;
 }
 
+// ------------------------------------------------ static scratch
+// For callers that cannot allocate: the staged couplings of the streamed-J
+// integrator in a file-scope device array instead of a caller workspace.
+// Its size is that of the largest staging (n = 1024, i.e. 64 row tiles,
+// couplings split into three bf16 terms); each GPU the library runs on holds
+// its own copy until the process ends.  The staging kernels rewrite every
+// byte the integrator reads, so nothing in it has to start at zero.
+constexpr size_t kStaticScratchBytes = (size_t)97 << 16;  // 6.06 MiB
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64];  // device address of `scratch` per device index
+
+// The device address of the current device's copy of `scratch`, looked up
+// once per device with that device current.  The array's name in host code
+// is not a device address; only this pointer is passed to kernels.
+int static_scratch(void **ptr) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(CHYM_ENODEV, "no HIP device: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= 64) return fail(CHYM_ENODEV, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(CHYM_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return CHYM_OK;
+}
+
 int validate_sizes(int32_t n, int32_t d, int32_t r) {
     if (n < 1) return fail(CHYM_EINVAL, "n = %d must be >= 1", n);
     if (d < 1 || d > 4) return fail(CHYM_EINVAL, "d = %d must be in 1..4", d);
@@ -953,6 +991,24 @@ int chym_integrate_workspace_size(const chym_problem *prob, const chym_run *run,
     if (rc) return rc;
     *bytes = slab_ws_bytes(variant_of(prob, run));
     return CHYM_OK;
+}
+
+int chym_integrate_noalloc(const chym_problem *prob, const chym_run *run, chym_stream_t stream) {
+    int rc = validate_problem(prob);
+    if (rc) return rc;
+    rc = validate_run(run);
+    if (rc) return rc;
+    rc = check_variant(prob, run);
+    if (rc) return rc;
+    const size_t need = slab_ws_bytes(variant_of(prob, run));
+    if (need == 0) return integrate_impl(prob, run, (hipStream_t)stream);  // no staging: nothing to hold
+    if (need > kStaticScratchBytes)
+        return fail(CHYM_EUNSUPPORTED, "n = %d with d = %d needs %zu bytes of staging; the static scratch holds %zu",
+                    prob->n, prob->d, need, kStaticScratchBytes);
+    void *ws = nullptr;
+    rc = static_scratch(&ws);
+    if (rc) return rc;
+    return integrate_impl(prob, run, (hipStream_t)stream, ws, kStaticScratchBytes);
 }
 
 int chym_integrate_ws(const chym_problem *prob, const chym_run *run, void *workspace, size_t ws_bytes,
