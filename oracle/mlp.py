@@ -7,9 +7,14 @@ W2 [128][128], b2 [128], w3 [128], b3.  Written from the definitions
 (matrix products, chain rule); pinned by finite differences and closed forms
 in tests/test_oracle_mlp.py.
 
-Features (per replica and checkpoint): E_hs / n (Eq. (3)), E / n of the sign
-readout, mean hyperspin norm, fraction of flipped signs since the previous
-checkpoint -- composed from the oracle's pinned energy and readout routines.
+Features (per replica and checkpoint), about the first component x_{p,1}
+(the one the anneal keeps and the readout reads): its Rayleigh quotient per
+spin -(x_1^T J x_1) / (n x_1^T x_1), the Ising energy per spin of the sign
+readout, its share of the squared norm, and the fraction of signs flipped
+since the previous checkpoint -- written from those definitions with the
+oracle's pinned energy and readout routines.  Standardization within each
+pump's batch of runs and the top-k selection of the restart policy are
+written out from their definitions too.
 """
 from __future__ import annotations
 
@@ -91,10 +96,43 @@ def bf16_round(a):
 def features(J, x, prev_sigma):
     """The four checkpoint features of every replica of x [n, r, d] and the
     new signs; prev_sigma [r][n] are the signs of the previous checkpoint."""
-    n = x.shape[0]
+    x = np.asarray(x, dtype=np.float64)
+    J = np.asarray(J, dtype=np.float64)
+    n, r, _ = x.shape
     sig = oracle.readout(x)
-    ehs = oracle.hs_energy(J, x) / n
+    x1 = x[:, :, 0]
+    s1 = (x1 * x1).sum(axis=0)
+    sall = (x * x).sum(axis=(0, 2))
+    quad = np.array([x1[:, i] @ J @ x1[:, i] for i in range(r)])
+    rq = np.where(s1 > 0, -quad / (n * np.where(s1 > 0, s1, 1.0)), 0.0)
     eis = oracle.ising_energy(J, sig) / n
-    nrm = np.sqrt((np.asarray(x, dtype=np.float64) ** 2).sum(axis=2)).mean(axis=0)
+    share = np.where(sall > 0, s1 / np.where(sall > 0, sall, 1.0), 0.0)
     flips = (sig != prev_sigma).mean(axis=1)
-    return np.stack([ehs, eis, nrm, flips], axis=1), sig
+    return np.stack([rq, eis, share, flips], axis=1), sig
+
+
+def standardize(F, group):
+    """Each column of F [groups * group][k] as (f - mean) / sd within each
+    group of `group` consecutive rows (population sd; 0 where sd = 0)."""
+    F = np.asarray(F, dtype=np.float64)
+    out = np.empty_like(F)
+    for g in range(F.shape[0] // group):
+        blk = F[g * group:(g + 1) * group]
+        mu = blk.mean(axis=0)
+        sd = np.sqrt(((blk - mu) ** 2).mean(axis=0))
+        out[g * group:(g + 1) * group] = np.where(sd > 0, (blk - mu) / np.where(sd > 0, sd, 1.0), 0.0)
+    return out
+
+
+def select_top(score, group, keep):
+    """Global indices [groups][keep] of the keep highest scores of each group
+    of consecutive scores, ascending; equal scores: lower index first; NaN
+    lowest."""
+    score = np.asarray(score, dtype=np.float64)
+    out = []
+    for g in range(score.shape[0] // group):
+        s = score[g * group:(g + 1) * group]
+        key = np.where(np.isnan(s), -np.inf, s)
+        order = sorted(range(group), key=lambda i: (-key[i], i))  # highest first, then lowest index
+        out.append(sorted(g * group + i for i in order[:keep]))
+    return np.array(out, dtype=np.int64)

@@ -75,7 +75,57 @@ def test_features_reference_small_case():
     x[:, 1, 0] = [0.5, 0.5]
     prev = np.array([[1, 1], [1, -1]], dtype=np.int8)
     f, sig = mlp.features(J, x, prev)
-    # replica 0: u0 = (0.6, 0.8), u1 = (-1, 0): E_hs = -2 (-0.6) = 1.2; signs (+, -): E = 2
-    np.testing.assert_allclose(f[0], [0.6, 1.0, 3.0, 0.5])
-    np.testing.assert_allclose(f[1], [-1.0, -1.0, 0.5, 0.5])
+    # replica 0: x_1 = (3, -1): x_1^T J x_1 = 2 * 3 * (-1) = -6, |x_1|^2 = 10, so the Rayleigh
+    # quotient per spin is 6 / 20; signs (+, -): E = 2, E / n = 1; share 10 / (9 + 16 + 1); one flip of two
+    np.testing.assert_allclose(f[0], [0.3, 1.0, 10.0 / 26.0, 0.5])
+    # replica 1: x_1 = (0.5, 0.5): quadratic form 0.5, |x_1|^2 0.5 -> -0.5; signs (+, +): E = -2; share 1
+    np.testing.assert_allclose(f[1], [-0.5, -1.0, 1.0, 0.5])
     np.testing.assert_array_equal(sig, [[1, -1], [1, 1]])
+    # a zero state: quotient and share are 0 by definition, every sign reads +1
+    z, sz = mlp.features(J, np.zeros((2, 1, 2)), np.array([[1, 1]], dtype=np.int8))
+    np.testing.assert_array_equal(z[0], [0.0, -1.0, 0.0, 0.0])
+
+
+def test_features_rayleigh_quotient_bounds():
+    """The quotient lies in [-lambda_max, -lambda_min] / n, with the ends at
+    the eigenvectors (placed in the first component)."""
+    J = np.array([[0, 1, -1], [1, 0, 1], [-1, 1, 0]], dtype=np.float64)
+    w, V = np.linalg.eigh(J)
+    g = np.random.default_rng(5)
+    x = g.standard_normal((3, 50, 3))
+    x[:, 0, 0], x[:, 1, 0] = V[:, -1], V[:, 0]
+    f, _ = mlp.features(J, x, np.ones((50, 3), dtype=np.int8))
+    assert np.all(f[:, 0] >= -w[-1] / 3 - 1e-12) and np.all(f[:, 0] <= -w[0] / 3 + 1e-12)
+    assert f[0, 0] == pytest.approx(-w[-1] / 3) and f[1, 0] == pytest.approx(-w[0] / 3)
+    assert np.all((f[:, 2] >= 0) & (f[:, 2] <= 1))
+
+
+def test_standardize_reference():
+    g = np.random.default_rng(6)
+    F = g.standard_normal((12, 5)) * 3 + 7
+    F[4:8, 2] = 1.5  # a constant column in the second group standardizes to 0
+    S = mlp.standardize(F, 4)
+    for k in range(3):
+        blk = S[4 * k:4 * k + 4]
+        np.testing.assert_allclose(blk.mean(axis=0), 0.0, atol=1e-12)
+        sd = blk.std(axis=0)
+        assert np.all((np.abs(sd - 1) < 1e-12) | (sd == 0))
+    assert not S[4:8, 2].any()
+    # invariant under a shift and a positive scale of the group's values
+    np.testing.assert_allclose(mlp.standardize(F * 2.5 - 4, 4), S, atol=1e-12)
+
+
+def test_select_top_reference_against_brute_force():
+    g = np.random.default_rng(7)
+    s = np.round(g.standard_normal(40), 1)  # many ties
+    s[3] = np.nan
+    idx = mlp.select_top(s, 10, 4)
+    for grp in range(4):
+        blk = s[grp * 10:(grp + 1) * 10]
+        key = np.where(np.isnan(blk), -np.inf, blk)
+        chosen = set(idx[grp] - grp * 10)
+        assert len(chosen) == 4 and list(idx[grp]) == sorted(idx[grp])
+        # every chosen score beats every other, and among equal scores the lower index is chosen
+        for i in chosen:
+            for j in set(range(10)) - chosen:
+                assert key[i] > key[j] or (key[i] == key[j] and i < j)
