@@ -212,13 +212,17 @@ def host_cpu_model() -> str:
 
 
 def tts_leg():
-    """Time to 99 % ground-state success, plain FP32 vs BF16 + learned
-    restart, on held-out N=100 SK instances (untimed by the bench clock)."""
+    """Time to 99 % ground-state success of the learned-restart workload
+    (SK N = 200, D = 3): plain FP32, BF16 and BF16 with the learned restart,
+    each executed and timed end to end on held-out instances (untimed by the
+    bench clock)."""
     from paper_2308_02329_amd import learned
 
     rep = learned.experiment(log=None)
-    keep = ("workload", "tts99_median_ms", "instances_solved", "auc_heldout", "keep_fraction",
-            "trajectories_train", "positives_heldout_bf16", "positives_heldout_f32", "updates_per_s", "seconds")
+    keep = ("workload", "tts99_median_ms", "instances_solved", "same_instances_solved", "learned_over_bf16_geomean",
+            "learned_over_bf16_ci95", "learned_over_f32_geomean", "learned_over_f32_ci95", "keep_fraction",
+            "chosen_epoch", "auc_within_batch_val", "auc_within_batch_heldout", "trajectories_train",
+            "positives_train", "ms_per_attempt", "kept_runs_match_plain", "seconds")
     def finite(v):
         if isinstance(v, dict):
             return {k: finite(x) for k, x in v.items()}

@@ -318,11 +318,20 @@ int chym_solve_batched(const chym_task *tasks, int32_t n_tasks, void *workspace,
  *
  * Features: CHYM_FEATURES = 8 checkpoints x 4 values per replica, stored
  * [r][CHYM_FEATURES] float32; checkpoint k fills columns 4k .. 4k+3 with
- *   E_hs / n      hyperspin energy per spin (Eq. (3), unit vectors)
+ *   R1            -(x_1^T J x_1) / (n x_1^T x_1): the Rayleigh quotient per
+ *                 spin of the first components x_{p,1} (0 if they are all 0)
  *   E / n         Ising energy per spin of the current sign readout
- *   mean_p |x_p|  mean hyperspin norm
+ *   share1        sum_p x_{p,1}^2 / sum_{p,mu} x_{p,mu}^2, the first
+ *                 component's share of the squared norm (0 for a zero state)
  *   flips / n     fraction of spins whose sign changed since the previous
  *                 checkpoint (sign words in prev_words, updated in place)
+ * (float32 arithmetic).  All four concern the first component, the one the
+ * anneal keeps and the readout reads: runs of one problem and pump reach the
+ * same hyperspin configuration up to a rotation, and its orientation, not
+ * rotation-invariant quantities such as E_hs, tells them apart.  Before the
+ * network the features are standardized within each pump's batch of runs
+ * (chym_feature_standardize), since the restart policy ranks runs within
+ * such a batch.
  * Network: CHYM_FEATURES -> 128 -> 128 -> 1, ReLU, sigmoid output, binary
  * cross-entropy; parameters in one block of CHYM_MLP_PARAMS values in the
  * order W1 [128][32], b1 [128], W2 [128][128], b2 [128], w3 [128], b3, held
@@ -333,12 +342,33 @@ int chym_solve_batched(const chym_task *tasks, int32_t n_tasks, void *workspace,
 #define CHYM_MLP_PARAMS 20865
 
 /* Sign words [r][ceil(n/64)] of x (bit set iff x_{p,1} >= 0): the reference
- * of the first checkpoint.  n * (d + 1) <= 8192. */
+ * of the first checkpoint. */
 int chym_sign_words(int32_t n, int32_t d, int32_t r, const float *x, uint64_t *words, chym_stream_t stream);
 
-/* Features of checkpoint `checkpoint` (0..7) of every replica of x. */
+/* Features of checkpoint `checkpoint` (0..7) of every replica of x; dense
+ * couplings, n <= 8192. */
 int chym_features(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dtype, const float *x,
                   uint64_t *prev_words, float *features, int32_t checkpoint, chym_stream_t stream);
+
+/* Standardizes features [groups * group][CHYM_FEATURES] within each group of
+ * `group` consecutive replicas (one pump's batch of runs): every column
+ * becomes (f - mean) / sd with the group's mean and population standard
+ * deviation (0 where sd = 0).  Deterministic; `out` may be `in`. */
+int chym_feature_standardize(int32_t groups, int32_t group, const float *in, float *out, chym_stream_t stream);
+
+/* For each group of `group` consecutive scores (one pump's batch of runs),
+ * the indices of its `keep` highest scores (equal scores: the lower index
+ * first; NaN ranks lowest), in ascending order, as global replica indices:
+ * idx [groups][keep] int32.  1 <= keep <= group. */
+int chym_select_top(int32_t groups, int32_t group, int32_t keep, const float *score, int32_t *idx,
+                    chym_stream_t stream);
+
+/* Copies the runs idx[0 .. m) of x_src [n][r_src][d] into x_dst [n][m][d]
+ * (run j of x_dst is run idx[j] of x_src) and, if pump_dst is not NULL,
+ * their pumps into pump_dst [m].  Every idx entry must lie in [0, r_src)
+ * (device data, not checked: chym_select_top writes such indices). */
+int chym_gather_replicas(int32_t n, int32_t d, int32_t r_src, const float *x_src, const float *pump_src, int32_t m,
+                         const int32_t *idx, float *x_dst, float *pump_dst, chym_stream_t stream);
 
 /* Float scratch the backward pass needs for a batch. */
 int chym_mlp_scratch_floats(int32_t batch, size_t *floats);
@@ -375,7 +405,10 @@ int chym_to_bf16(const float *src, uint16_t *dst, int32_t n, chym_stream_t strea
  *                     takes work items of 16 * waves replicas, leaving
  *                     registers for two wavefronts per SIMD;
  *   CHYM_KERNEL_LDSJ1 the same with one wavefront per SIMD (the whole
- *                     register file for each wave).
+ *                     register file for each wave);
+ *   CHYM_KERNEL_PIPE  J in LDS as for LDSJ1, with the step loop software-
+ *                     pipelined: the vector work of one step runs between
+ *                     the matrix-core products of the next.
  * The table is process-wide and starts empty (CHYM_KERNEL_REGJ, 4 waves per
  * block, for every variant).  Plans change speed only, never results.
  */
@@ -383,13 +416,18 @@ int chym_to_bf16(const float *src, uint16_t *dst, int32_t n, chym_stream_t strea
 #define CHYM_KERNEL_REGJ 1
 #define CHYM_KERNEL_LDSJ 2
 #define CHYM_KERNEL_LDSJ1 3
+#define CHYM_KERNEL_PIPE 4  /* J in LDS, one wavefront per SIMD that interleaves the update of the previous
+                               step and the operand split with the current step's products (two accumulator
+                               sets); built for d = 2, 3 and 2 to 7 row tiles with couplings in one bf16
+                               term (any storage in the bf16 form; int8, bf16 or FP8 in the float32 form) */
 
 typedef struct chym_plan_entry {
     int32_t n;         /* problem size the entry applies to (any n with the same 16-row tile count) */
     int32_t d;
     int32_t precision; /* CHYM_PREC_* */
     int32_t j_dtype;   /* CHYM_J_* */
-    int32_t kernel;    /* CHYM_KERNEL_REGJ, _LDSJ or _LDSJ1 (CHYM_KERNEL_AUTO: remove the entry) */
+    int32_t kernel;    /* CHYM_KERNEL_REGJ, _LDSJ, _LDSJ1 or _PIPE (CHYM_KERNEL_AUTO: remove the entry);
+                          a kind not built for the shape is refused with CHYM_EUNSUPPORTED */
     int32_t waves;     /* wavefronts per block, 1..4 */
     float ms;          /* autotune: measured time of the probe run of this entry (informational) */
     float reserved;    /* must be 0 */

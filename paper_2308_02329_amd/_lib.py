@@ -34,7 +34,7 @@ EXPORTS = (
     "chym_plan_load", "chym_integrate_workspace_size", "chym_integrate_ws", "chym_solve_ws",
     "chym_sign_words", "chym_features", "chym_mlp_scratch_floats", "chym_mlp_forward", "chym_mlp_backward",
     "chym_mlp_adam", "chym_to_bf16", "chym_map_integrate", "chym_map_batch_workspace_size", "chym_map_batch",
-    "chym_integrate_noalloc",
+    "chym_integrate_noalloc", "chym_feature_standardize", "chym_select_top", "chym_gather_replicas",
 )
 
 CHYM_FEATURES = 32
@@ -44,6 +44,7 @@ CHYM_KERNEL_AUTO = 0
 CHYM_KERNEL_REGJ = 1
 CHYM_KERNEL_LDSJ = 2
 CHYM_KERNEL_LDSJ1 = 3
+CHYM_KERNEL_PIPE = 4
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -183,6 +184,10 @@ def _load_learned(lib):
     f = ctypes.c_float
     lib.chym_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, _vp, f, f, f, f, _i32, _vp]
     lib.chym_to_bf16.argtypes = [_vp, _vp, _i32, _vp]
+    lib.chym_feature_standardize.argtypes = [_i32, _i32, _vp, _vp, _vp]
+    lib.chym_select_top.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp]
+    lib.chym_gather_replicas.argtypes = [_i32, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp]
     for name in ("chym_sign_words", "chym_features", "chym_mlp_scratch_floats", "chym_mlp_forward",
-                 "chym_mlp_backward", "chym_mlp_adam", "chym_to_bf16"):
+                 "chym_mlp_backward", "chym_mlp_adam", "chym_to_bf16", "chym_feature_standardize",
+                 "chym_select_top", "chym_gather_replicas"):
         getattr(lib, name).restype = ctypes.c_int

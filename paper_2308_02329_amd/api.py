@@ -12,7 +12,7 @@ import ctypes
 import torch
 
 from . import _lib as L
-from ._lib import (CHYM_J_BF16, CHYM_J_ELL, CHYM_J_F32, CHYM_J_FP8, CHYM_J_I8, CHYM_KERNEL_AUTO, CHYM_KERNEL_LDSJ, CHYM_KERNEL_LDSJ1, CHYM_KERNEL_REGJ,
+from ._lib import (CHYM_J_BF16, CHYM_J_ELL, CHYM_J_F32, CHYM_J_FP8, CHYM_J_I8, CHYM_KERNEL_AUTO, CHYM_KERNEL_LDSJ, CHYM_KERNEL_LDSJ1, CHYM_KERNEL_PIPE, CHYM_KERNEL_REGJ,
                    CHYM_PREC_BF16, CHYM_PREC_F32, ChymError, ChymOut, ChymPlanEntry, ChymProblem, ChymRun)
 
 __all__ = ["chym_sign_words", "chym_features", "chym_mlp_forward", "chym_mlp_backward", "chym_mlp_adam",
@@ -22,7 +22,7 @@ __all__ = ["chym_sign_words", "chym_features", "chym_mlp_forward", "chym_mlp_bac
            "chym_batch_workspace_size", "chym_batch_create", "chym_batch_launch", "chym_batch_launch_nograph",
            "chym_batch_destroy", "ChymBatch", "chym_plan_set", "chym_plan_get", "chym_plan_autotune",
            "chym_plan_save", "chym_plan_load", "chym_split3_bf16", "CHYM_KERNEL_REGJ", "CHYM_KERNEL_LDSJ",
-           "CHYM_KERNEL_AUTO", "CHYM_KERNEL_LDSJ1"]
+           "CHYM_KERNEL_AUTO", "CHYM_KERNEL_LDSJ1", "CHYM_KERNEL_PIPE"]
 
 
 def precision_code(p) -> int:
@@ -494,6 +494,57 @@ def chym_features(J, x, prev_words, features, checkpoint, stream=None):
     _need(features, "features", torch.float32, (r, L.CHYM_FEATURES))
     L.check(L.load().chym_features(n, d, r, _vp(J), _jdtype(J), _vp(x), _vp(prev_words), _vp(features),
                                    int(checkpoint), _stream(stream)), "chym_features")
+
+
+def chym_feature_standardize(features, group, out=None, stream=None):
+    """Standardize features [groups * group, 32] within each group of `group`
+    consecutive rows (one pump's batch of runs); out may be features."""
+    r = features.shape[0]
+    _need(features, "features", torch.float32, (r, L.CHYM_FEATURES))
+    if group < 1 or r % group:
+        raise ValueError(f"{r} feature rows are not a whole number of groups of {group}")
+    if out is None:
+        out = torch.empty_like(features)
+    _need(out, "out", torch.float32, (r, L.CHYM_FEATURES))
+    L.check(L.load().chym_feature_standardize(r // group, int(group), _vp(features), _vp(out), _stream(stream)),
+            "chym_feature_standardize")
+    return out
+
+
+def chym_select_top(score, group, keep, idx=None, stream=None):
+    """Global indices int32 [groups, keep] of the `keep` highest scores of each
+    group of `group` consecutive scores, ascending."""
+    r = score.shape[0]
+    _need(score, "score", torch.float32, (r,))
+    if group < 1 or r % group:
+        raise ValueError(f"{r} scores are not a whole number of groups of {group}")
+    if idx is None:
+        idx = torch.empty((r // group, int(keep)), dtype=torch.int32, device=score.device)
+    _need(idx, "idx", torch.int32, (r // group, int(keep)))
+    L.check(L.load().chym_select_top(r // group, int(group), int(keep), _vp(score), _vp(idx), _stream(stream)),
+            "chym_select_top")
+    return idx
+
+
+def chym_gather_replicas(x, idx, pump=None, x_out=None, pump_out=None, stream=None):
+    """Runs idx (int32 [m], entries in [0, r)) of x [n, r, d] into x_out
+    [n, m, d], and their pumps into pump_out [m] when pump is given."""
+    n, r, d = x.shape
+    _need(x, "x", torch.float32)
+    idx = idx.reshape(-1)
+    _need(idx, "idx", torch.int32)
+    m = idx.shape[0]
+    if x_out is None:
+        x_out = torch.empty((n, m, d), dtype=torch.float32, device=x.device)
+    _need(x_out, "x_out", torch.float32, (n, m, d))
+    if pump is not None:
+        _need(pump, "pump", torch.float32, (r,))
+        if pump_out is None:
+            pump_out = torch.empty(m, dtype=torch.float32, device=x.device)
+        _need(pump_out, "pump_out", torch.float32, (m,))
+    L.check(L.load().chym_gather_replicas(n, d, r, _vp(x), _vp(pump), m, _vp(idx), _vp(x_out), _vp(pump_out),
+                                          _stream(stream)), "chym_gather_replicas")
+    return x_out, pump_out
 
 
 def chym_mlp_forward(features, w_bf16, logit=None, h1=None, h2=None, stream=None):

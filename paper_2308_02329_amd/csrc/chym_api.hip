@@ -278,10 +278,23 @@ PlanValue plan_for(const VariantKey &k) {
 }
 
 int kind_of_code(int code) {
-    return code == CHYM_KERNEL_LDSJ ? chym::kKernelLdsJ : code == CHYM_KERNEL_LDSJ1 ? chym::kKernelLdsJ1 : chym::kKernelRegJ;
+    switch (code) {
+        case CHYM_KERNEL_LDSJ: return chym::kKernelLdsJ;
+        case CHYM_KERNEL_LDSJ1: return chym::kKernelLdsJ1;
+        case CHYM_KERNEL_PIPE: return chym::kKernelPipe;
+        default: return chym::kKernelRegJ;
+    }
 }
 int code_of_kind(int kind) {
-    return kind == chym::kKernelLdsJ ? CHYM_KERNEL_LDSJ : kind == chym::kKernelLdsJ1 ? CHYM_KERNEL_LDSJ1 : CHYM_KERNEL_REGJ;
+    switch (kind) {
+        case chym::kKernelLdsJ: return CHYM_KERNEL_LDSJ;
+        case chym::kKernelLdsJ1: return CHYM_KERNEL_LDSJ1;
+        case chym::kKernelPipe: return CHYM_KERNEL_PIPE;
+        default: return CHYM_KERNEL_REGJ;
+    }
+}
+bool valid_kernel_code(int code) {
+    return code == CHYM_KERNEL_REGJ || code == CHYM_KERNEL_LDSJ || code == CHYM_KERNEL_LDSJ1 || code == CHYM_KERNEL_PIPE;
 }
 
 Variant variant_of_shape(int n, int precision, int j_dtype) {
@@ -1075,9 +1088,11 @@ int chym_plan_set(const chym_plan_entry *e) {
         g_plan.erase(k);
         return CHYM_OK;
     }
-    if (e->kernel != CHYM_KERNEL_REGJ && e->kernel != CHYM_KERNEL_LDSJ && e->kernel != CHYM_KERNEL_LDSJ1)
-        return fail(CHYM_EINVAL, "kernel = %d is not a CHYM_KERNEL_* value", e->kernel);
+    if (!valid_kernel_code(e->kernel)) return fail(CHYM_EINVAL, "kernel = %d is not a CHYM_KERNEL_* value", e->kernel);
     if (e->waves < 1 || e->waves > 4) return fail(CHYM_EINVAL, "waves = %d must be in 1..4", e->waves);
+    if (!chym::persistent_kind_exists(std::get<0>(k), e->d, std::get<2>(k), std::get<3>(k), kind_of_code(e->kernel)))
+        return fail(CHYM_EUNSUPPORTED, "kernel = %d is not built for n = %d, d = %d in this form", e->kernel, e->n,
+                    e->d);
     g_plan[k] = PlanValue{kind_of_code(e->kernel), e->waves, e->ms};
     return CHYM_OK;
 }
@@ -1125,6 +1140,8 @@ int chym_plan_autotune_workspace_size(int32_t n, int32_t d, int32_t replicas, in
     return CHYM_OK;
 }
 
+constexpr int kTimedReps = 3;  // timed runs per autotune candidate (after one warm-up); the fastest counts
+
 int chym_plan_autotune(int32_t n, int32_t d, int32_t precision, int32_t j_dtype, int32_t replicas, int32_t steps,
                        void *workspace, size_t ws_bytes, chym_plan_entry *best, chym_plan_entry *cand,
                        int32_t max_cand, int32_t *n_cand, chym_stream_t stream) {
@@ -1170,11 +1187,16 @@ int chym_plan_autotune(int32_t n, int32_t d, int32_t precision, int32_t j_dtype,
         had = it != g_plan.end();
         if (had) saved = it->second;
     }
-    const PlanValue cands[] = {{chym::kKernelRegJ, 4, 0.f},
-                               {chym::kKernelLdsJ, 2, 0.f},
-                               {chym::kKernelLdsJ, 4, 0.f},
-                               {chym::kKernelLdsJ1, 4, 0.f}};
-    constexpr int kCands = sizeof(cands) / sizeof(cands[0]);
+    const PlanValue all_cands[] = {{chym::kKernelRegJ, 4, 0.f},
+                                   {chym::kKernelLdsJ, 2, 0.f},
+                                   {chym::kKernelLdsJ, 4, 0.f},
+                                   {chym::kKernelLdsJ1, 4, 0.f},
+                                   {chym::kKernelPipe, 4, 0.f}};
+    PlanValue cands[sizeof(all_cands) / sizeof(all_cands[0])];
+    int kCands = 0;
+    for (const PlanValue &pv : all_cands)
+        if (chym::persistent_kind_exists(std::get<0>(key), d, std::get<2>(key), std::get<3>(key), pv.kind))
+            cands[kCands++] = pv;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -1192,14 +1214,16 @@ int chym_plan_autotune(int32_t n, int32_t d, int32_t precision, int32_t j_dtype,
         rc = chym_batch_create(&task, 1, ws + L.off_batch, L.batch_bytes, &plan);
         if (rc) break;
         float ms = 0.0f;
-        for (int rep = 0; rep < 2 && rc == CHYM_OK; ++rep) {  // warm-up, then timed
+        for (int rep = 0; rep < 1 + kTimedReps && rc == CHYM_OK; ++rep) {  // warm-up, then the fastest timed run
+            float t = 0.0f;
             e = chym::launch_fill_state(task.run.x, (size_t)n * replicas * d, st);
             if (e == hipSuccess) e = hipEventRecord(e0, st);
             if (e == hipSuccess) rc = chym_batch_launch_nograph(plan, st);
             if (e == hipSuccess && rc == CHYM_OK) e = hipEventRecord(e1, st);
             if (e == hipSuccess && rc == CHYM_OK) e = hipEventSynchronize(e1);
-            if (e == hipSuccess && rc == CHYM_OK) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && rc == CHYM_OK) e = hipEventElapsedTime(&t, e0, e1);
             if (e != hipSuccess) rc = hip_fail(e, "autotune timing");
+            if (rep == 1 || (rep > 1 && t < ms)) ms = t;
         }
         chym_batch_destroy(plan);
         if (rc) break;
@@ -1290,7 +1314,7 @@ int chym_features(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dtyp
                   uint64_t *prev_words, float *features, int32_t checkpoint, chym_stream_t stream) {
     int rc = validate_sizes(n, d, r);
     if (rc) return rc;
-    if ((long long)n * (d + 1) > 8192) return fail(CHYM_EUNSUPPORTED, "features need n * (d + 1) <= 8192");
+    if (n > 8192) return fail(CHYM_EUNSUPPORTED, "features need n <= 8192");
     if (j_dtype == CHYM_J_ELL) return fail(CHYM_EUNSUPPORTED, "features take dense couplings");
     if (!valid_jdtype(j_dtype)) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
     if (!j || !x || !prev_words || !features) return fail(CHYM_EINVAL, "pointers must not be NULL");
@@ -1301,6 +1325,43 @@ int chym_features(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dtyp
     hipError_t e = chym::launch_features(n, d, r, j, j_dtype, x, prev_words, features, CHYM_FEATURES, 4 * checkpoint,
                                          (hipStream_t)stream);
     return e == hipSuccess ? CHYM_OK : hip_fail(e, "features launch");
+}
+
+int chym_feature_standardize(int32_t groups, int32_t group, const float *in, float *out, chym_stream_t stream) {
+    if (groups < 1 || group < 1) return fail(CHYM_EINVAL, "groups = %d and group = %d must be >= 1", groups, group);
+    if (!in || !out) return fail(CHYM_EINVAL, "pointers must not be NULL");
+    if ((long long)groups * group * CHYM_FEATURES > (1ll << 31))
+        return fail(CHYM_EUNSUPPORTED, "at most 2^31 feature values");
+    int rc = check_device();
+    if (rc) return rc;
+    hipError_t e = chym::launch_standardize(groups, group, in, out, (hipStream_t)stream);
+    return e == hipSuccess ? CHYM_OK : hip_fail(e, "standardize launch");
+}
+
+int chym_select_top(int32_t groups, int32_t group, int32_t keep, const float *score, int32_t *idx,
+                    chym_stream_t stream) {
+    if (groups < 1 || group < 1) return fail(CHYM_EINVAL, "groups = %d and group = %d must be >= 1", groups, group);
+    if (keep < 1 || keep > group) return fail(CHYM_EINVAL, "keep = %d must be in 1..group (%d)", keep, group);
+    if (!score || !idx) return fail(CHYM_EINVAL, "pointers must not be NULL");
+    if ((long long)groups * group > (1ll << 31) - 1) return fail(CHYM_EUNSUPPORTED, "at most 2^31 - 1 scores");
+    int rc = check_device();
+    if (rc) return rc;
+    hipError_t e = chym::launch_select_top(groups, group, keep, score, idx, (hipStream_t)stream);
+    return e == hipSuccess ? CHYM_OK : hip_fail(e, "select launch");
+}
+
+int chym_gather_replicas(int32_t n, int32_t d, int32_t r_src, const float *x_src, const float *pump_src, int32_t m,
+                         const int32_t *idx, float *x_dst, float *pump_dst, chym_stream_t stream) {
+    int rc = validate_sizes(n, d, r_src);
+    if (rc) return rc;
+    if (m < 0) return fail(CHYM_EINVAL, "m = %d must be >= 0", m);
+    if (!x_src || !idx || !x_dst || (pump_dst && !pump_src)) return fail(CHYM_EINVAL, "pointers must not be NULL");
+    if (m == 0) return CHYM_OK;
+    rc = check_device();
+    if (rc) return rc;
+    hipError_t e = chym::launch_gather_replicas(n, d, r_src, x_src, pump_src, m, idx, x_dst, pump_dst,
+                                                (hipStream_t)stream);
+    return e == hipSuccess ? CHYM_OK : hip_fail(e, "gather launch");
 }
 
 int chym_mlp_scratch_floats(int32_t batch, size_t *floats) {
@@ -1383,7 +1444,7 @@ int chym_plan_load(const char *path) {
         float ms;
         if (sscanf(line, "%d %d %d %d %d %d %f", &t, &d, &xs, &js, &kernel, &waves, &ms) != 7 || t < 1 || d < 1 ||
             d > 4 || (xs != 1 && xs != 3) || (js != 1 && js != 3) ||
-            (kernel != CHYM_KERNEL_REGJ && kernel != CHYM_KERNEL_LDSJ && kernel != CHYM_KERNEL_LDSJ1) || waves < 1 ||
+            !valid_kernel_code(kernel) || waves < 1 ||
             waves > 4) {
             fclose(f);
             return fail(CHYM_EINVAL, "%s:%d: malformed plan entry", path, lineno);

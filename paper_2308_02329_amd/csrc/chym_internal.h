@@ -135,6 +135,10 @@ bool integrate_variant_exists(int tiles, int d, int xs, int js);
 constexpr int kKernelRegJ = 0;
 constexpr int kKernelLdsJ = 1;   // two wavefronts per SIMD
 constexpr int kKernelLdsJ1 = 2;  // one wavefront per SIMD
+constexpr int kKernelPipe = 3;   // one wavefront per SIMD, update and split interleaved with the products
+// Whether a persistent kernel of this kind is built for the shape (the
+// pipelined kind exists for some shapes only).
+bool persistent_kind_exists(int tiles, int d, int xs, int js, int kind);
 hipError_t persistent_occupancy(int tiles, int d, int xs, int js, int kind, int waves_per_block, int *blocks_per_cu);
 hipError_t launch_zero_counters(int *counters, int n, hipStream_t stream);
 // FP8 (E4M3 + per-row power-of-two) packing of a float32 coupling matrix.
@@ -204,6 +208,10 @@ hipError_t launch_integrate_slab_persistent(int tiles, int d, int xs, int js, si
 hipError_t launch_features(int n, int d, int r, const void *j, int j_dtype, const float *x, uint64_t *prev,
                            float *feat, int feat_stride, int feat_off, hipStream_t stream);
 hipError_t launch_sign_words(int n, int d, int r, const float *x, uint64_t *words, hipStream_t stream);
+hipError_t launch_standardize(int groups, int group, const float *in, float *out, hipStream_t stream);
+hipError_t launch_select_top(int groups, int group, int keep, const float *score, int32_t *idx, hipStream_t stream);
+hipError_t launch_gather_replicas(int n, int d, int r_src, const float *x_src, const float *pump_src, int m,
+                                  const int32_t *idx, float *x_dst, float *pump_dst, hipStream_t stream);
 int mlp_param_count();
 size_t mlp_backward_scratch_floats(int batch);
 hipError_t launch_mlp_forward(int batch, const float *feat, const void *wb, float *logit, float *h1, float *h2,

@@ -1,19 +1,29 @@
-// Trajectory features for the learned early restart, and the small MLP that
-// maps them to a success logit.
+// Trajectory features for the learned early restart, the per-batch
+// standardization, top-k selection and replica gather that the restart loop
+// needs, and the small MLP that maps the features to a success logit.
 //
-// Features (per replica, at one checkpoint): the hyperspin energy per spin
-// E_hs / N (Eq. (3), unit vectors), the Ising energy per spin of the current
-// sign readout E / N, the mean hyperspin norm mean_p |x_p|, and the fraction
-// of spins whose sign flipped since the previous checkpoint.  One wavefront
-// per replica, float64 reductions.
+// Features (per replica, at one checkpoint), all about the first component,
+// the one the anneal keeps and the readout reads: its Rayleigh quotient per
+// spin -(x_1^T J x_1) / (n x_1^T x_1), the Ising energy per spin of the
+// current sign readout, the first component's share of the squared norm
+// sum_p x_{p,1}^2 / sum_{p,mu} x_{p,mu}^2, and the fraction of spins whose
+// sign flipped since the previous checkpoint.  Runs of one problem and pump
+// reach the same hyperspin configuration up to a rotation, so quantities
+// invariant under rotations (the hyperspin energy, the norms) do not tell
+// them apart; the first component's orientation does.  One wavefront per
+// replica, float32 sums in a fixed order.
 //
 // MLP: 32 -> 128 -> 128 -> 1, ReLU, sigmoid output, binary cross-entropy.
 // Weights are kept as float32 master copies (updated by Adam) and as a bf16
 // copy that the forward and backward passes use; activations and
 // accumulations are float32.
+#include <algorithm>
+
 #include "chym_internal.h"
 
 namespace chym {
+
+constexpr int kFeat = CHYM_FEATURES;  // feature columns per replica
 
 template <typename T>
 __device__ __forceinline__ T wsum(T v) {
@@ -22,66 +32,198 @@ __device__ __forceinline__ T wsum(T v) {
     return v;
 }
 
-// LDS per wavefront: u[n][d] (float64) and the n signs as +-1 (float64).
+// LDS per wavefront: the first components x_{p,1} [n] and the signs as +-1 [n].
 __global__ __launch_bounds__(64) void k_features(int n, int d, int r, const void *__restrict__ j, int j_dtype,
                                                  const float *__restrict__ x, uint64_t *__restrict__ prev,
                                                  float *__restrict__ feat, int feat_stride, int feat_off) {
-    extern __shared__ double sh[];
-    double *u = sh;            // [n][d]
-    double *sg = sh + n * d;   // [n]
+    extern __shared__ float shf[];
+    float *x1 = shf;       // [n]
+    float *sg = shf + n;   // [n]
     const int lane = threadIdx.x;
     const int rep = blockIdx.x;
     if (rep >= r) return;
     const int w = (n + 63) >> 6;
-    double nsum = 0.0;
+    float s1 = 0.0f, sall = 0.0f;
     int flips = 0;
     for (int q = lane; q < n; q += 64) {
         const float *xq = x + ((size_t)q * r + rep) * d;
-        double s = 0.0;
-        for (int mu = 0; mu < d; ++mu) {
-            const double v = (double)xq[mu];
-            s = s + v * v;
-        }
-        const double nrm = sqrt(s);
-        nsum += nrm;
-        for (int mu = 0; mu < d; ++mu) u[q * d + mu] = nrm > 0.0 ? (double)xq[mu] / nrm : 0.0;
+        float s = 0.0f;
+        for (int mu = 0; mu < d; ++mu) s = fmaf(xq[mu], xq[mu], s);
+        sall += s;
+        s1 = fmaf(xq[0], xq[0], s1);
+        x1[q] = xq[0];
         const bool up = xq[0] >= 0.0f;
-        sg[q] = up ? 1.0 : -1.0;
+        sg[q] = up ? 1.0f : -1.0f;
         const bool was = (prev[(size_t)rep * w + (q >> 6)] >> (q & 63)) & 1ull;
         flips += (up != was);
     }
     __syncthreads();
-    double ehs = 0.0, eis = 0.0;
+    // column sums: G_q = sum_p J_pq x_{p,1}, h_q = sum_p J_pq sigma_p, so that
+    // x_1^T J x_1 = sum_q x_{q,1} G_q and sigma^T J sigma = sum_q sigma_q h_q
+    float quad = 0.0f, eis = 0.0f;
     for (int q = lane; q < n; q += 64) {
-        double hh = 0.0, hi = 0.0;
+        float gq = 0.0f, hq = 0.0f;
         for (int p = 0; p < n; ++p) {
-            const double jv = (double)coupling(j, j_dtype, n, p, q);
-            double dot = 0.0;
-            for (int mu = 0; mu < d; ++mu) dot = dot + u[p * d + mu] * u[q * d + mu];
-            hh = hh + jv * dot;
-            hi = hi + jv * sg[p];
+            const float jv = coupling(j, j_dtype, n, p, q);
+            gq = fmaf(jv, x1[p], gq);
+            hq = fmaf(jv, sg[p], hq);
         }
-        ehs += hh;
-        eis += hi * sg[q];
+        quad = fmaf(x1[q], gq, quad);
+        eis = fmaf(sg[q], hq, eis);
     }
-    ehs = wsum(ehs);
+    quad = wsum(quad);
     eis = wsum(eis);
-    nsum = wsum(nsum);
+    s1 = wsum(s1);
+    sall = wsum(sall);
     flips = wsum(flips);
     // new sign words (one per 64 spins, built by the lanes that own them)
     __syncthreads();
     for (int wd = 0; wd < w; ++wd) {
         const int q = wd * 64 + lane;
-        const bool up = q < n && sg[q] > 0.0;
+        const bool up = q < n && sg[q] > 0.0f;
         const uint64_t bits = __ballot(up);
         if (lane == 0) prev[(size_t)rep * w + wd] = bits;
     }
     if (lane == 0) {
         float *f = feat + (size_t)rep * feat_stride + feat_off;
-        f[0] = (float)(-ehs / n);
-        f[1] = (float)(-eis / n);
-        f[2] = (float)(nsum / n);
+        f[0] = s1 > 0.0f ? -quad / ((float)n * s1) : 0.0f;
+        f[1] = -eis / (float)n;
+        f[2] = sall > 0.0f ? s1 / sall : 0.0f;
         f[3] = (float)flips / (float)n;
+    }
+}
+
+// Standardizes every feature column within each group of `group`
+// consecutive replicas (one pump's batch of runs): (f - mean) / sd, with the
+// mean and the population standard deviation of the group, 0 where sd = 0.
+// One block per group; sums in a fixed order (per-thread strides, then a
+// tree), so the result is deterministic.
+__global__ __launch_bounds__(256) void k_standardize(int group, const float *__restrict__ in,
+                                                     float *__restrict__ out) {
+    __shared__ float red[256];
+    const size_t base = (size_t)blockIdx.x * group * kFeat;
+    for (int c = 0; c < kFeat; ++c) {
+        float sum = 0.0f;
+        for (int i = threadIdx.x; i < group; i += blockDim.x) sum += in[base + (size_t)i * kFeat + c];
+        red[threadIdx.x] = sum;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        const float mean = red[0] / (float)group;
+        __syncthreads();
+        float ss = 0.0f;
+        for (int i = threadIdx.x; i < group; i += blockDim.x) {
+            const float v = in[base + (size_t)i * kFeat + c] - mean;
+            ss = fmaf(v, v, ss);
+        }
+        red[threadIdx.x] = ss;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        const float sd = sqrtf(red[0] / (float)group);
+        __syncthreads();
+        for (int i = threadIdx.x; i < group; i += blockDim.x) {
+            const float v = in[base + (size_t)i * kFeat + c];
+            out[base + (size_t)i * kFeat + c] = sd > 0.0f ? (v - mean) / sd : 0.0f;
+        }
+    }
+}
+
+// Order-preserving map of a float to an unsigned key (NaN lowest).
+__device__ __forceinline__ uint32_t score_key(float v) {
+    if (v != v) return 0u;
+    const uint32_t b = __float_as_uint(v);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+template <int B>
+__device__ __forceinline__ int block_count(bool pred, int *red) {
+    const uint64_t m = __ballot(pred);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[wv] = __popcll(m);
+    __syncthreads();
+    int tot = 0;
+    for (int i = 0; i < B / 64; ++i) tot += red[i];
+    __syncthreads();
+    return tot;
+}
+
+// Exclusive prefix count of pred over the block in thread order, and the total.
+template <int B>
+__device__ __forceinline__ int block_scan(bool pred, int *red, int *total) {
+    const uint64_t m = __ballot(pred);
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    if (ln == 0) red[wv] = __popcll(m);
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int i = 0; i < B / 64; ++i) {
+        if (i < wv) before += red[i];
+        tot += red[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + __popcll(m & ((ln == 0) ? 0ull : (~0ull >> (64 - ln))));
+}
+
+// For each group of `group` consecutive scores, the indices of its `keep`
+// highest scores (equal scores: the lower index first; NaN lowest), written
+// in ascending order to idx[g * keep ...] as global replica indices.  One
+// block per group: a bisection over the 32-bit keys finds the keep-th
+// largest key, then one ordered pass writes the indices.
+__global__ __launch_bounds__(1024) void k_select_top(int group, int keep, const float *__restrict__ score,
+                                                     int32_t *__restrict__ idx) {
+    __shared__ int red[16];
+    const size_t base = (size_t)blockIdx.x * group;
+    uint32_t lo = 0u, hi = 0xffffffffu;  // invariant: count(key >= lo) >= keep
+    while (lo < hi) {
+        const uint32_t mid = lo + (uint32_t)(((uint64_t)hi - lo + 1) >> 1);
+        int cnt = 0;
+        for (int i0 = 0; i0 < group; i0 += 1024) {
+            const int i = i0 + threadIdx.x;
+            cnt += block_count<1024>(i < group && score_key(score[base + i]) >= mid, red);
+        }
+        if (cnt >= keep) lo = mid;
+        else hi = mid - 1u;
+    }
+    const uint32_t t = lo;
+    int above = 0;  // keys strictly above t: all kept
+    for (int i0 = 0; i0 < group; i0 += 1024) {
+        const int i = i0 + threadIdx.x;
+        above += block_count<1024>(i < group && score_key(score[base + i]) > t, red);
+    }
+    int eq_left = keep - above;  // keys equal to t still to keep, lowest index first
+    int out = 0;
+    for (int i0 = 0; i0 < group; i0 += 1024) {
+        const int i = i0 + threadIdx.x;
+        const uint32_t k = i < group ? score_key(score[base + i]) : 0u;
+        int eq_tot = 0;
+        const int eq_before = block_scan<1024>(i < group && k == t, red, &eq_tot);
+        const bool take = i < group && (k > t || (k == t && eq_before < eq_left));
+        int tot = 0;
+        const int pos = block_scan<1024>(take, red, &tot);
+        if (take) idx[(size_t)blockIdx.x * keep + out + pos] = (int32_t)(base + i);
+        out += tot;
+        eq_left -= eq_tot < eq_left ? eq_tot : eq_left;
+    }
+}
+
+// x_dst[p][j][mu] = x_src[p][idx[j]][mu] and pump_dst[j] = pump_src[idx[j]].
+__global__ __launch_bounds__(256) void k_gather_replicas(int n, int d, int r_src, const float *__restrict__ x_src,
+                                                         const float *__restrict__ pump_src, int m,
+                                                         const int32_t *__restrict__ idx, float *__restrict__ x_dst,
+                                                         float *__restrict__ pump_dst) {
+    const size_t tot = (size_t)n * m * d;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int mu = (int)(e % d);
+        const size_t jq = e / d;
+        const int jr = (int)(jq % m);
+        const size_t p = jq / m;
+        x_dst[e] = x_src[(p * r_src + idx[jr]) * d + mu];
+        if (p == 0 && mu == 0 && pump_dst) pump_dst[jr] = pump_src[idx[jr]];
     }
 }
 
@@ -102,7 +244,7 @@ __global__ __launch_bounds__(64) void k_sign_words(int n, int d, int r, const fl
 
 hipError_t launch_features(int n, int d, int r, const void *j, int j_dtype, const float *x, uint64_t *prev,
                            float *feat, int feat_stride, int feat_off, hipStream_t stream) {
-    const size_t lds = sizeof(double) * ((size_t)n * d + n);
+    const size_t lds = sizeof(float) * 2 * (size_t)n;
     hipLaunchKernelGGL(k_features, dim3(r), dim3(64), lds, stream, n, d, r, j, j_dtype, x, prev, feat, feat_stride,
                        feat_off);
     return hipGetLastError();
@@ -110,6 +252,28 @@ hipError_t launch_features(int n, int d, int r, const void *j, int j_dtype, cons
 
 hipError_t launch_sign_words(int n, int d, int r, const float *x, uint64_t *words, hipStream_t stream) {
     hipLaunchKernelGGL(k_sign_words, dim3(r), dim3(64), 0, stream, n, d, r, x, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_standardize(int groups, int group, const float *in, float *out, hipStream_t stream) {
+    if (groups <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_standardize, dim3(groups), dim3(256), 0, stream, group, in, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_top(int groups, int group, int keep, const float *score, int32_t *idx, hipStream_t stream) {
+    if (groups <= 0 || keep <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_select_top, dim3(groups), dim3(1024), 0, stream, group, keep, score, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_replicas(int n, int d, int r_src, const float *x_src, const float *pump_src, int m,
+                                  const int32_t *idx, float *x_dst, float *pump_dst, hipStream_t stream) {
+    if (m <= 0) return hipSuccess;
+    const size_t tot = (size_t)n * m * d;
+    const unsigned blocks = (unsigned)std::min<size_t>((tot + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_gather_replicas, dim3(blocks), dim3(256), 0, stream, n, d, r_src, x_src, pump_src, m, idx,
+                       x_dst, pump_dst);
     return hipGetLastError();
 }
 

@@ -1,21 +1,27 @@
 """Learned early restart for the CHYM and its time-to-solution accounting.
 
-A run of the machine is cheap to start and expensive to finish.  From
-features of its first part (default: the first 10 % of the Euler steps,
-sampled at 8 checkpoints, see ``chym_features`` in include/chym.h) a small
-network predicts whether the run will end in the Ising ground state; at
-that checkpoint each pump's batch of runs keeps its highest-scored fraction
-and the others are abandoned and restarted from fresh initial states (a
-rank within the batch, not an absolute threshold: the network's scores are
-not calibrated across instances).
-Every kept run is still integrated to the end and scored by its exact Ising
-energy, so the method's answers are unchanged; only the cost per success
-changes.  The plain method (no restarts) is the fallback.
+A run of the machine is cheap to start and expensive to finish.  At a
+decision point early in the run (default: after the first 10 % of the
+Euler steps, with features sampled at 8 checkpoints, see ``chym_features``
+in include/chym.h) a small network scores every run; each pump's batch of
+runs keeps its highest-scored fraction, integrates only those to the end,
+and starts fresh runs instead of the others.  Every kept run is still
+integrated to the end and judged by its exact Ising energy, so the method's
+answers are unchanged; only the cost per success changes.  Keeping every
+run is the plain method, always a candidate when the policy is chosen.
 
-All arithmetic runs in libchym's kernels: the integrator, the feature
-kernel, and the network's forward, backward and Adam kernels.  This module
-holds the orchestration: data generation, the training loop, the
-restart policy and the time-to-99%-success (TTS99) bookkeeping
+Runs of one problem and pump converge to the same hyperspin configuration
+up to a rotation; what tells them apart early is the orientation of the
+first component, the one the anneal keeps.  The features describe it
+(Rayleigh quotient, Ising energy of its signs, its share of the norm, sign
+flips) and are standardized within each pump's batch of runs, since the
+policy ranks runs within such a batch.
+
+All arithmetic runs in libchym's kernels: the integrator, the features,
+their standardization, the network's forward, backward and Adam kernels,
+the top-k selection of the kept runs and their gather.  This module holds
+the orchestration: data generation, the training loop, the executed policy
+and the time-to-99%-success (TTS99) bookkeeping
 
     TTS99 = t_attempt * ln(0.01) / ln(1 - p_success_per_attempt)
 
@@ -24,8 +30,8 @@ infinity).  With restarts an attempt costs the partial run, plus the rest of
 the run for the kept fraction, and succeeds when kept and successful.
 
 The ground-state energy of an instance is the best energy found by any run
-of it (a putative ground state; exact ones come from exhaustive search in
-the tests).
+of it and by a longer search (a putative ground state; exact ones come from
+exhaustive search in the tests).
 
     python -m paper_2308_02329_amd.learned --out report.json
 """
@@ -49,8 +55,8 @@ N_FEAT = L.CHYM_FEATURES
 # ---------------------------------------------------------------- network
 class RestartNet:
     """32 -> 128 -> 128 -> 1 network on the GPU: float32 master weights, a
-    bf16 copy used by the forward/backward kernels, Adam moments, and the
-    feature standardization (mean, scale) learned from the training set."""
+    bf16 copy used by the forward/backward kernels, and Adam moments.  Its
+    inputs are features standardized within each pump's batch of runs."""
 
     def __init__(self, seed: int = 0, device: str = "cuda"):
         g = np.random.default_rng(seed)
@@ -65,8 +71,6 @@ class RestartNet:
         self.m = torch.zeros_like(self.w)
         self.v = torch.zeros_like(self.w)
         self.t = 0
-        self.mu = torch.zeros(N_FEAT, device=self.device)
-        self.sd = torch.ones(N_FEAT, device=self.device)
         self._bufs = {}
 
     def state(self):
@@ -76,13 +80,6 @@ class RestartNet:
         for dst, src in zip((self.w, self.wb, self.m, self.v), st[:4]):
             dst.copy_(src)
         self.t = st[4]
-
-    def set_scaler(self, feats: torch.Tensor):
-        self.mu = feats.mean(dim=0)
-        self.sd = feats.std(dim=0).clamp_min(1e-6)
-
-    def standardize(self, feats: torch.Tensor) -> torch.Tensor:
-        return ((feats - self.mu) / self.sd).contiguous()
 
     def _buf(self, b):
         if b not in self._bufs:
@@ -107,28 +104,14 @@ class RestartNet:
         return float(bf["loss"].mean().item())
 
     def logits(self, xs: torch.Tensor) -> torch.Tensor:
-        """Logits of standardized features."""
+        """Logits (the policy ranks by them; the sigmoid is monotone)."""
         return api.chym_mlp_forward(xs.contiguous(), self.wb)
-
-    def inference_weights(self) -> torch.Tensor:
-        """bf16 weights with the standardization folded into the first layer,
-        so that raw features go straight into the forward kernel:
-        W1' = W1 / sd (per input), b1' = b1 - W1' mu."""
-        w = self.w.clone()
-        w1 = w[:4096].view(128, 32) / self.sd[None, :]
-        w[:4096] = w1.reshape(-1)
-        w[4096:4224] = w[4096:4224] - w1 @ self.mu
-        return api.chym_to_bf16(w)
-
-    def predict_raw(self, feats: torch.Tensor, wb_inf: torch.Tensor | None = None) -> torch.Tensor:
-        wb_inf = self.inference_weights() if wb_inf is None else wb_inf
-        return api.chym_mlp_forward(feats.contiguous(), wb_inf)
 
     def fit(self, xs: torch.Tensor, y: torch.Tensor, epochs: int = 4, batch: int = 8192, lr: float = 2e-3,
             seed: int = 0, pos_frac: float = 0.0, log=None) -> list:
-        """Mini-batch training on standardized features; returns epoch losses.
-        pos_frac > 0 draws that share of every batch from the positives (with
-        replacement): rare successes are otherwise a handful per batch."""
+        """Mini-batch training; returns epoch losses.  pos_frac > 0 draws that
+        share of every batch from the positives (with replacement): rare
+        successes are otherwise a handful per batch."""
         g = torch.Generator(device=xs.device)
         g.manual_seed(seed)
         n = xs.shape[0]
@@ -159,60 +142,134 @@ class RestartNet:
 
 
 # ------------------------------------------------------------- simulation
-def run_instance(J, pumps_per_replica, x0, steps, dt, eps, btil, eta, precision, frac=0.1, n_ckpt=N_CKPT,
-                 d=3):
-    """Integrate one instance with feature checkpoints in the first `frac` of
-    the steps.  Returns (features [R, 32], Ising energies [R], gpu ms of the
-    partial phase, gpu ms of the rest, total updates)."""
-    dev = x0.device
-    n, r, _ = x0.shape
-    alpha = torch.from_numpy(synth.anneal_schedule(steps, d)[0]).to(dev)
-    x = x0.clone()
+def checkpoints(steps, frac=0.1, n_ckpt=N_CKPT):
+    """The n_ckpt feature checkpoints (step counts) spread over the first
+    `frac` of the run; the last one is the decision point."""
     k_feat = max(n_ckpt, int(round(frac * steps)))
-    ckpts = [int(round(k_feat * (c + 1) / n_ckpt)) for c in range(n_ckpt)]
-    feats = torch.zeros((r, N_FEAT), dtype=torch.float32, device=dev)
-    prm = dict(eps=eps, btil=btil, eta=eta, dt=dt, precision=precision)
-    ws = None
-    nbytes = api.chym_integrate_workspace_size(J, x, precision=precision)
-    if nbytes:
-        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    return [int(round(k_feat * (c + 1) / n_ckpt)) for c in range(n_ckpt)]
+
+
+class Problem:
+    """One SK instance with its run inputs on the device."""
+
+    def __init__(self, Jn, d=3, steps=20000, dt=0.01, eta=2e-4, device="cuda"):
+        self.Jn = Jn
+        self.n, self.d, self.steps = Jn.shape[0], d, steps
+        self.dev = torch.device(device)
+        self.J = torch.from_numpy(Jn).to(self.dev)
+        self.alpha = torch.from_numpy(synth.anneal_schedule(steps, d)[0]).to(self.dev)
+        self.prm = dict(eps=float(np.float32(synth.default_eps(Jn))), btil=1.0, eta=eta, dt=dt)
+
+    def integrate(self, pump, x, k0, k1, precision, ws=None):
+        if k1 > k0:
+            api.chym_integrate(self.J, pump, x, self.alpha, steps=k1 - k0, start_step=k0, precision=precision,
+                               workspace=ws, **self.prm)
+
+    def workspace(self, x, precision):
+        nb = api.chym_integrate_workspace_size(self.J, x, precision=precision)
+        return torch.empty(nb + 256, dtype=torch.uint8, device=self.dev) if nb else None
+
+    def energies(self, x):
+        r = x.shape[1]
+        spins = torch.empty((r, api.spin_words(self.n)), dtype=torch.int64, device=self.dev)
+        api.chym_readout(x, spins)
+        e = torch.empty(r, dtype=torch.int32, device=self.dev)
+        api.chym_ising_energy(self.J, spins, e)
+        return e
+
+    def features(self, pump, x, group, precision, ws, frac=0.1):
+        """Phase one of a run: integrate x to the decision point, taking the
+        features at the checkpoints; returns them standardized within each
+        pump batch of `group` runs, and the decision step."""
+        r = x.shape[1]
+        feats = torch.zeros((r, N_FEAT), dtype=torch.float32, device=self.dev)
+        words = api.chym_sign_words(x)
+        k = 0
+        for c, kc in enumerate(checkpoints(self.steps, frac)):
+            self.integrate(pump, x, k, kc, precision, ws)
+            api.chym_features(self.J, x, words, feats, c)
+            k = kc
+        api.chym_feature_standardize(feats, group, out=feats)
+        return feats, k
+
+
+def run_with_features(prob: Problem, pump, x0, group, precision="bf16", frac=0.1):
+    """Every run to the end, with the features of its first part: (features
+    [R, 32], Ising energies [R], GPU ms of the first part, GPU ms of the
+    rest)."""
+    x = x0.clone()
+    ws = prob.workspace(x, precision)
     e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
     e0.record()
-    words = api.chym_sign_words(x)
-    k = 0
-    for c, kc in enumerate(ckpts):
-        api.chym_integrate(J, pumps_per_replica, x, alpha, steps=kc - k, start_step=k, workspace=ws, **prm)
-        api.chym_features(J, x, words, feats, c)
-        k = kc
+    feats, k = prob.features(pump, x, group, precision, ws, frac)
     e1.record()
-    api.chym_integrate(J, pumps_per_replica, x, alpha, steps=steps - k, start_step=k, workspace=ws, **prm)
-    spins = torch.empty((r, api.spin_words(n)), dtype=torch.int64, device=dev)
-    api.chym_readout(x, spins)
-    e = torch.empty(r, dtype=torch.int32, device=dev)
-    api.chym_ising_energy(J, spins, e)
+    prob.integrate(pump, x, k, prob.steps, precision, ws)
+    e = prob.energies(x)
     e2.record()
     torch.cuda.synchronize()
-    return feats, e, e0.elapsed_time(e1), e1.elapsed_time(e2), n * r * d * steps
+    return feats, e, e0.elapsed_time(e1), e1.elapsed_time(e2)
 
 
-def generate(n_inst, n=200, d=3, n_ic=1000, n_pumps=20, steps=5000, dt=0.01, precision="bf16", seed_base=0,
-             config=5, device="cuda", frac=0.1, log=None):
-    """Simulated trajectories of n_inst SK instances (n_ic initial states x
-    n_pumps pumps each).  Returns per-instance dicts."""
-    dev = torch.device(device)
-    pumps = np.linspace(0.5, 2.0, n_pumps)
-    pr = torch.from_numpy(synth.pump_grid(n_ic, pumps)).to(dev)
+def run_plain(prob: Problem, pump, x0, precision):
+    """The plain method: every run to the end, no features.  (energies, ms)."""
+    x = x0.clone()
+    ws = prob.workspace(x, precision)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    prob.integrate(pump, x, 0, prob.steps, precision, ws)
+    e = prob.energies(x)
+    e1.record()
+    torch.cuda.synchronize()
+    return e, e0.elapsed_time(e1)
+
+
+def run_policy(prob: Problem, net: RestartNet, pump, x0, group, keep, precision="bf16", frac=0.1):
+    """The restart policy executed: every run to the decision point with
+    features, the network's scores, the ceil(keep * group) best of each pump
+    batch gathered into a compact state and integrated to the end, their
+    exact energies.  Returns (kept global indices [R // group, m], their
+    energies [R // group * m], GPU ms of the whole)."""
+    x = x0.clone()
+    r = x.shape[1]
+    m = max(1, int(math.ceil(keep * group)))
+    ws = prob.workspace(x, precision)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    feats, k = prob.features(pump, x, group, precision, ws, frac)
+    logit = net.logits(feats)
+    idx = api.chym_select_top(logit, group, m)
+    xk, pk = api.chym_gather_replicas(x, idx, pump=pump)
+    wk = prob.workspace(xk, precision)
+    prob.integrate(pk, xk, k, prob.steps, precision, wk)
+    e = prob.energies(xk)
+    e1.record()
+    torch.cuda.synchronize()
+    assert r % group == 0
+    return idx, e, e0.elapsed_time(e1)
+
+
+def instance(index, n=200, config=5):
+    return synth.sk_pm1(n, config, index)
+
+
+def initial_states(prob, r, seed):
+    return synth.initial_states_torch(prob.n, r, prob.d, seed=seed, device=prob.dev)
+
+
+def generate(indices, n=200, d=3, n_ic=1000, pumps=np.linspace(0.5, 2.0, 20), steps=20000, frac=0.1,
+             precision="bf16", seed_base=7, log=None):
+    """Runs of the instances (n_ic initial states x each pump) with features
+    of their first part.  Returns per-instance dicts."""
     out = []
-    for i in range(n_inst):
-        Jn = synth.sk_pm1(n, config, seed_base + i)
-        eps = float(np.float32(synth.default_eps(Jn)))
-        J = torch.from_numpy(Jn).to(dev)
-        x0 = synth.initial_states_torch(n, n_ic * n_pumps, d, seed=1000003 * config + seed_base + i, device=dev)
-        f, e, t_part, t_rest, ups = run_instance(J, pr, x0, steps, dt, eps, 1.0, 2e-4, precision, frac=frac, d=d)
-        out.append(dict(index=seed_base + i, J=Jn, feats=f, E=e, t_part_ms=t_part, t_rest_ms=t_rest, updates=ups,
-                        n_ic=n_ic, n_pumps=n_pumps, pumps=pumps))
+    for i in indices:
+        prob = Problem(instance(i, n), d, steps)
+        pr = torch.from_numpy(synth.pump_grid(n_ic, pumps)).to(prob.dev)
+        x0 = initial_states(prob, pr.shape[0], seed_base * 1000003 + i)
+        f, e, t_part, t_rest = run_with_features(prob, pr, x0, n_ic, precision, frac)
+        out.append(dict(index=i, Jn=prob.Jn, feats=f, E=e, t_part_ms=t_part, t_rest_ms=t_rest, n_ic=n_ic,
+                        pumps=np.asarray(pumps), steps=steps))
         if log:
-            log(f"instance {seed_base + i}: {precision} {t_part + t_rest:.1f} ms, best E {int(e.min().item())}")
+            log(f"instance {i}: {precision} {t_part + t_rest:.1f} ms, best E {int(e.min().item())}")
     return out
 
 
@@ -243,19 +300,31 @@ def auc(scores, labels):
     return float((ranks[labels].sum() - npos * (npos + 1) / 2) / (npos * nneg))
 
 
+def within_batch_auc(scores, labels, group):
+    """Mean AUC over the pump batches (groups of consecutive runs) that hold
+    both outcomes: how well the scores rank runs within a batch, the only
+    ranking the policy uses."""
+    s = np.asarray(scores).reshape(-1, group)
+    y = np.asarray(labels, dtype=bool).reshape(-1, group)
+    vals = [auc(a, b) for a, b in zip(s, y) if 0 < b.sum() < group]
+    return float(np.mean(vals)) if vals else float("nan")
+
+
 def instance_tts(inst, egs, q=None, keep=1.0):
-    """Best-pump TTS99 (ms) of an instance.  With scores q, the restart
-    policy keeps, in every pump's batch of runs, the ceil(keep * n_ic) runs
-    with the highest scores at the checkpoint and restarts the others (ties
-    by run index); keep = 1 is the plain method."""
+    """Best-pump TTS99 (ms) of an instance from its runs with features (the
+    cost model: the measured first part for every run, the measured rest for
+    the kept ones).  With scores q, the restart policy keeps, in every
+    pump's batch of runs, the ceil(keep * n_ic) runs with the highest scores
+    at the decision point (ties by run index); keep = 1 is the plain
+    method."""
     e = inst["E"].cpu().numpy()
     succ = e == egs
     R = len(e)
     t_part = inst["t_part_ms"] / R
     t_full = (inst["t_part_ms"] + inst["t_rest_ms"]) / R
     best = math.inf
-    n_ic, n_p = inst["n_ic"], inst["n_pumps"]
-    for k in range(n_p):
+    n_ic = inst["n_ic"]
+    for k in range(R // n_ic):
         sl = slice(k * n_ic, (k + 1) * n_ic)
         s = succ[sl]
         if q is None or keep >= 1.0:
@@ -270,19 +339,6 @@ def instance_tts(inst, egs, q=None, keep=1.0):
     return best
 
 
-def evaluate(insts_plain, insts_learned, egs, net, keep):
-    q_all = []
-    rows = []
-    for ip, il, g in zip(insts_plain, insts_learned, egs):
-        q = torch.sigmoid(net.predict_raw(il["feats"])).cpu().numpy()
-        q_all.append(q)
-        rows.append(dict(index=ip["index"], egs=int(g), tts_plain_f32_ms=instance_tts(ip, g),
-                         tts_bf16_ms=instance_tts(il, g), tts_bf16_learned_ms=instance_tts(il, g, q, keep),
-                         p_best_f32=float(max((ip["E"].cpu().numpy() == g)[k * ip["n_ic"]:(k + 1) * ip["n_ic"]].mean()
-                                              for k in range(ip["n_pumps"])))))
-    return rows, q_all
-
-
 def validation_score(tts, base):
     """Score of a restart policy on validation instances: the geometric mean
     of its best-pump TTS99 over the instances the plain method solves (base
@@ -295,13 +351,13 @@ def validation_score(tts, base):
     return float(np.exp(np.mean(np.log(tts[ok]))))
 
 
-KEEP_GRID = (1.0, 0.7, 0.5, 0.35, 0.25, 0.18, 0.12, 0.08, 0.05, 0.03, 0.02, 0.01)
+KEEP_GRID = (1.0, 0.85, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2)
 
 
 def choose_keep(insts, egs, net, grid=KEEP_GRID):
     """Kept fraction with the lowest validation_score on insts (1, never
     restart, is always feasible).  Returns (keep, score in ms)."""
-    qs = [torch.sigmoid(net.predict_raw(i["feats"])).cpu().numpy() for i in insts]
+    qs = [net.logits(i["feats"]).cpu().numpy() for i in insts]
     base = [instance_tts(i, g) for i, g in zip(insts, egs)]
     best = (math.inf, 1.0)
     for kf in grid:
@@ -325,116 +381,177 @@ def search_egs(Jn, n_rep=20000, d=3, steps=20000, dt=0.01, seed=0, device="cuda"
     return int(out["e_ising"].min().item())
 
 
-def experiment(n_train=50, n_val=10, n_test=20, n=100, d=3, n_ic=1000, n_pumps=20, steps=5000, epochs=6, seed=0,
-               frac=0.1, pos_frac=0.1, lr=2e-3, search_steps=20000, n_ic_eval=5000, log=print):
-    """Generate, train, evaluate; returns a JSON-able report.
+def bootstrap_ratio(num, den, reps=2000, seed=0):
+    """Geometric mean of num / den over instances with a 95 % bootstrap
+    interval (resampling instances)."""
+    r = np.log(np.asarray(num, dtype=np.float64) / np.asarray(den, dtype=np.float64))
+    if r.size == 0:
+        return math.nan, (math.nan, math.nan)
+    g = np.random.default_rng(seed)
+    boots = [np.exp(np.mean(r[g.integers(0, r.size, r.size)])) for _ in range(reps)]
+    return float(np.exp(r.mean())), (float(np.percentile(boots, 2.5)), float(np.percentile(boots, 97.5)))
 
-    Training and validation instances are run in the BF16 form; held-out
-    instances in both forms from the same initial states.  The putative
-    ground state of an instance is the best energy of any of its runs,
-    including a longer search (search_steps > 0).  The epoch and the
-    kept fraction of the restart policy are those with the lowest
-    validation_score (geometric mean TTS99 over the validation instances,
-    no instance the plain method solves may be lost); keeping every run
-    (the plain method) is always a candidate.  Validation and held-out instances get n_ic_eval
-    initial states per pump: success is rare enough that a best-pump
-    TTS99 from fewer runs is mostly noise."""
+
+def evaluate_instance(i, net, keep, n=200, d=3, steps=20000, pilot_ic=1000, eval_ic=20000, n_eval_pumps=3,
+                      pumps=np.linspace(0.5, 2.0, 20), search_steps=20000, frac=0.1, seed_base=11):
+    """One held-out instance: a plain BF16 pilot over every pump picks its
+    n_eval_pumps best pumps; there, from the same eval_ic fresh initial
+    states per pump, the plain FP32 form, the plain BF16 form and the BF16
+    form with the restart policy are run and timed end to end.  The
+    putative ground state is the best energy of all of these and of a longer
+    search.  Returns the per-method best-pump TTS99 (measured costs), the
+    success counts and the cost model's prediction for the policy."""
+    prob = Problem(instance(i, n), d, steps)
+    pr = torch.from_numpy(synth.pump_grid(pilot_ic, pumps)).to(prob.dev)
+    e_pilot, _ = run_plain(prob, pr, initial_states(prob, pr.shape[0], seed_base * 1000003 + i), "bf16")
+    ep = e_pilot.cpu().numpy().reshape(len(pumps), pilot_ic)
+    counts = (ep == ep.min()).sum(axis=1)
+    chosen = np.sort(np.argsort(-counts, kind="stable")[:n_eval_pumps])
+    pe = np.asarray(pumps)[chosen]
+    pr = torch.from_numpy(synth.pump_grid(eval_ic, pe)).to(prob.dev)
+    x0 = initial_states(prob, pr.shape[0], (seed_base + 1) * 1000003 + i)
+    e_f32, ms_f32 = run_plain(prob, pr, x0, "f32")
+    e_bf, ms_bf = run_plain(prob, pr, x0, "bf16")
+    idx, e_kept, ms_pol = run_policy(prob, net, pr, x0, eval_ic, keep, "bf16", frac)
+    f_cm, e_cm, t_part, t_rest = run_with_features(prob, pr, x0, eval_ic, "bf16", frac)
+    egs = min(int(ep.min()), int(e_f32.min().item()), int(e_bf.min().item()))
+    if search_steps:
+        egs = min(egs, search_egs(prob.Jn, d=d, steps=search_steps, seed=7 + i))
+    R = pr.shape[0]
+    m = idx.shape[1]
+    s_f32 = (e_f32.cpu().numpy() == egs).reshape(len(pe), eval_ic)
+    s_bf = (e_bf.cpu().numpy() == egs).reshape(len(pe), eval_ic)
+    s_pol = (e_kept.cpu().numpy() == egs).reshape(len(pe), m)
+    # the kept runs followed the same trajectories as in the plain BF16 run
+    same = bool(np.array_equal(e_kept.cpu().numpy(), e_bf.cpu().numpy()[idx.cpu().numpy().ravel()]))
+    t = {"plain_f32": min(tts99(ms_f32 / R, s.mean()) for s in s_f32),
+         "bf16": min(tts99(ms_bf / R, s.mean()) for s in s_bf),
+         "bf16_learned": min(tts99(ms_pol / R, s.sum() / eval_ic) for s in s_pol)}
+    model_cost = (t_part + (m / eval_ic) * t_rest) / R
+    lab = (e_cm.cpu().numpy() == egs)
+    return dict(index=i, egs=egs, pumps=pe.tolist(), tts99_ms=t, successes={
+        "plain_f32": s_f32.sum(axis=1).tolist(), "bf16": s_bf.sum(axis=1).tolist(),
+        "bf16_learned": s_pol.sum(axis=1).tolist()},
+        ms_per_attempt={"plain_f32": ms_f32 / R, "bf16": ms_bf / R, "bf16_learned": ms_pol / R,
+                        "bf16_learned_model": model_cost},
+        kept_match_plain=same, auc_within=within_batch_auc(net.logits(f_cm).cpu().numpy(), lab, eval_ic))
+
+
+def experiment(n_train=50, n_val=10, n_test=20, n=200, d=3, n_ic=1000, n_pumps=20, steps=20000, epochs=6, seed=0,
+               frac=0.1, pos_frac=0.1, lr=2e-3, search_steps=20000, val_ic=2500, eval_ic=20000, pilot_ic=1000,
+               log=print):
+    """Generate, train, choose the policy, evaluate; returns a JSON-able
+    report.
+
+    Training instances (n_train x n_pumps x n_ic runs, BF16 form) give the
+    features and labels (final energy == putative ground state).  After
+    every epoch the kept fraction is chosen on the validation instances
+    (val_ic runs per pump) by validation_score with the cost model; the
+    epoch and fraction with the lowest score win, keeping every run (the
+    plain method) always a candidate.  Held-out instances are evaluated by
+    evaluate_instance: the three methods run for real at each instance's
+    best pumps, from the same initial states."""
     t0 = time.time()
-    kw = dict(n=n, d=d, n_ic=n_ic, n_pumps=n_pumps, steps=steps, frac=frac, log=log)
-    train = generate(n_train, precision="bf16", seed_base=0, **kw)
-    kw["n_ic"] = n_ic_eval
-    val = generate(n_val, precision="bf16", seed_base=5_000, **kw)
-    test_bf16 = generate(n_test, precision="bf16", seed_base=10_000, **kw)
-    test_f32 = generate(n_test, precision="f32", seed_base=10_000, **kw)
+    pumps = np.linspace(0.5, 2.0, n_pumps)
+    kw = dict(n=n, d=d, pumps=pumps, steps=steps, frac=frac, log=None)
+    train = generate(range(n_train), n_ic=n_ic, **kw)
+    val = generate(range(5000, 5000 + n_val), n_ic=val_ic, **kw)
 
-    def putative(insts, extra=()):
+    def putative(insts):
         out = []
-        for k, i in enumerate(insts):
+        for i in insts:
             e = int(i["E"].min().item())
-            for o in extra:
-                e = min(e, int(o[k]["E"].min().item()))
             if search_steps:
-                e = min(e, search_egs(i["J"], d=d, steps=search_steps, seed=7 + i["index"]))
+                e = min(e, search_egs(i["Jn"], d=d, steps=search_steps, seed=7 + i["index"]))
             out.append(e)
         return out
 
     egs_train, egs_val = putative(train), putative(val)
-    egs_test = putative(test_bf16, (test_f32,))
     feats = torch.cat([i["feats"] for i in train])
     labels = torch.cat([(i["E"] == g).float() for i, g in zip(train, egs_train)])
+    if log:
+        log(f"data: {feats.shape[0]} training runs, {int(labels.sum().item())} successes, {time.time() - t0:.1f} s")
     net = RestartNet(seed=seed)
-    net.set_scaler(feats)
-    xs = net.standardize(feats)
     t_fit = time.time()
     hist, val_curve = [], []
     base_tts = [instance_tts(i, g) for i, g in zip(val, egs_val)]
     base_val = validation_score(base_tts, base_tts)
     best = (base_val, 1.0, -1, net.state())  # never restart
     for ep in range(epochs):
-        hist += net.fit(xs, labels, epochs=1, lr=lr, pos_frac=pos_frac, seed=seed * 1000 + ep)
+        hist += net.fit(feats, labels, epochs=1, lr=lr, pos_frac=pos_frac, seed=seed * 1000 + ep)
         kf, sc_val = choose_keep(val, egs_val, net)
         val_curve.append(dict(epoch=ep, keep=kf, tts99_val_geomean_ms=sc_val))
         if log:
-            log(f"epoch {ep}: loss {hist[-1]:.4f} val TTS99 (geometric mean) {sc_val:.4f} ms (keep {kf:.3g})")
+            log(f"epoch {ep}: loss {hist[-1]:.4f} val TTS99 (geometric mean) {sc_val:.4f} ms (keep {kf:.3g}), "
+                f"without restarts {base_val:.4f} ms")
         if sc_val < best[0]:
             best = (sc_val, kf, ep, net.state())
     net.load_state(best[3])
     keep = best[1]
     torch.cuda.synchronize()
     t_fit = time.time() - t_fit
-    a_train = auc(torch.sigmoid(net.predict_raw(feats)).cpu().numpy(), labels.cpu().numpy() > 0.5)
-    rows, qs = evaluate(test_f32, test_bf16, egs_test, net, keep)
-    lab = np.concatenate([(i["E"].cpu().numpy() == g) for i, g in zip(test_bf16, egs_test)])
-    a = auc(np.concatenate(qs), lab)
-
-    def med(key):
-        return float(np.median([r[key] for r in rows]))
-
-    upd = sum(i["updates"] for i in test_f32)
-    ms_f32 = sum(i["t_part_ms"] + i["t_rest_ms"] for i in test_f32)
-    ms_bf16 = sum(i["t_part_ms"] + i["t_rest_ms"] for i in test_bf16)
+    val_lab = np.concatenate([(i["E"].cpu().numpy() == g) for i, g in zip(val, egs_val)])
+    val_auc = within_batch_auc(np.concatenate([net.logits(i["feats"]).cpu().numpy() for i in val]), val_lab, val_ic)
+    rows = []
+    for k in range(n_test):
+        row = evaluate_instance(10000 + k, net, keep, n=n, d=d, steps=steps, pilot_ic=pilot_ic, eval_ic=eval_ic,
+                                pumps=pumps, search_steps=search_steps, frac=frac)
+        rows.append(row)
+        if log:
+            log(f"held-out {row['index']}: TTS99 ms " + ", ".join(f"{a} {b:.3g}" for a, b in row["tts99_ms"].items())
+                + f"; successes {row['successes']}")
+    fin = lambda key: [r["tts99_ms"][key] for r in rows]  # noqa: E731
+    solved = {m: [math.isfinite(v) for v in fin(m)] for m in ("plain_f32", "bf16", "bf16_learned")}
+    both = [a and b for a, b in zip(solved["bf16"], solved["bf16_learned"])]
+    ratio, ci = bootstrap_ratio([v for v, ok in zip(fin("bf16_learned"), both) if ok],
+                                [v for v, ok in zip(fin("bf16"), both) if ok])
+    both32 = [a and b for a, b in zip(solved["plain_f32"], solved["bf16_learned"])]
+    ratio_f32, ci_f32 = bootstrap_ratio([v for v, ok in zip(fin("bf16_learned"), both32) if ok],
+                                        [v for v, ok in zip(fin("plain_f32"), both32) if ok], seed=1)
+    cost = {m: float(np.mean([r["ms_per_attempt"][m] for r in rows]))
+            for m in ("plain_f32", "bf16", "bf16_learned", "bf16_learned_model")}
     report = dict(
-        workload=f"SK +-1 N={n}, D={d}, {n_pumps} pumps, {steps} steps, features over the first {frac:.0%} of "
-                 f"steps; {n_train} training instances x {n_ic} initial states per pump, {n_val} validation and "
-                 f"{n_test} held-out instances x {n_ic_eval}",
+        workload=f"SK +-1 N={n}, D={d}, {n_pumps} pumps, {steps} Euler steps, decision after {frac:.0%} of the steps "
+                 f"(8 feature checkpoints); {n_train} training instances x {n_ic} runs per pump, {n_val} validation "
+                 f"instances x {val_ic}; {n_test} held-out instances, each run at its 3 best pumps (pilot of "
+                 f"{pilot_ic} runs per pump) from the same {eval_ic} initial states per pump by every method",
         trajectories_train=int(feats.shape[0]), positives_train=float(labels.mean().item()),
-        positives_heldout_bf16=float(lab.mean()),
-        positives_heldout_f32=float(np.mean(np.concatenate([(i["E"].cpu().numpy() == g)
-                                                            for i, g in zip(test_f32, egs_test)]))),
-        loss_history=hist, validation=val_curve, tts99_val_geomean_without_restart_ms=base_val, chosen_epoch=best[2],
-        train_seconds=t_fit, keep_fraction=keep, auc_train=a_train, auc_heldout=a,
-        tts99_median_ms=dict(plain_f32=med("tts_plain_f32_ms"), bf16=med("tts_bf16_ms"),
-                             bf16_learned=med("tts_bf16_learned_ms")),
-        instances_solved=dict(plain_f32=sum(math.isfinite(r["tts_plain_f32_ms"]) for r in rows),
-                              bf16=sum(math.isfinite(r["tts_bf16_ms"]) for r in rows),
-                              bf16_learned=sum(math.isfinite(r["tts_bf16_learned_ms"]) for r in rows)),
-        updates_per_s=dict(f32=upd / (ms_f32 / 1e3), bf16=upd / (ms_bf16 / 1e3)),
+        loss_history=hist, validation=val_curve, tts99_val_geomean_without_restart_ms=base_val,
+        chosen_epoch=best[2], keep_fraction=keep, train_seconds=t_fit, auc_within_batch_val=val_auc,
+        auc_within_batch_heldout=float(np.nanmean([r["auc_within"] for r in rows])),
+        tts99_median_ms={m: float(np.median(fin(m))) for m in ("plain_f32", "bf16", "bf16_learned")},
+        instances_solved={m: int(sum(v)) for m, v in solved.items()},
+        same_instances_solved=solved["bf16"] == solved["bf16_learned"],
+        learned_over_bf16_geomean=ratio, learned_over_bf16_ci95=ci,
+        learned_over_f32_geomean=ratio_f32, learned_over_f32_ci95=ci_f32,
+        ms_per_attempt=cost, kept_runs_match_plain=all(r["kept_match_plain"] for r in rows),
         per_instance=rows, seconds=time.time() - t0)
     return report
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train", type=int, default=40)
+    ap.add_argument("--train", type=int, default=50)
     ap.add_argument("--val", type=int, default=10)
     ap.add_argument("--test", type=int, default=20)
-    ap.add_argument("--n", type=int, default=100)
+    ap.add_argument("--n", type=int, default=200)
     ap.add_argument("--d", type=int, default=3)
     ap.add_argument("--ics", type=int, default=1000)
     ap.add_argument("--pumps", type=int, default=20)
-    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--frac", type=float, default=0.1)
+    ap.add_argument("--eval-ic", type=int, default=20000)
     ap.add_argument("--search-steps", type=int, default=20000)
     ap.add_argument("--out", type=str, default="")
     a = ap.parse_args()
     rep = experiment(a.train, a.val, a.test, a.n, a.d, a.ics, a.pumps, a.steps, a.epochs, frac=a.frac,
-                     search_steps=a.search_steps)
+                     search_steps=a.search_steps, eval_ic=a.eval_ic)
     s = json.dumps(rep, default=float)
     if a.out:
         with open(a.out, "w") as f:
             f.write(s)
-    print(json.dumps({k: v for k, v in rep.items() if k != "per_instance"}, default=float))
+    print(json.dumps({k: v for k, v in rep.items() if k not in ("per_instance", "loss_history")}, default=float))
 
 
 if __name__ == "__main__":
