@@ -308,7 +308,15 @@ hipError_t launch_integrate_map_persistent(int tiles, int d, int xs, int blocks,
 }
 
 static void (*lds_kernel(const KernelFn &fn, int kind))(const IntegArgs *, const int2 *, int, int *) {
-    return kind == kKernelLdsJ1 ? fn.persistent_lds1 : fn.persistent_lds;
+    return kind == kKernelPipe ? fn.persistent_pipe : kind == kKernelLdsJ1 ? fn.persistent_lds1 : fn.persistent_lds;
+}
+
+static bool uses_lds(int kind) { return kind == kKernelLdsJ || kind == kKernelLdsJ1 || kind == kKernelPipe; }
+
+bool persistent_kind_exists(int tiles, int d, int xs, int js, int kind) {
+    KernelFn fn = lookup(tiles, d, xs, js);
+    if (!fn.persistent) return false;
+    return kind == kKernelPipe ? fn.persistent_pipe != nullptr : true;
 }
 
 static hipError_t prepare_lds(const KernelFn &fn, int kind) {
@@ -321,7 +329,8 @@ hipError_t persistent_occupancy(int tiles, int d, int xs, int js, int kind, int 
     KernelFn fn = lookup(tiles, d, xs, js);
     *blocks_per_cu = 0;
     if (!fn.persistent) return hipErrorInvalidDeviceFunction;
-    if (kind == kKernelLdsJ || kind == kKernelLdsJ1) {
+    if (uses_lds(kind)) {
+        if (!lds_kernel(fn, kind)) return hipErrorInvalidDeviceFunction;
         hipError_t e = prepare_lds(fn, kind);
         if (e != hipSuccess) return e;
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, lds_kernel(fn, kind), 64 * waves_per_block,
@@ -341,7 +350,8 @@ hipError_t launch_integrate_persistent(int tiles, int d, int xs, int js, int kin
                                        hipStream_t stream) {
     KernelFn fn = lookup(tiles, d, xs, js);
     if (!fn.persistent) return hipErrorInvalidDeviceFunction;
-    if (kind == kKernelLdsJ || kind == kKernelLdsJ1) {
+    if (uses_lds(kind)) {
+        if (!lds_kernel(fn, kind)) return hipErrorInvalidDeviceFunction;
         hipError_t e = prepare_lds(fn, kind);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(lds_kernel(fn, kind), dim3(blocks), dim3(64 * waves_per_block), fn.lds_bytes, stream,

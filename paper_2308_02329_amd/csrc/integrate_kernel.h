@@ -457,6 +457,264 @@ void k_integrate_persistent_lds(const IntegArgs *__restrict__ tasks, const int2 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Software-pipelined variant: one wavefront per SIMD, J in the block's LDS.
+//
+// With the products of a step issued back to back and the vector work of
+// the update and the operand split done between steps, a wavefront keeps
+// the matrix cores idle during its vector work; two wavefronts per SIMD
+// only cover for each other when their phases happen to alternate.  Here a
+// single wavefront interleaves the two itself: while chunk c of step k runs
+// on the matrix cores it finishes the update of step k-1 for row tiles
+// 2c+2 and 2c+3 (whose products completed in step k-1) and splits them into
+// the operands of chunk c+1 of step k; in the last chunk, whose products are
+// issued tile by tile, it updates tiles 0 and 1 of step k as soon as their
+// products are complete and splits the next step's chunk 0.  Step k-1's
+// products (being consumed) and step k's (being formed) live in two
+// accumulator sets, and two operand sets alternate; the step loop is
+// unrolled by two so that every choice of set is static.  Each accumulator
+// takes its products in the same order as in every other variant (chunk by
+// chunk, state terms smallest first), and the update is the same arithmetic,
+// so results are bit-identical.
+
+// The Euler update of one row tile (4 rows x D components of the lane's
+// replica) from its products: x <- x (1 + dt (r-1) - dt btil S - dt eta x^2)
+// + dt eps alpha_mu G, written as in integrate_group.
+template <int D>
+__device__ __forceinline__ void pipe_update_tile(float (&xt)[D][4], const f32x4 (&acc)[D], const float (&ga)[D],
+                                                 float base, float nbd, float ned) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        float x2[D];
+#pragma unroll
+        for (int mu = 0; mu < D; ++mu) x2[mu] = xt[mu][v] * xt[mu][v];
+        float S = x2[0];
+#pragma unroll
+        for (int mu = 1; mu < D; ++mu) S = S + x2[mu];
+        const float cc = fmaf(nbd, S, base);
+#pragma unroll
+        for (int mu = 0; mu < D; ++mu) {
+            const float y = xt[mu][v] * fmaf(ned, x2[mu], cc);
+            xt[mu][v] = fmaf(ga[mu], acc[mu][v], y);
+        }
+    }
+}
+
+// Operands of chunk c (row tiles 2c and 2c+1 of the lane's own state).
+template <int NT, int D, int XS>
+__device__ __forceinline__ void pipe_split_chunk(const float (&x)[NT][D][4], int c, XSplit<XS> (&b)[D],
+                                                 const NegPair &negk) {
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+        float v8[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int tile = 2 * c + (s >> 2);
+            v8[s] = (tile < NT) ? x[tile < NT ? tile : 0][mu][s & 3] : 0.0f;
+        }
+        split8<XS>(v8, b[mu], negk);
+    }
+}
+
+// The products of chunk c for every row tile, tile by tile; the chunk-0
+// products start from zero.
+template <int NT, int D, int XS, int JS>
+__device__ __forceinline__ void pipe_products(f32x4 (&acc)[NT][D], const XSplit<XS> (&b)[D], const bf16x8 *jl,
+                                              int c, int lane) {
+    constexpr int NC = (NT + 1) / 2;
+    constexpr int NP = JS == 1 ? XS : 6;
+    constexpr int pj[6] = {JS == 1 ? 0 : 2, JS == 1 ? 0 : 1, 0, JS == 1 ? 0 : 1, 0, 0};
+    constexpr int px[6] = {JS == 1 ? XS - 1 : 0, JS == 1 ? (XS > 1 ? XS - 2 : 0) : 1, JS == 1 ? 0 : 2, 0, 1, 0};
+#pragma unroll
+    for (int I = 0; I < NT; ++I) {
+        bf16x8 af[JS];
+#pragma unroll
+        for (int t = 0; t < JS; ++t) af[t] = jl[((t * NT + I) * NC + c) * 64 + lane];
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+#pragma unroll
+            for (int mu = 0; mu < D; ++mu)
+                acc[I][mu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    af[pj[q]], b[mu].t[px[q]], (c == 0 && q == 0) ? f32x4{0.0f, 0.0f, 0.0f, 0.0f} : acc[I][mu], 0, 0,
+                    0);
+    }
+}
+
+// Asks the scheduler to alternate one matrix-core product with `v` vector
+// instructions, `m` times.
+template <int M, int V>
+__device__ __forceinline__ void pipe_interleave() {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, V, 0);  // V VALU
+    }
+}
+
+// One step of the pipelined loop.  cur receives this step's products; prev
+// holds the previous step's (PREV), whose update is finished here for row
+// tiles 2 .. NT-1; bx[P] holds this step's chunk-0 operands on entry.  NEXT:
+// the last chunk also finishes this step's update of tiles 0 and 1 and
+// splits the next step's chunk 0 into bx[(P + NC) & 1].
+template <int NT, int D, int XS, int JS, int P, bool PREV, bool NEXT>
+__device__ __forceinline__ void pipe_step(float (&x)[NT][D][4], f32x4 (&cur)[NT][D], const f32x4 (&prev)[NT][D],
+                                          XSplit<XS> (&bx)[2][D], const float (&ga_cur)[D], const float (&ga_prev)[D],
+                                          const bf16x8 *jl, int lane, float base, float nbd, float ned,
+                                          const NegPair &negk) {
+    constexpr int NC = (NT + 1) / 2;
+    constexpr int NP = JS == 1 ? XS : 6;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const int bi = (P + c) & 1;
+        pipe_products<NT, D, XS, JS>(cur, bx[bi], jl, c, lane);
+        if (c + 1 < NC) {
+            if constexpr (PREV) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int I = 2 * c + 2 + h;
+                    if (I < NT) pipe_update_tile<D>(x[I < NT ? I : 0], prev[I < NT ? I : 0], ga_prev, base, nbd, ned);
+                }
+            }
+            pipe_split_chunk<NT, D, XS>(x, c + 1, bx[bi ^ 1], negk);
+        } else if constexpr (NEXT) {
+            pipe_update_tile<D>(x[0], cur[0], ga_cur, base, nbd, ned);
+            if (NT > 1) pipe_update_tile<D>(x[NT > 1 ? 1 : 0], cur[NT > 1 ? 1 : 0], ga_cur, base, nbd, ned);
+            pipe_split_chunk<NT, D, XS>(x, 0, bx[bi ^ 1], negk);
+        }
+        pipe_interleave<NT * D * NP, 4>();
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Integrates the 16 replicas rep0 .. rep0+15 of problem a with the pipelined
+// step loop; J fragments are read from the block's LDS copy.
+template <int NT, int D, int XS, int JS>
+__device__ __forceinline__ void integrate_group_pipe(const IntegArgs &a, int rep0, const bf16x8 *jl) {
+    const int n = a.n;
+    const int r = a.r;
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4;
+    const int rep = rep0 + (lane & 15);
+    const bool valid = rep < r;
+
+    float x[NT][D][4];
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int p = 16 * I + 4 * g + v;
+            const bool ok = valid && p < n;
+#pragma unroll
+            for (int mu = 0; mu < D; ++mu) x[I][mu][v] = ok ? a.x[((size_t)p * r + rep) * D + mu] : 0.0f;
+        }
+    const float base = valid ? fmaf(a.dt, a.pump[rep] - 1.0f, 1.0f) : 0.0f;
+    const NegPair negk = neg_pair();
+    const float nbd = -(a.dt * a.btil);
+    const float ned = -(a.dt * a.eta);
+    const float dte = a.dt * a.eps;
+    auto weights = [&](int k, float (&ga)[D]) __attribute__((always_inline)) {
+        const float *al = a.alpha + (size_t)(a.start_step + k) * D;
+#pragma unroll
+        for (int mu = 0; mu < D; ++mu)
+            ga[mu] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(dte * al[mu])));
+    };
+
+    constexpr int NC = (NT + 1) / 2;
+    constexpr int P1 = NC & 1;  // chunk-0 operand set of odd steps
+    const int steps = a.steps;
+    if (steps > 0) {
+        f32x4 accA[NT][D], accB[NT][D];
+        XSplit<XS> bx[2][D];
+        float ga0[D], ga1[D];
+        pipe_split_chunk<NT, D, XS>(x, 0, bx[0], negk);
+        weights(0, ga0);
+        if (steps == 1) {
+            pipe_step<NT, D, XS, JS, 0, false, false>(x, accA, accB, bx, ga0, ga0, jl, lane, base, nbd, ned, negk);
+#pragma unroll
+            for (int I = 0; I < NT; ++I) pipe_update_tile<D>(x[I], accA[I], ga0, base, nbd, ned);
+        } else {
+            pipe_step<NT, D, XS, JS, 0, false, true>(x, accA, accB, bx, ga0, ga0, jl, lane, base, nbd, ned, negk);
+            int k = 1;
+            // pairs of steps (k odd into accB, k + 1 even into accA), each with a successor
+            for (; k + 2 < steps; k += 2) {
+                asm volatile("" ::: "memory");  // J fragments stay in LDS, read again every step
+                weights(k, ga1);
+                pipe_step<NT, D, XS, JS, P1, true, true>(x, accB, accA, bx, ga1, ga0, jl, lane, base, nbd, ned,
+                                                         negk);
+                asm volatile("" ::: "memory");
+                weights(k + 1, ga0);
+                pipe_step<NT, D, XS, JS, 0, true, true>(x, accA, accB, bx, ga0, ga1, jl, lane, base, nbd, ned, negk);
+            }
+            asm volatile("" ::: "memory");
+            weights(k, ga1);
+            if (k + 1 < steps) {  // two steps left: k into accB, k + 1 (the last) into accA
+                pipe_step<NT, D, XS, JS, P1, true, true>(x, accB, accA, bx, ga1, ga0, jl, lane, base, nbd, ned,
+                                                         negk);
+                weights(k + 1, ga0);
+                pipe_step<NT, D, XS, JS, 0, true, false>(x, accA, accB, bx, ga0, ga1, jl, lane, base, nbd, ned,
+                                                         negk);
+#pragma unroll
+                for (int I = 0; I < NT; ++I) pipe_update_tile<D>(x[I], accA[I], ga0, base, nbd, ned);
+            } else {  // one step left: k (the last) into accB
+                pipe_step<NT, D, XS, JS, P1, true, false>(x, accB, accA, bx, ga1, ga0, jl, lane, base, nbd, ned,
+                                                          negk);
+#pragma unroll
+                for (int I = 0; I < NT; ++I) pipe_update_tile<D>(x[I], accB[I], ga1, base, nbd, ned);
+            }
+        }
+    }
+
+    // the store's addresses are formed here from an opaque base, so that
+    // the load's are not kept live through the step loop
+    float *xout = a.x;
+    int rr = r;
+    asm volatile("" : "+s"(xout), "+s"(rr));
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int p = 16 * I + 4 * g + v;
+            if (valid && p < n) {
+#pragma unroll
+                for (int mu = 0; mu < D; ++mu) xout[((size_t)p * rr + rep) * D + mu] = x[I][mu][v];
+            }
+        }
+}
+
+// Many problems of one variant with the pipelined step loop: a block of W
+// wavefronts, one per SIMD, pops work items (problem, slab of 16 W
+// replicas), stages the problem's J fragments in LDS once, and each
+// wavefront integrates its 16 replicas.
+template <int NT, int D, int XS, int JS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
+void k_integrate_persistent_pipe(const IntegArgs *__restrict__ tasks, const int2 *__restrict__ items, int n_items,
+                                 int *__restrict__ counter) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    bf16x8 *jl = reinterpret_cast<bf16x8 *>(smem);
+    __shared__ int s_item;
+    const int waves = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6;
+    for (;;) {
+        __syncthreads();  // the previous item's LDS reads are done
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        if (it >= n_items) break;
+        const int2 w = items[it];
+        const IntegArgs a = tasks[w.x];
+        stage_j<NT, JS>(a, jl);
+        __syncthreads();
+        const int rep0 = (w.y * waves + wave) * 16;
+        if (rep0 < a.r) integrate_group_pipe<NT, D, XS, JS>(a, rep0, jl);
+    }
+}
+
+// Shapes the pipelined variant is built for: two accumulator sets, two
+// operand sets and the state within one wavefront's 512 registers.
+constexpr bool pipe_supported(int nt, int d, int xs, int js) {
+    return js == 1 && (d == 2 || d == 3) && nt >= 2 && nt <= 7 && xs >= 1;
+}
+
 template <int NT, int JS>
 constexpr size_t lds_j_bytes() {
     return (size_t)JS * NT * ((NT + 1) / 2) * 64 * sizeof(bf16x8);
@@ -470,6 +728,7 @@ struct KernelSet {
     size_t lds_bytes;
     void (*single_map)(IntegArgs);  // round-trip map form (single coupling term only)
     void (*persistent_map)(const IntegArgs *, const int2 *, int, int *);  // same, many problems
+    void (*persistent_pipe)(const IntegArgs *, const int2 *, int, int *);  // pipelined, one wavefront per SIMD
 };
 
 // Largest row-tile count per (d, xs, js) that compiles without scratch
@@ -483,13 +742,20 @@ constexpr int resident_max_tiles(int d, int xs, int js) {
 }
 
 template <int NT, int D, int XS, int JS>
+constexpr void (*pipe_fn())(const IntegArgs *, const int2 *, int, int *) {
+    if constexpr (pipe_supported(NT, D, XS, JS)) return k_integrate_persistent_pipe<NT, D, XS, JS>;
+    else return nullptr;
+}
+
+template <int NT, int D, int XS, int JS>
 KernelSet variant_or_null() {
     if constexpr (NT <= resident_max_tiles(D, XS, JS))
         return KernelSet{k_integrate_resident<NT, D, XS, JS>, k_integrate_persistent<NT, D, XS, JS>,
                          k_integrate_persistent_lds<NT, D, XS, JS, 2>, k_integrate_persistent_lds<NT, D, XS, JS, 1>,
                          lds_j_bytes<NT, JS>(),
                          (JS == 1 && NT <= kMapMaxTiles) ? k_integrate_resident<NT, D, XS, JS, true> : nullptr,
-                         (JS == 1 && NT <= kMapMaxTiles) ? k_integrate_persistent<NT, D, XS, JS, true> : nullptr};
+                         (JS == 1 && NT <= kMapMaxTiles) ? k_integrate_persistent<NT, D, XS, JS, true> : nullptr,
+                         pipe_fn<NT, D, XS, JS>()};
     else
         return KernelSet{nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr};
 }

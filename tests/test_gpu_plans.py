@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from paper_2308_02329_amd import api
+from paper_2308_02329_amd import api, synth
 
 torch = pytest.importorskip("torch")
 from gpu_helpers import Case, to_dev  # noqa: E402
@@ -72,9 +72,52 @@ def test_lds_plan_matches_register_plan_bit_exact(n, d, prec, kernel, waves):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("n,d,prec", [(100, 3, "f32"), (100, 2, "f32"), (100, 3, "bf16"), (80, 3, "f32"),
+                                      (40, 2, "bf16"), (20, 3, "f32")])
+def test_pipelined_plan_matches_register_plan_bit_exact(n, d, prec):
+    """The software-pipelined kind gives the register-resident kind's results
+    bit for bit: every tail of its two-step loop (1, 2, 3 and 4 steps, odd
+    and even longer runs), even and odd chunk counts (n = 80: three chunks),
+    ragged replica counts, and start steps inside the annealing ramp."""
+    specs = [(n, d, 70, 151), (n, d, 33, 150), (n, d, 16, 1), (n, d, 17, 2), (n, d, 20, 3), (n, d, 64, 4)]
+    cases = [Case(nn, dd, r, max(s, 1), key=(31, i)) for i, (nn, dd, r, s) in enumerate(specs)]
+
+    def run(start):
+        tasks = []
+        for c, (_, _, r, s) in zip(cases, specs):
+            Jd, pump, x, _ = c.gpu_inputs()
+            al = to_dev(synth.anneal_schedule(400, d)[0])  # start steps inside the ramp (0.4 .. 0.8 of 400)
+            tasks.append(dict(J=Jd, pump=pump, x=x, alpha=al, steps=s, start_step=start, precision=prec,
+                              **c.params()))
+        b = api.chym_batch_create(tasks)
+        b.launch()
+        torch.cuda.synchronize()
+        b.destroy()
+        return [t["x"].cpu().numpy() for t in tasks]
+
+    for start in (0, 157):
+        api.chym_plan_set(n, d, prec, torch.int8, api.CHYM_KERNEL_REGJ, 4)
+        ref = run(start)
+        api.chym_plan_set(n, d, prec, torch.int8, api.CHYM_KERNEL_PIPE, 4)
+        assert api.chym_plan_get(n, d, prec, torch.int8)["kernel"] == api.CHYM_KERNEL_PIPE
+        got = run(start)
+        api.chym_plan_set(n, d, prec, torch.int8, api.CHYM_KERNEL_AUTO, 4)
+        for a, b, sp in zip(ref, got, specs):
+            assert np.array_equal(a, b), (sp, start)
+
+
+def test_pipelined_plan_refused_where_not_built():
+    with pytest.raises(api.ChymError) as ei:
+        api.chym_plan_set(100, 4, "f32", torch.int8, api.CHYM_KERNEL_PIPE, 4)
+    assert ei.value.code == -2
+    with pytest.raises(api.ChymError):
+        api.chym_plan_set(100, 3, "f32", torch.float32, api.CHYM_KERNEL_PIPE, 4)  # three coupling terms
+
+
 def test_autotune_installs_a_candidate(tmp_path):
     best, cands = api.chym_plan_autotune(48, 2, "f32", torch.int8, replicas=4096, steps=50)
-    assert len(cands) == 4 and all(c["ms"] > 0 for c in cands)
+    assert len(cands) == 5 and all(c["ms"] > 0 for c in cands)  # the pipelined kind is built for this shape
+    assert api.CHYM_KERNEL_PIPE in [c["kernel"] for c in cands]
     assert best["ms"] == min(c["ms"] for c in cands)
     assert api.chym_plan_get(48, 2, "f32", torch.int8)["kernel"] == best["kernel"]
     path = tmp_path / "plans.txt"
