@@ -38,7 +38,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "chym_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# CHYM_SANITIZED_LIBS=1: an AddressSanitizer + UndefinedBehaviorSanitizer build
+# (clang, so that it shares the ASan runtime of the library's sanitized build)
+_SANITIZE = os.environ.get("CHYM_SANITIZED_LIBS") == "1"
+_LIB = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
 _lib = None
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -47,11 +50,18 @@ _u8p = ctypes.POINTER(ctypes.c_uint8)
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, no FP contraction, OpenMP)."""
+    """Compile the oracle with gcc (-O2, no FP contraction, OpenMP); with
+    CHYM_SANITIZED_LIBS=1, with clang and the address and undefined-behaviour
+    sanitizers instead."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+        if _SANITIZE:
+            cmd = ["/opt/rocm/lib/llvm/bin/clang", "-O1", "-g", "-std=c11", "-ffp-contract=off", "-fopenmp",
+                   "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+                   "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+        else:
+            cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                   "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB

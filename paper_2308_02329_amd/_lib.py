@@ -5,7 +5,8 @@ import ctypes
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libchym.so")
+# CHYM_SANITIZED_LIBS=1: the host-sanitized build (python -m paper_2308_02329_amd.build --sanitize)
+LIB_PATH = os.path.join(PKG, "libchym_san.so" if os.environ.get("CHYM_SANITIZED_LIBS") == "1" else "libchym.so")
 
 CHYM_OK = 0
 CHYM_EINVAL = -1
