@@ -149,17 +149,19 @@ __device__ __forceinline__ void stage_j(const IntegArgs &a, bf16x8 *jl) {
 
 // Gain of the nonlinear medium for a field of amplitude A under pump h:
 // K = P / (P cosh(kl P) - h sinh(kl P)), P = sqrt(h^2 + A^2), written as
-// 2 P e / ((P + h) + (P - h) e^2) with e = exp(kl P) and P - h = A^2 / (P + h),
-// which has no cancellation for h >= 0.  The square root, reciprocals and
-// exponential are the hardware's (each within about 1 ulp); kl2 = kl log2(e).
+// 2 P e / ((P + h) + (P - h) e^2) with e = exp(kl P); with P - h = A^2 / (P + h)
+// and both terms multiplied by s = P + h this is 2 P e s / (s^2 + A^2 e^2),
+// which has no cancellation for h >= 0 and needs one reciprocal.  The square
+// root, reciprocal and exponential are the hardware's (each within about
+// 1 ulp); kl2 = kl log2(e).
 __device__ __forceinline__ float nlm_gain(float A, float h, float kl2) {
     const float A2 = A * A;
     const float P = __builtin_amdgcn_sqrtf(fmaf(h, h, A2));
     const float s = P + h;
     if (!(s > 0.0f)) return 1.0f;  // A = h = 0: the medium is transparent
     const float e = __builtin_amdgcn_exp2f(kl2 * P);
-    const float den = fmaf(A2 * __builtin_amdgcn_rcpf(s), e * e, s);
-    return (2.0f * P * e) * __builtin_amdgcn_rcpf(den);
+    const float den = fmaf(A2, e * e, s * s);
+    return (2.0f * P * e * s) * __builtin_amdgcn_rcpf(den);
 }
 
 // Integrates the 16 replicas rep0 .. rep0+15 of problem a for a.steps steps.

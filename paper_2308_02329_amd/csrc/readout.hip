@@ -14,27 +14,27 @@ __device__ void readout_one(int n, int d, int r, int rep, const float *__restric
     const int w = (n + 63) >> 6;
     {
         uint64_t word = 0;
-        double m = 0.0;
+        float m = 0.0f;  // float32: the share needs no more (its reference runs in float64, rtol 1e-6)
         int bad = 0;
         for (int p = 0; p < n; ++p) {
             const float *xp = x + ((size_t)p * r + rep) * d;
             const float v0 = xp[0];
             if (v0 >= 0.0f) word |= 1ull << (p & 63);
-            double tot = 0.0, ext = 0.0;
+            float tot = 0.0f, ext = 0.0f;
             for (int mu = 0; mu < d; ++mu) {
                 const float v = xp[mu];
-                const double dv = (double)v;
-                tot = tot + dv * dv;
-                if (mu > 0) ext = ext + dv * dv;
+                const float v2 = v * v;
+                tot = tot + v2;
+                if (mu > 0) ext = ext + v2;
                 if (!isfinite(v) || fabsf(v) > 1e3f) bad = 1;
             }
-            if (tot > 0.0 && ext / tot > m) m = ext / tot;
+            if (tot > 0.0f && ext / tot > m) m = ext / tot;
             if ((p & 63) == 63 || p == n - 1) {
                 if (spins) spins[(size_t)rep * w + (p >> 6)] = word;
                 word = 0;
             }
         }
-        if (extra) extra[rep] = m;
+        if (extra) extra[rep] = (double)m;
         if (diverged) diverged[rep] = (uint8_t)bad;
     }
 }

@@ -6,8 +6,9 @@ Tolerances:
   float32, so the per-step error is a few float32 ulps of O(1) amplitudes;
   the dissipative dynamics keep the accumulated error well inside 1e-4 over
   the run lengths tested (measured ~7e-5 over 2000 steps).
-* readout, Ising energy (integer J), extra-component share, divergence flag:
-  bit-exact when both sides read the same final state.
+* readout, Ising energy (integer J), divergence flag: bit-exact when both
+  sides read the same final state; extra-component share (float32 on the
+  GPU, float64 in the oracle): relative 1e-6.
 * hyperspin energy (float64 on both sides, different summation order):
   relative 1e-12.
 """
@@ -62,7 +63,7 @@ def test_n16_d2_640_runs_trajectory_and_scores():
     E = oracle.ising_energy(case.J, sig)
     np.testing.assert_array_equal(e32.cpu().numpy(), E.astype(np.int32))
     np.testing.assert_array_equal(e64.cpu().numpy(), E)
-    np.testing.assert_array_equal(extra.cpu().numpy(), oracle.extra_frac(xg))
+    np.testing.assert_allclose(extra.cpu().numpy(), oracle.extra_frac(xg), rtol=1e-6, atol=0)
     np.testing.assert_array_equal(div.cpu().numpy(), oracle.diverged(xg))
     # and the two trajectories read out the same spins on every run
     assert np.array_equal(sig, oracle.readout(xo))
@@ -171,7 +172,7 @@ def test_readout_and_energy_edge_values_bit_exact():
     api.chym_readout(xd, spins, extra, div)
     sig = oracle.readout(x)
     np.testing.assert_array_equal(spins.cpu().numpy(), pack_spins(sig))
-    np.testing.assert_array_equal(extra.cpu().numpy(), oracle.extra_frac(x))
+    np.testing.assert_allclose(extra.cpu().numpy(), oracle.extra_frac(x), rtol=1e-6, atol=0)
     np.testing.assert_array_equal(div.cpu().numpy(), oracle.diverged(x))
     for J in (synth.sk_pm1(n, 18, 0), (synth.sk_pm1(n, 18, 1) * np.int8(7))):
         e32 = torch.empty(r, dtype=torch.int32, device="cuda")
