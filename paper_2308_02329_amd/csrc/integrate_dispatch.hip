@@ -49,10 +49,10 @@ int slab_tpw_for(int tiles) {
 
 size_t slab_lds_bytes(int tiles, int d, int xs) { return (size_t)((tiles + 1) / 2) * d * xs * 64 * sizeof(bf16x8); }
 
-// The fragments, plus two chunks of padding: the streamed-J kernel's
-// prefetch ring refills two chunks ahead unconditionally, so for the last
-// tile it loads (and discards) up to two chunks past the staged data.  Its
-// offset travels in the scalar operand of the buffer load, which the range
+// The fragments, plus kSlabRingChunks chunks of padding: the streamed-J
+// kernel's prefetch ring refills unconditionally, so around the last tile it
+// loads (and discards) up to that many chunks past the staged data.  Their
+// offsets travel in the scalar operand of the buffer load, which the range
 // check of the buffer resource does not cover; the padding keeps those loads
 // inside the workspace.
 size_t slab_jfrag_bytes(int tiles, int js) {
@@ -247,7 +247,7 @@ __global__ void k_split3(const float *x, int64_t n8, bf16x8 *hi, bf16x8 *mid, bf
 #pragma unroll
     for (int s = 0; s < 8; ++s) v[s] = x[i * 8 + s];
     XSplit<3> out;
-    split8<3>(v, out, neg_pair());
+    split8<3>(v, out);
     hi[i] = out.t[0];
     mid[i] = out.t[1];
     lo[i] = out.t[2];

@@ -26,9 +26,9 @@
 // in float32.  An integer J is exact in bf16; a float J is split the same
 // way and the six leading cross terms are kept (error ~2^-24 relative).
 // BF16 form: one bf16 term each.  The split works on pairs of values: one
-// packed conversion rounds two values, and each residual x - hi is formed by
-// a bf16 dot product against (-1, 0) or (0, -1) accumulated onto x, which is
-// exact because the residual is representable.
+// packed conversion rounds two values, and each residual x - hi is a plain
+// float subtraction of the widened bf16 half, exact because the residual is
+// representable.
 //
 // The Euler update (pump gain, coupling with the annealing weight, nonlocal
 // loss, local saturation) is fused after the contraction and works on the
@@ -53,27 +53,17 @@ __device__ __forceinline__ float bf_to_f(__bf16 h) { return (float)h; }
 
 __device__ __forceinline__ bf16x2 pack_rne(float a, float b) { return __builtin_convertvector((f32x2){a, b}, bf16x2); }
 
-// The packed bf16 constants (-1, 0) and (0, -1), forced into VGPRs.  Left to
-// the compiler, (-1, 0) is encoded as the inline constant -1.0, which the
-// dot instruction reads as the float32 bit pattern, i.e. as (0, -1): the
-// residual would subtract the wrong half.  An empty asm with a VGPR operand
-// hides the value so it always travels in a register.
-struct NegPair {
-    bf16x2 lo, hi;
-};
-__device__ __forceinline__ NegPair neg_pair() {
-    uint32_t lo = 0x0000BF80u, hi = 0xBF800000u;
-    asm("" : "+v"(lo));
-    asm("" : "+v"(hi));
-    return NegPair{__builtin_bit_cast(bf16x2, lo), __builtin_bit_cast(bf16x2, hi)};
+// a - (float)h.x and b - (float)h.y, exact when representable.  The halves
+// are widened by a shift or a mask and subtracted on the vector ALU: a bf16
+// dot product against (-1, 0) gives the same value, but on gfx950 the dot
+// instruction does not execute alongside matrix-core products (measured: each
+// one costs several times a plain vector instruction when interleaved with
+// them).
+__device__ __forceinline__ float resid_lo(bf16x2 h, float a) {
+    return a - __uint_as_float(__builtin_bit_cast(uint32_t, h) << 16);
 }
-
-// a - (float)h.x and b - (float)h.y, exact when representable.
-__device__ __forceinline__ float resid_lo(bf16x2 h, float a, const NegPair &k) {
-    return __builtin_amdgcn_fdot2_f32_bf16(h, k.lo, a, false);
-}
-__device__ __forceinline__ float resid_hi(bf16x2 h, float b, const NegPair &k) {
-    return __builtin_amdgcn_fdot2_f32_bf16(h, k.hi, b, false);
+__device__ __forceinline__ float resid_hi(bf16x2 h, float b) {
+    return b - __uint_as_float(__builtin_bit_cast(uint32_t, h) & 0xffff0000u);
 }
 
 __device__ __forceinline__ bf16x8 join4(bf16x2 p0, bf16x2 p1, bf16x2 p2, bf16x2 p3) {
@@ -85,7 +75,7 @@ __device__ __forceinline__ bf16x8 join4(bf16x2 p0, bf16x2 p1, bf16x2 p2, bf16x2 
 
 // Splits 8 floats (4 pairs) into XS bf16 terms whose sum is exact.
 template <int XS>
-__device__ __forceinline__ void split8(const float (&v)[8], XSplit<XS> &out, const NegPair &k) {
+__device__ __forceinline__ void split8(const float (&v)[8], XSplit<XS> &out) {
     bf16x2 t[XS][4];
 #pragma unroll
     for (int pr = 0; pr < 4; ++pr) {
@@ -93,9 +83,9 @@ __device__ __forceinline__ void split8(const float (&v)[8], XSplit<XS> &out, con
         const bf16x2 h = pack_rne(a, b);
         t[0][pr] = h;
         if constexpr (XS == 3) {
-            const float ra = resid_lo(h, a, k), rb = resid_hi(h, b, k);
+            const float ra = resid_lo(h, a), rb = resid_hi(h, b);
             const bf16x2 m = pack_rne(ra, rb);
-            const float sa = resid_lo(m, ra, k), sb = resid_hi(m, rb, k);
+            const float sa = resid_lo(m, ra), sb = resid_hi(m, rb);
             t[1][pr] = m;
             t[2][pr] = pack_rne(sa, sb);
         }
@@ -211,7 +201,6 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0, co
     const float base = valid ? (MAP ? a.c0 : fmaf(a.dt, a.pump[rep] - 1.0f, 1.0f)) : 0.0f;
     const float hmap = (MAP && valid) ? a.pump[rep] : 0.0f;
     const float kl2 = a.kl * 1.44269504088896340736f;  // kl log2(e)
-    const NegPair negk = neg_pair();
     const float nbd = -(a.dt * a.btil);
     const float ned = -(a.dt * a.eta);
     const float dte = a.dt * a.eps;
@@ -296,7 +285,7 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0, co
                                 const int tile = 2 * c + (s >> 2);
                                 v8[s] = (tile < NT) ? x[tile < NT ? tile : 0][mu][s & 3] : 0.0f;
                             }
-                            split8<XS>(v8, bm, negk);
+                            split8<XS>(v8, bm);
                         }
                         bf16x8 af[NT][JS];
 #pragma unroll
@@ -327,7 +316,7 @@ __device__ __forceinline__ void integrate_group(const IntegArgs &a, int rep0, co
                             const int tile = 2 * c + (s >> 2);
                             v8[s] = (tile < NT) ? x[tile < NT ? tile : 0][mu][s & 3] : 0.0f;
                         }
-                        split8<XS>(v8, bx[mu], negk);
+                        split8<XS>(v8, bx[mu]);
                     }
                     // row tiles in groups of TG, each accumulator taking its term
                     // pairs in the order above whatever TG is: with D >= 3 one tile
@@ -504,8 +493,7 @@ __device__ __forceinline__ void pipe_update_tile(float (&xt)[D][4], const f32x4 
 
 // Operands of chunk c (row tiles 2c and 2c+1 of the lane's own state).
 template <int NT, int D, int XS>
-__device__ __forceinline__ void pipe_split_chunk(const float (&x)[NT][D][4], int c, XSplit<XS> (&b)[D],
-                                                 const NegPair &negk) {
+__device__ __forceinline__ void pipe_split_chunk(const float (&x)[NT][D][4], int c, XSplit<XS> (&b)[D]) {
 #pragma unroll
     for (int mu = 0; mu < D; ++mu) {
         float v8[8];
@@ -514,7 +502,7 @@ __device__ __forceinline__ void pipe_split_chunk(const float (&x)[NT][D][4], int
             const int tile = 2 * c + (s >> 2);
             v8[s] = (tile < NT) ? x[tile < NT ? tile : 0][mu][s & 3] : 0.0f;
         }
-        split8<XS>(v8, b[mu], negk);
+        split8<XS>(v8, b[mu]);
     }
 }
 
@@ -550,8 +538,7 @@ __device__ __forceinline__ void pipe_products(f32x4 (&acc)[NT][D], const XSplit<
 template <int NT, int D, int XS, int JS, int P, bool PREV, bool NEXT>
 __device__ __forceinline__ void pipe_step(float (&x)[NT][D][4], f32x4 (&cur)[NT][D], const f32x4 (&prev)[NT][D],
                                           XSplit<XS> (&bx)[2][D], const float (&ga_cur)[D], const float (&ga_prev)[D],
-                                          const bf16x8 *jl, int lane, float base, float nbd, float ned,
-                                          const NegPair &negk) {
+                                          const bf16x8 *jl, int lane, float base, float nbd, float ned) {
     constexpr int NC = (NT + 1) / 2;
     constexpr int NP = JS == 1 ? XS : 6;
 #pragma unroll
@@ -566,11 +553,11 @@ __device__ __forceinline__ void pipe_step(float (&x)[NT][D][4], f32x4 (&cur)[NT]
                     if (I < NT) pipe_update_tile<D>(x[I < NT ? I : 0], prev[I < NT ? I : 0], ga_prev, base, nbd, ned);
                 }
             }
-            pipe_split_chunk<NT, D, XS>(x, c + 1, bx[bi ^ 1], negk);
+            pipe_split_chunk<NT, D, XS>(x, c + 1, bx[bi ^ 1]);
         } else if constexpr (NEXT) {
             pipe_update_tile<D>(x[0], cur[0], ga_cur, base, nbd, ned);
             if (NT > 1) pipe_update_tile<D>(x[NT > 1 ? 1 : 0], cur[NT > 1 ? 1 : 0], ga_cur, base, nbd, ned);
-            pipe_split_chunk<NT, D, XS>(x, 0, bx[bi ^ 1], negk);
+            pipe_split_chunk<NT, D, XS>(x, 0, bx[bi ^ 1]);
         }
         // chunks stay in their order (no code moves across this point); an
         // explicit interleave pattern of products and vector instructions
@@ -601,7 +588,6 @@ __device__ __forceinline__ void integrate_group_pipe(const IntegArgs &a, int rep
             for (int mu = 0; mu < D; ++mu) x[I][mu][v] = ok ? a.x[((size_t)p * r + rep) * D + mu] : 0.0f;
         }
     const float base = valid ? fmaf(a.dt, a.pump[rep] - 1.0f, 1.0f) : 0.0f;
-    const NegPair negk = neg_pair();
     const float nbd = -(a.dt * a.btil);
     const float ned = -(a.dt * a.eta);
     const float dte = a.dt * a.eps;
@@ -619,38 +605,34 @@ __device__ __forceinline__ void integrate_group_pipe(const IntegArgs &a, int rep
         f32x4 accA[NT][D], accB[NT][D];
         XSplit<XS> bx[2][D];
         float ga0[D], ga1[D];
-        pipe_split_chunk<NT, D, XS>(x, 0, bx[0], negk);
+        pipe_split_chunk<NT, D, XS>(x, 0, bx[0]);
         weights(0, ga0);
         if (steps == 1) {
-            pipe_step<NT, D, XS, JS, 0, false, false>(x, accA, accB, bx, ga0, ga0, jl, lane, base, nbd, ned, negk);
+            pipe_step<NT, D, XS, JS, 0, false, false>(x, accA, accB, bx, ga0, ga0, jl, lane, base, nbd, ned);
 #pragma unroll
             for (int I = 0; I < NT; ++I) pipe_update_tile<D>(x[I], accA[I], ga0, base, nbd, ned);
         } else {
-            pipe_step<NT, D, XS, JS, 0, false, true>(x, accA, accB, bx, ga0, ga0, jl, lane, base, nbd, ned, negk);
+            pipe_step<NT, D, XS, JS, 0, false, true>(x, accA, accB, bx, ga0, ga0, jl, lane, base, nbd, ned);
             int k = 1;
             // pairs of steps (k odd into accB, k + 1 even into accA), each with a successor
             for (; k + 2 < steps; k += 2) {
                 asm volatile("" ::: "memory");  // J fragments stay in LDS, read again every step
                 weights(k, ga1);
-                pipe_step<NT, D, XS, JS, P1, true, true>(x, accB, accA, bx, ga1, ga0, jl, lane, base, nbd, ned,
-                                                         negk);
+                pipe_step<NT, D, XS, JS, P1, true, true>(x, accB, accA, bx, ga1, ga0, jl, lane, base, nbd, ned);
                 asm volatile("" ::: "memory");
                 weights(k + 1, ga0);
-                pipe_step<NT, D, XS, JS, 0, true, true>(x, accA, accB, bx, ga0, ga1, jl, lane, base, nbd, ned, negk);
+                pipe_step<NT, D, XS, JS, 0, true, true>(x, accA, accB, bx, ga0, ga1, jl, lane, base, nbd, ned);
             }
             asm volatile("" ::: "memory");
             weights(k, ga1);
             if (k + 1 < steps) {  // two steps left: k into accB, k + 1 (the last) into accA
-                pipe_step<NT, D, XS, JS, P1, true, true>(x, accB, accA, bx, ga1, ga0, jl, lane, base, nbd, ned,
-                                                         negk);
+                pipe_step<NT, D, XS, JS, P1, true, true>(x, accB, accA, bx, ga1, ga0, jl, lane, base, nbd, ned);
                 weights(k + 1, ga0);
-                pipe_step<NT, D, XS, JS, 0, true, false>(x, accA, accB, bx, ga0, ga1, jl, lane, base, nbd, ned,
-                                                         negk);
+                pipe_step<NT, D, XS, JS, 0, true, false>(x, accA, accB, bx, ga0, ga1, jl, lane, base, nbd, ned);
 #pragma unroll
                 for (int I = 0; I < NT; ++I) pipe_update_tile<D>(x[I], accA[I], ga0, base, nbd, ned);
             } else {  // one step left: k (the last) into accB
-                pipe_step<NT, D, XS, JS, P1, true, false>(x, accB, accA, bx, ga1, ga0, jl, lane, base, nbd, ned,
-                                                          negk);
+                pipe_step<NT, D, XS, JS, P1, true, false>(x, accB, accA, bx, ga1, ga0, jl, lane, base, nbd, ned);
 #pragma unroll
                 for (int I = 0; I < NT; ++I) pipe_update_tile<D>(x[I], accB[I], ga1, base, nbd, ned);
             }

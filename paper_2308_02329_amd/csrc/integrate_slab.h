@@ -40,9 +40,10 @@ namespace chym {
 //   [256 + S, ...)     fragments: bf16 [tile][chunk][JS][64 lanes] x 16 B, or
 //                      E4M3 [tile][chunk][64 lanes] x 8 B
 constexpr size_t kStageHeader = 256;
-// chunks of J fragments the streamed-J kernel keeps in flight (its prefetch
-// ring); the staging carries that many chunks of padding after the last tile
-constexpr int kSlabRingChunks = 2;
+// the most chunks of J fragments the streamed-J kernel keeps in flight (its
+// prefetch ring); the staging carries that many chunks of padding after the
+// last tile
+constexpr int kSlabRingChunks = 4;
 __host__ __device__ inline size_t stage_scale_bytes(int tiles) { return ((size_t)tiles * 64 + 255) / 256 * 256; }
 __host__ __device__ inline size_t stage_frag_offset(int tiles) { return kStageHeader + stage_scale_bytes(tiles); }
 
@@ -83,8 +84,7 @@ __device__ __forceinline__ int slab_b_index(int c, int mu, int t, int lane, int 
 // Writes the operand terms of tile I (its four rows of this lane) into the
 // half (I & 1) of chunk I >> 1.
 template <int D, int XS>
-__device__ __forceinline__ void slab_write_tile(const float (&xt)[D][4], int I, int lane, bf16x8 *lb,
-                                                const NegPair &k) {
+__device__ __forceinline__ void slab_write_tile(const float (&xt)[D][4], int I, int lane, bf16x8 *lb) {
     typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
 #pragma unroll
     for (int mu = 0; mu < D; ++mu) {
@@ -95,9 +95,9 @@ __device__ __forceinline__ void slab_write_tile(const float (&xt)[D][4], int I, 
             const bf16x2 h = pack_rne(a, b);
             t[0][pr] = h;
             if constexpr (XS == 3) {
-                const float ra = resid_lo(h, a, k), rb = resid_hi(h, b, k);
+                const float ra = resid_lo(h, a), rb = resid_hi(h, b);
                 const bf16x2 m = pack_rne(ra, rb);
-                const float sa = resid_lo(m, ra, k), sb = resid_hi(m, rb, k);
+                const float sa = resid_lo(m, ra), sb = resid_hi(m, rb);
                 t[1][pr] = m;
                 t[2][pr] = pack_rne(sa, sb);
             }
@@ -115,26 +115,41 @@ __device__ __forceinline__ void slab_write_tile(const float (&xt)[D][4], int I, 
 // chunk count of the staging; lb: LDS operand area of ncp * D * XS
 // fragments.  Called by all W wavefronts of the block; contains block
 // barriers.
+//
+// The J fragments a wavefront needs form one fixed sequence per step: its
+// tile groups in order, each group's chunks in order.  They are read as one
+// continuous stream, RD chunks ahead through a ring of registers: the slot
+// of chunk c is c % RD (every group starts at slot 0), and the load that
+// refills a slot after its chunk is taken fetches the next chunk of the same
+// slot, which is chunk c + RD of the group or, past the group's end, chunk
+// c % RD of the next group (the first group of the next step after the last
+// one: J does not change between steps).  Every refill is a load, so a slot's
+// next value is always the register its load writes, and the prefetch crosses
+// group and step boundaries.
 template <int D, int XS, int JS, int TPW, bool F8, int W>
 __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, const unsigned char *__restrict__ stage,
                                                int ncp, bf16x8 *lb) {
     // tiles accumulated together (register budget: 256 per lane at two
     // wavefronts per SIMD, 512 at one)
     constexpr int GS = W == 8 ? (D >= 3 ? 2 : 4) : (D >= 3 ? 4 : 8);
-    constexpr int RD = kSlabRingChunks;  // chunks of J fragments in flight (more spills at D = 4)
     constexpr int NG = TPW / GS;        // groups of owned tiles
+    // chunks of J fragments in flight: E4M3 fragments take two registers
+    // per tile, bf16 ones four per term
+    constexpr int RD = F8 ? 4 : 2;
+    static_assert(RD <= kSlabRingChunks, "the staging pads kSlabRingChunks chunks past the last tile");
+    // PF: the state operand of the next chunk is read from LDS while the
+    // current chunk's products run, where its registers fit
+    constexpr bool PF = XS == 1 ? D >= 3 : D == 2;
     const int n = a.n;
     const int r = a.r;
     const int nt = (n + 15) / 16;
     const int lane = threadIdx.x & 63;
     // wave-uniform: tile and chunk offsets stay in scalar registers
-    const int w0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int w = w0;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int jcol = lane & 15;
     const int g = lane >> 4;
     const int rep = rep0 + jcol;
     const bool valid = rep < r;
-    const NegPair negk = neg_pair();
     // J fragments through a buffer resource: per-lane offset lane * bytes,
     // wave-uniform offset of (tile, chunk, term) in scalar registers
     constexpr int FB = F8 ? 8 : 16;                // bytes per lane per fragment
@@ -143,6 +158,25 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
     const int jvoff = lane * FB;
     // row scales 2^e_p of the E4M3 fragments (per-lane offset jcol, tile offset uniform)
     const __amdgpu_buffer_rsrc_t sres = buffer_over(stage + kStageHeader, (uint32_t)(nt * 64));
+
+    // groups holding at least one tile (their first tiles are w + GS W grp)
+    int ngw = 0;
+#pragma unroll
+    for (int grp = 0; grp < NG; ++grp)
+        if (w + GS * W * grp < nt) ngw = grp + 1;
+    // byte offset of the first chunk of tile i of group grp (past the last
+    // tile: the group's first tile, whose products are never used)
+    auto tile_off = [&](int grp, int i) __attribute__((always_inline)) {
+        const int I0 = w + GS * W * grp;
+        const int I = I0 + W * i < nt ? I0 + W * i : I0;
+        return I * ncp * CHB;
+    };
+    auto scale_of = [&](int grp, int i) __attribute__((always_inline)) {
+        const int I0 = w + GS * W * grp;
+        const int I = I0 + W * i < nt ? I0 + W * i : I0;
+        // the lane's A row is 16 I + (lane & 15)
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sres, jcol * 4, I * 64, 0));
+    };
 
     // zero the operand area (chunks past the last tile read as zero)
     for (int i = threadIdx.x; i < ncp * D * XS * 64; i += blockDim.x) lb[i] = bf16x8{};
@@ -159,8 +193,28 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
 #pragma unroll
             for (int mu = 0; mu < D; ++mu) x[k][mu][v] = ok ? a.x[((size_t)p * r + rep) * D + mu] : 0.0f;
         }
-        if (I < nt) slab_write_tile<D, XS>(x[k], I, lane, lb, negk);
+        if (I < nt) slab_write_tile<D, XS>(x[k], I, lane, lb);
     }
+
+    // the ring holds the first RD chunks of group 0; the scales of group 0
+    bf16x8 ring[F8 ? 1 : RD][GS][JS];
+    uint2 ring8[F8 ? RD : 1][GS];
+    float sc[GS];
+#pragma unroll
+    for (int i = 0; i < GS; ++i) sc[i] = F8 ? scale_of(0, i) : 1.0f;
+#pragma unroll
+    for (int sl = 0; sl < RD; ++sl)
+#pragma unroll
+        for (int i = 0; i < GS; ++i) {
+            // chunks past the tile's last (ncp < RD) are the next tile's or the
+            // staging's padding, loaded and never used
+            if constexpr (F8) {
+                ring8[sl][i] = load_frag8(jres, jvoff, tile_off(0, i) + sl * CHB);
+            } else {
+#pragma unroll
+                for (int t = 0; t < JS; ++t) ring[sl][i][t] = load_frag16(jres, jvoff, tile_off(0, i) + sl * CHB + t * 1024);
+            }
+        }
     __syncthreads();
 
     const float base = valid ? fmaf(a.dt, a.pump[rep] - 1.0f, 1.0f) : 0.0f;
@@ -171,11 +225,8 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
     constexpr int pj[6] = {JS == 1 ? 0 : 2, JS == 1 ? 0 : 1, 0, JS == 1 ? 0 : 1, 0, 0};
     constexpr int px[6] = {JS == 1 ? XS - 1 : 0, JS == 1 ? (XS > 1 ? XS - 2 : 0) : 1, JS == 1 ? 0 : 2, 0, 1, 0};
 
+    bf16x8 bxr[PF ? D : 1][PF ? XS : 1];  // PF: the state operand of the next chunk
     for (int k = 0; k < a.steps; ++k) {
-        // tile offsets are cheap scalar arithmetic: form them again every step
-        // instead of keeping them live in registers across the run
-        int w = w0;
-        asm volatile("" : "+s"(w));
         const float *al = a.alpha + (size_t)(a.start_step + k) * D;
         float ga[D];
 #pragma unroll
@@ -183,62 +234,61 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
 
 #pragma unroll
         for (int grp = 0; grp < NG; ++grp) {
-            // tiles I0 + 8 i, i < GS
-            const int I0 = w + GS * W * grp;
-            if (I0 >= nt) break;  // wave-uniform
+            if (grp >= ngw) break;  // wave-uniform
+            // the group whose chunks follow this group's in the stream
+            const bool more = grp + 1 < ngw;
+            int so[GS], son[GS];
+            float scn[GS];
+#pragma unroll
+            for (int i = 0; i < GS; ++i) {
+                so[i] = tile_off(grp, i);
+                son[i] = more ? tile_off(grp + 1 < NG ? grp + 1 : 0, i) : tile_off(0, i);
+                if constexpr (F8) scn[i] = more ? scale_of(grp + 1 < NG ? grp + 1 : 0, i) : scale_of(0, i);
+            }
             f32x4 acc[GS][D];
 #pragma unroll
             for (int i = 0; i < GS; ++i)
 #pragma unroll
                 for (int mu = 0; mu < D; ++mu) acc[i][mu] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-            int jso[GS];  // byte offset of the tile's first chunk
-            float sc[GS];
+            if constexpr (PF) {
+                if (grp == 0) {
+                    // later groups find chunk 0 in bxr, read during the previous
+                    // group's last chunk
 #pragma unroll
-            for (int i = 0; i < GS; ++i) {
-                const int I = I0 + W * i < nt ? I0 + W * i : I0;  // past the end: a valid tile
-                jso[i] = I * ncp * CHB;
-                // the lane's A row is 16 I + (lane & 15)
-                sc[i] = F8 ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sres, jcol * 4, I * 64, 0))
-                           : 1.0f;
+                    for (int mu = 0; mu < D; ++mu)
+#pragma unroll
+                        for (int t = 0; t < XS; ++t) bxr[mu][t] = lb[slab_b_index(0, mu, t, lane, D, XS)];
+                }
             }
-            // J fragments RD chunks ahead: ring slot sl holds chunk c with c % RD == sl
-            bf16x8 ring[F8 ? 1 : RD][GS][JS];
-            uint2 ring8[F8 ? RD : 1][GS];
-#pragma unroll
-            for (int sl = 0; sl < RD; ++sl)
+            // chunk c (c % RD == sl): take its J fragments from ring slot sl and
+            // refill the slot, take its state operand, accumulate
+            auto chunk = [&](int sl, int c) __attribute__((always_inline)) {
+                bf16x8 af[GS][JS];
+                const int cn = c + RD;
 #pragma unroll
                 for (int i = 0; i < GS; ++i) {
+                    const int nxt = cn < ncp ? so[i] + cn * CHB : son[i] + sl * CHB;
                     if constexpr (F8) {
-                        ring8[sl][i] = sl < ncp ? load_frag8(jres, jvoff, jso[i] + sl * CHB) : uint2{0u, 0u};
+                        af[i][0] = fp8_fragment(ring8[sl][i], sc[i]);
+                        ring8[sl][i] = load_frag8(jres, jvoff, nxt);
                     } else {
 #pragma unroll
-                        for (int t = 0; t < JS; ++t)
-                            ring[sl][i][t] = sl < ncp ? load_frag16(jres, jvoff, jso[i] + sl * CHB + t * 1024)
-                                                      : bf16x8{};
+                        for (int t = 0; t < JS; ++t) {
+                            af[i][t] = ring[sl][i][t];
+                            ring[sl][i][t] = load_frag16(jres, jvoff, nxt + t * 1024);
+                        }
                     }
                 }
-            // PF: the state operand of the next chunk is read from LDS while the
-            // current chunk's products run (its registers fit without spills
-            // for these shapes; measured 4-8% faster there, slower for D = 2
-            // in the bf16 form, and spilling at D = 4 or D = 3 in float32)
-            constexpr bool PF = (D == 3 && XS == 1) || (D == 2 && XS == 3);
-            bf16x8 bxr[PF ? D : 1][PF ? XS : 1];
-            if constexpr (PF) {
-#pragma unroll
-                for (int mu = 0; mu < D; ++mu)
-#pragma unroll
-                    for (int t = 0; t < XS; ++t) bxr[mu][t] = lb[slab_b_index(0, mu, t, lane, D, XS)];
-            }
-            auto chunk = [&](int c, bf16x8 (&af)[GS][JS]) __attribute__((always_inline)) {
                 bf16x8 bx[D][XS];
                 if constexpr (PF) {
-                    const int cn = c + 1 < ncp ? c + 1 : c;  // the last chunk reads its own again
+                    // past the last chunk: chunk 0 of the next group
+                    const int cb = c + 1 < ncp ? c + 1 : 0;
 #pragma unroll
                     for (int mu = 0; mu < D; ++mu)
 #pragma unroll
                         for (int t = 0; t < XS; ++t) {
                             bx[mu][t] = bxr[PF ? mu : 0][PF ? t : 0];
-                            bxr[PF ? mu : 0][PF ? t : 0] = lb[slab_b_index(cn, mu, t, lane, D, XS)];
+                            bxr[PF ? mu : 0][PF ? t : 0] = lb[slab_b_index(cb, mu, t, lane, D, XS)];
                         }
                 } else {
 #pragma unroll
@@ -255,48 +305,14 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
                             acc[i][mu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i][pj[q]], bx[mu][px[q]],
                                                                                 acc[i][mu], 0, 0, 0);
             };
-            // RD chunks per iteration; the refill of each ring slot is
-            // unconditional (past the tile's last chunk it loads the next
-            // tile's fragments, or for the last tile the RD chunks of padding
-            // that slab_jfrag_bytes adds to the staging, and never uses them),
-            // so the slot's next value is always the load itself and stays in
-            // the register the load writes.  The last ncp % RD chunks are
-            // peeled off.
-            auto take = [&](int sl, int cnext, bf16x8 (&af)[GS][JS]) __attribute__((always_inline)) {
-                if constexpr (F8) {
-#pragma unroll
-                    for (int i = 0; i < GS; ++i) af[i][0] = fp8_fragment(ring8[sl][i], sc[i]);
-#pragma unroll
-                    for (int i = 0; i < GS; ++i) ring8[sl][i] = load_frag8(jres, jvoff, jso[i] + cnext * CHB);
-                } else {
-#pragma unroll
-                    for (int i = 0; i < GS; ++i)
-#pragma unroll
-                        for (int t = 0; t < JS; ++t) af[i][t] = ring[sl][i][t];
-#pragma unroll
-                    for (int i = 0; i < GS; ++i)
-#pragma unroll
-                        for (int t = 0; t < JS; ++t)
-                            ring[sl][i][t] = load_frag16(jres, jvoff, jso[i] + cnext * CHB + t * 1024);
-                }
-            };
             int c = 0;
             for (; c + RD <= ncp; c += RD) {
 #pragma unroll
-                for (int sl = 0; sl < RD; ++sl) {
-                    bf16x8 af[GS][JS];
-                    take(sl, c + sl + RD, af);
-                    chunk(c + sl, af);
-                }
+                for (int sl = 0; sl < RD; ++sl) chunk(sl, c + sl);
             }
 #pragma unroll
-            for (int sl = 0; sl + 1 < RD; ++sl) {
-                if (c + sl < ncp) {
-                    bf16x8 af[GS][JS];
-                    take(sl, c + sl + RD, af);
-                    chunk(c + sl, af);
-                }
-            }
+            for (int sl = 0; sl + 1 < RD; ++sl)
+                if (c + sl < ncp) chunk(sl, c + sl);
             // fused Euler update of the group's tiles
 #pragma unroll
             for (int i = 0; i < GS; ++i) {
@@ -318,12 +334,16 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
                     }
                 }
             }
+            if constexpr (F8) {
+#pragma unroll
+                for (int i = 0; i < GS; ++i) sc[i] = scn[i];
+            }
         }
         __syncthreads();  // every wavefront is done reading the old operand
 #pragma unroll
         for (int kk = 0; kk < TPW; ++kk) {
             const int I = w + W * kk;
-            if (I < nt) slab_write_tile<D, XS>(x[kk], I, lane, lb, negk);
+            if (I < nt) slab_write_tile<D, XS>(x[kk], I, lane, lb);
         }
         __syncthreads();
     }

@@ -81,9 +81,9 @@ def test_unsupported_size_reported_before_device():
     assert "workspace" in lib.chym_last_error().decode()
     nbytes = ctypes.c_size_t(0)
     assert lib.chym_integrate_workspace_size(ctypes.byref(prob), ctypes.byref(run), ctypes.byref(nbytes)) == 0
-    # header, row scales of 63 x 16 rows, 63 row tiles x 32 chunks x 1 KiB fragments, and two chunks of
+    # header, row scales of 63 x 16 rows, 63 row tiles x 32 chunks x 1 KiB fragments, and four chunks of
     # padding that the kernel's prefetch ring may load (and discard) past the last tile
-    assert nbytes.value == 256 + 4096 + (63 * 32 + 2) * 1024
+    assert nbytes.value == 256 + 4096 + (63 * 32 + 4) * 1024
     assert lib.chym_integrate_ws(ctypes.byref(prob), ctypes.byref(run), ctypes.c_void_p(0x10000), 100,
                                  None) == L.CHYM_ENOMEM
     small = _prob(n=100, d=2)
