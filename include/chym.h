@@ -409,8 +409,16 @@ int chym_to_bf16(const float *src, uint16_t *dst, int32_t n, chym_stream_t strea
  *   CHYM_KERNEL_PIPE  J in LDS as for LDSJ1, with the step loop software-
  *                     pipelined: the vector work of one step runs between
  *                     the matrix-core products of the next.
- * The table is process-wide and starts empty (CHYM_KERNEL_REGJ, 4 waves per
- * block, for every variant).  Plans change speed only, never results.
+ *   CHYM_KERNEL_SLAB  the streamed-J kernel, for the variants beyond the
+ *                     register-resident ones (its only kind there): `waves`
+ *                     is its block size, 8 (two wavefronts per SIMD) or 16
+ *                     (four per SIMD, bf16 form, up to 32 row tiles, or
+ *                     64 at d <= 2).
+ * The table is process-wide and starts empty: CHYM_KERNEL_REGJ with 4 waves
+ * per block for the register-resident variants, CHYM_KERNEL_SLAB with 16
+ * waves up to 32 row tiles where built and 8 beyond for the streamed-J ones.
+ * The single-problem calls (chym_integrate_ws, chym_solve_ws) use the
+ * streamed-J entries too.  Plans change speed only, never results.
  */
 #define CHYM_KERNEL_AUTO 0
 #define CHYM_KERNEL_REGJ 1
@@ -420,15 +428,17 @@ int chym_to_bf16(const float *src, uint16_t *dst, int32_t n, chym_stream_t strea
                                step and the operand split with the current step's products (two accumulator
                                sets); built for d = 2, 3 and 2 to 7 row tiles with couplings in one bf16
                                term (any storage in the bf16 form; int8, bf16 or FP8 in the float32 form) */
+#define CHYM_KERNEL_SLAB 5  /* the streamed-J kernel (n beyond the register-resident variants) */
 
 typedef struct chym_plan_entry {
     int32_t n;         /* problem size the entry applies to (any n with the same 16-row tile count) */
     int32_t d;
     int32_t precision; /* CHYM_PREC_* */
     int32_t j_dtype;   /* CHYM_J_* */
-    int32_t kernel;    /* CHYM_KERNEL_REGJ, _LDSJ, _LDSJ1 or _PIPE (CHYM_KERNEL_AUTO: remove the entry);
+    int32_t kernel;    /* CHYM_KERNEL_REGJ, _LDSJ, _LDSJ1 or _PIPE for register-resident variants,
+                          CHYM_KERNEL_SLAB for streamed-J ones (CHYM_KERNEL_AUTO: remove the entry);
                           a kind not built for the shape is refused with CHYM_EUNSUPPORTED */
-    int32_t waves;     /* wavefronts per block, 1..4 */
+    int32_t waves;     /* wavefronts per block: 1..4, or 8 or 16 for CHYM_KERNEL_SLAB */
     float ms;          /* autotune: measured time of the probe run of this entry (informational) */
     float reserved;    /* must be 0 */
 } chym_plan_entry;

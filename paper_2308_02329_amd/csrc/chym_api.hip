@@ -153,6 +153,8 @@ int check_variant(const chym_problem *prob, const chym_run *run) {
     return CHYM_OK;
 }
 
+int slab_plan_waves(const Variant &v, int d);  // block size of the streamed-J kernel from the plan table
+
 int integrate_impl(const chym_problem *prob, const chym_run *run, hipStream_t stream, void *ws = nullptr,
                    size_t ws_bytes = 0) {
     int rc = check_variant(prob, run);
@@ -177,7 +179,8 @@ int integrate_impl(const chym_problem *prob, const chym_run *run, hipStream_t st
     }
     if (v.slab) {
         hipError_t e = chym::launch_stage_jfrag(a, v.js, ws, stream);
-        if (e == hipSuccess) e = chym::launch_integrate_slab(v.tiles, prob->d, v.xs, v.js, a, ws, stream);
+        const int waves = slab_plan_waves(v, prob->d);
+        if (e == hipSuccess) e = chym::launch_integrate_slab(v.tiles, prob->d, v.xs, v.js, waves, a, ws, stream);
         if (e != hipSuccess) return hip_fail(e, "slab integrate launch");
         return CHYM_OK;
     }
@@ -257,10 +260,14 @@ int validate_hs(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dtype,
 typedef std::tuple<int, int, int, int> VariantKey;  // (tiles, d, xs, js)
 
 struct PlanValue {
-    int kind;   // chym::kKernelRegJ / kKernelLdsJ / kKernelLdsJ1
+    int kind;   // chym::kKernelRegJ / kKernelLdsJ / kKernelLdsJ1 / kKernelPipe / kKernelSlab
     int waves;  // wavefronts per block
     float ms;
 };
+
+// Streamed-J variants take the slab kernel; their plans choose its block
+// size.  Internal kind of such a plan.
+constexpr int kKernelSlab = 100;
 
 std::mutex g_plan_mu;
 std::map<VariantKey, PlanValue> g_plan;
@@ -270,18 +277,34 @@ constexpr int kPersistentWaves = 4;
 
 VariantKey key_of(const Variant &v, int d) { return std::make_tuple(v.tiles, d, v.xs, v.js); }
 
+bool key_is_slab(const VariantKey &k) {
+    return std::get<0>(k) > chym::resident_tile_limit(std::get<1>(k), std::get<2>(k), std::get<3>(k));
+}
+
+// Default block size of the slab kernel: sixteen wavefronts up to 32 row
+// tiles where built (measured faster there), else eight.
+int default_slab_waves(const VariantKey &k) {
+    const int tiles = std::get<0>(k), d = std::get<1>(k), xs = std::get<2>(k), js = std::get<3>(k);
+    return (tiles <= 32 && chym::slab_shape_exists(tiles, d, xs, js, chym::kSlabWaves16)) ? chym::kSlabWaves16
+                                                                                          : chym::kSlabWaves8;
+}
+
 PlanValue plan_for(const VariantKey &k) {
     std::lock_guard<std::mutex> lk(g_plan_mu);
     auto it = g_plan.find(k);
     if (it != g_plan.end()) return it->second;
+    if (key_is_slab(k)) return PlanValue{kKernelSlab, default_slab_waves(k), 0.0f};
     return PlanValue{chym::kKernelRegJ, kDefaultWaves, 0.0f};
 }
+
+int slab_plan_waves(const Variant &v, int d) { return plan_for(key_of(v, d)).waves; }
 
 int kind_of_code(int code) {
     switch (code) {
         case CHYM_KERNEL_LDSJ: return chym::kKernelLdsJ;
         case CHYM_KERNEL_LDSJ1: return chym::kKernelLdsJ1;
         case CHYM_KERNEL_PIPE: return chym::kKernelPipe;
+        case CHYM_KERNEL_SLAB: return kKernelSlab;
         default: return chym::kKernelRegJ;
     }
 }
@@ -290,11 +313,13 @@ int code_of_kind(int kind) {
         case chym::kKernelLdsJ: return CHYM_KERNEL_LDSJ;
         case chym::kKernelLdsJ1: return CHYM_KERNEL_LDSJ1;
         case chym::kKernelPipe: return CHYM_KERNEL_PIPE;
+        case kKernelSlab: return CHYM_KERNEL_SLAB;
         default: return CHYM_KERNEL_REGJ;
     }
 }
 bool valid_kernel_code(int code) {
-    return code == CHYM_KERNEL_REGJ || code == CHYM_KERNEL_LDSJ || code == CHYM_KERNEL_LDSJ1 || code == CHYM_KERNEL_PIPE;
+    return code == CHYM_KERNEL_REGJ || code == CHYM_KERNEL_LDSJ || code == CHYM_KERNEL_LDSJ1 ||
+           code == CHYM_KERNEL_PIPE || code == CHYM_KERNEL_SLAB;
 }
 
 Variant variant_of_shape(int n, int precision, int j_dtype) {
@@ -313,9 +338,8 @@ int validate_shape(int32_t n, int32_t d, int32_t precision, int32_t j_dtype) {
         return fail(CHYM_EINVAL, "precision = %d is not CHYM_PREC_F32 or CHYM_PREC_BF16", precision);
     if (!valid_jdtype(j_dtype)) return fail(CHYM_EINVAL, "bad j_dtype %d", j_dtype);
     const Variant v = variant_of_shape(n, precision, j_dtype);
-    if (v.tiles > chym::resident_tile_limit(d, v.xs, v.js))
-        return fail(CHYM_EUNSUPPORTED, "n = %d with d = %d has no launch plans (it runs on the slab integrator)", n,
-                    d);
+    if (v.tiles > chym::resident_tile_limit(d, v.xs, v.js) && !chym::slab_variant_exists(v.tiles, d, v.xs, v.js))
+        return fail(CHYM_EUNSUPPORTED, "n = %d with d = %d in this precision is beyond the integrators", n, d);
     return CHYM_OK;
 }
 
@@ -433,7 +457,7 @@ int plan_layout(const chym_task *tasks, int32_t n_tasks, BatchLayout *L) {
             for (const int2 &it : lst) g.lds = std::max(g.lds, chym::ell_lds_bytes(tasks[it.x].prob.n, g.d));
         } else if (g.v.slab) {
             g.kind = -1;
-            g.waves = 4;
+            g.waves = plan_for(key_of(g.v, g.d)).waves;  // the slab kernel's block size
             g.lds = chym::slab_lds_bytes(g.v.tiles, g.d, g.v.xs);
         } else {
             const PlanValue pv = plan_for(key_of(g.v, g.d));
@@ -541,7 +565,7 @@ int issue_batch(const chym_batch *b, hipStream_t main, const std::vector<hipStre
                                                       counters + gi, s);
         else if (g.v.slab)
             e = chym::launch_integrate_slab_persistent(
-                g.v.tiles, g.d, g.v.xs, g.v.js, g.lds, g.blocks, tasks_d, items_d + g.item_off, g.n_items,
+                g.v.tiles, g.d, g.v.xs, g.v.js, g.waves, g.lds, g.blocks, tasks_d, items_d + g.item_off, g.n_items,
                 counters + gi, reinterpret_cast<const void *const *>(b->ws + L.off_jfp),
                 reinterpret_cast<const int *>(b->ws + L.off_ncp), s);
         else
@@ -704,7 +728,7 @@ int batch_build(const chym_task *tasks, int32_t n_tasks, void *workspace, size_t
         int per_cu = 0;
         if (e == hipSuccess) {
             if (g.v.ell) e = chym::ell_persistent_occupancy(g.d, g.lds, &per_cu);
-            else if (g.v.slab) e = chym::slab_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, g.lds, &per_cu);
+            else if (g.v.slab) e = chym::slab_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, g.waves, g.lds, &per_cu);
             else e = chym::persistent_occupancy(g.v.tiles, g.d, g.v.xs, g.v.js, g.kind, g.waves, &per_cu);
         }
         const int need = (g.v.ell || g.v.slab || g.kind != chym::kKernelRegJ) ? g.n_items
@@ -1089,10 +1113,21 @@ int chym_plan_set(const chym_plan_entry *e) {
         return CHYM_OK;
     }
     if (!valid_kernel_code(e->kernel)) return fail(CHYM_EINVAL, "kernel = %d is not a CHYM_KERNEL_* value", e->kernel);
-    if (e->waves < 1 || e->waves > 4) return fail(CHYM_EINVAL, "waves = %d must be in 1..4", e->waves);
-    if (!chym::persistent_kind_exists(std::get<0>(k), e->d, std::get<2>(k), std::get<3>(k), kind_of_code(e->kernel)))
-        return fail(CHYM_EUNSUPPORTED, "kernel = %d is not built for n = %d, d = %d in this form", e->kernel, e->n,
-                    e->d);
+    if (key_is_slab(k) != (e->kernel == CHYM_KERNEL_SLAB))
+        return fail(CHYM_EUNSUPPORTED, "n = %d, d = %d in this form runs on the %s kernel: kernel must %s CHYM_KERNEL_SLAB",
+                    e->n, e->d, key_is_slab(k) ? "streamed-J" : "register-resident", key_is_slab(k) ? "be" : "not be");
+    if (e->kernel == CHYM_KERNEL_SLAB) {
+        if (e->waves != chym::kSlabWaves8 && e->waves != chym::kSlabWaves16)
+            return fail(CHYM_EINVAL, "waves = %d must be 8 or 16 for the streamed-J kernel", e->waves);
+        if (!chym::slab_shape_exists(std::get<0>(k), e->d, std::get<2>(k), std::get<3>(k), e->waves))
+            return fail(CHYM_EUNSUPPORTED, "no streamed-J block of %d wavefronts for n = %d, d = %d in this form",
+                        e->waves, e->n, e->d);
+    } else {
+        if (e->waves < 1 || e->waves > 4) return fail(CHYM_EINVAL, "waves = %d must be in 1..4", e->waves);
+        if (!chym::persistent_kind_exists(std::get<0>(k), e->d, std::get<2>(k), std::get<3>(k), kind_of_code(e->kernel)))
+            return fail(CHYM_EUNSUPPORTED, "kernel = %d is not built for n = %d, d = %d in this form", e->kernel, e->n,
+                        e->d);
+    }
     g_plan[k] = PlanValue{kind_of_code(e->kernel), e->waves, e->ms};
     return CHYM_OK;
 }
@@ -1125,9 +1160,10 @@ ProbeLayout probe_layout(int n, int d, int r, int steps) {
     L.off_x = L.off_pump + align_up((size_t)r * 4);
     L.off_alpha = L.off_x + align_up((size_t)n * r * d * 4);
     L.off_batch = L.off_alpha + align_up((size_t)steps * d * 4);
-    // batch workspace of one resident task: its work list is largest with
-    // 16-replica items; no staged couplings follow the tables
-    L.batch_bytes = batch_tables(1, (size_t)((r + 15) / 16), 1).off_jf;
+    // batch workspace of one task: its work list is largest with 16-replica
+    // items; the staged couplings of a streamed-J task follow the tables
+    // (sized for three coupling terms, the most any form stages)
+    L.batch_bytes = batch_tables(1, (size_t)((r + 15) / 16), 1).off_jf + align_up(chym::slab_jfrag_bytes((n + 15) / 16, 3));
     L.total = L.off_batch + L.batch_bytes;
     return L;
 }
@@ -1191,12 +1227,19 @@ int chym_plan_autotune(int32_t n, int32_t d, int32_t precision, int32_t j_dtype,
                                    {chym::kKernelLdsJ, 2, 0.f},
                                    {chym::kKernelLdsJ, 4, 0.f},
                                    {chym::kKernelLdsJ1, 4, 0.f},
-                                   {chym::kKernelPipe, 4, 0.f}};
+                                   {chym::kKernelPipe, 4, 0.f},
+                                   {kKernelSlab, chym::kSlabWaves8, 0.f},
+                                   {kKernelSlab, chym::kSlabWaves16, 0.f}};
     PlanValue cands[sizeof(all_cands) / sizeof(all_cands[0])];
     int kCands = 0;
-    for (const PlanValue &pv : all_cands)
-        if (chym::persistent_kind_exists(std::get<0>(key), d, std::get<2>(key), std::get<3>(key), pv.kind))
-            cands[kCands++] = pv;
+    const bool slab = key_is_slab(key);
+    for (const PlanValue &pv : all_cands) {
+        const bool ok = slab ? (pv.kind == kKernelSlab &&
+                                chym::slab_shape_exists(std::get<0>(key), d, std::get<2>(key), std::get<3>(key), pv.waves))
+                             : (pv.kind != kKernelSlab &&
+                                chym::persistent_kind_exists(std::get<0>(key), d, std::get<2>(key), std::get<3>(key), pv.kind));
+        if (ok) cands[kCands++] = pv;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -1444,12 +1487,20 @@ int chym_plan_load(const char *path) {
         float ms;
         if (sscanf(line, "%d %d %d %d %d %d %f", &t, &d, &xs, &js, &kernel, &waves, &ms) != 7 || t < 1 || d < 1 ||
             d > 4 || (xs != 1 && xs != 3) || (js != 1 && js != 3) ||
-            !valid_kernel_code(kernel) || waves < 1 ||
-            waves > 4) {
+            !valid_kernel_code(kernel) ||
+            (kernel == CHYM_KERNEL_SLAB ? (waves != chym::kSlabWaves8 && waves != chym::kSlabWaves16)
+                                        : (waves < 1 || waves > 4))) {
             fclose(f);
             return fail(CHYM_EINVAL, "%s:%d: malformed plan entry", path, lineno);
         }
-        got.push_back({std::make_tuple(t, d, xs, js), PlanValue{kind_of_code(kernel), waves, ms}});
+        const VariantKey k = std::make_tuple(t, d, xs, js);
+        const bool slab_ok = kernel != CHYM_KERNEL_SLAB || chym::slab_shape_exists(t, d, xs, js, waves);
+        if (key_is_slab(k) != (kernel == CHYM_KERNEL_SLAB) || !slab_ok) {
+            fclose(f);
+            return fail(CHYM_EINVAL, "%s:%d: kernel %d does not run %d tiles at d = %d in this form", path, lineno,
+                        kernel, t, d);
+        }
+        got.push_back({k, PlanValue{kind_of_code(kernel), waves, ms}});
     }
     fclose(f);
     std::lock_guard<std::mutex> lk(g_plan_mu);

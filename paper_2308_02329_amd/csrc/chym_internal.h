@@ -187,20 +187,26 @@ hipError_t launch_score_batched(const ScoreArgs *tasks, const int64_t *first, in
 // Streamed-J slab integrator (large n).  Tiles of 16 rows; kSlabMaxLds
 // bounds the LDS operand area of one column slab.
 constexpr size_t kSlabMaxLds = 159 * 1024;  // 160 KiB per CU, less room for static LDS
-int slab_tpw_for(int tiles);
+// Blocks of eight or sixteen wavefronts (kSlabWaves8, kSlabWaves16); the
+// sixteen-wavefront shapes are built for the bf16 form, up to 32 tiles (64
+// at d <= 2).
+constexpr int kSlabWaves8 = 8;
+constexpr int kSlabWaves16 = 16;
+int slab_tpw_for(int tiles, int waves);
 size_t slab_lds_bytes(int tiles, int d, int xs);
 size_t slab_jfrag_bytes(int tiles, int js);
-bool slab_variant_exists(int tiles, int d, int xs, int js);
+bool slab_variant_exists(int tiles, int d, int xs, int js);  // the eight-wavefront shape
+bool slab_shape_exists(int tiles, int d, int xs, int js, int waves);
 hipError_t launch_stage_jfrag(const IntegArgs &a, int js, void *out, hipStream_t stream);
 // Stages the couplings of the tasks list[0 .. n) of a batch (all with js
 // coupling terms) into stages[task], ncps[task] chunks each; tasks, list,
 // ncps and stages are device arrays.
 hipError_t launch_stage_batched(int js, const IntegArgs *tasks, const int *list, int n, const int *ncps,
                                 unsigned char *const *stages, hipStream_t stream);
-hipError_t launch_integrate_slab(int tiles, int d, int xs, int js, const IntegArgs &a, const void *jfrag,
+hipError_t launch_integrate_slab(int tiles, int d, int xs, int js, int waves, const IntegArgs &a, const void *jfrag,
                                  hipStream_t stream);
-hipError_t slab_occupancy(int tiles, int d, int xs, int js, size_t lds, int *blocks_per_cu);
-hipError_t launch_integrate_slab_persistent(int tiles, int d, int xs, int js, size_t lds, int blocks,
+hipError_t slab_occupancy(int tiles, int d, int xs, int js, int waves, size_t lds, int *blocks_per_cu);
+hipError_t launch_integrate_slab_persistent(int tiles, int d, int xs, int js, int waves, size_t lds, int blocks,
                                             const IntegArgs *tasks, const int2 *items, int n_items, int *counter,
                                             const void *const *jfs, const int *ncps, hipStream_t stream);
 

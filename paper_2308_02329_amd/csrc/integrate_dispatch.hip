@@ -32,19 +32,19 @@ static SlabKernels lookup_slab_shape(int tpw, int waves, int d, int xs, int js) 
     return SlabKernels{nullptr, nullptr, 0};
 }
 
-// Block shape of the slab kernel for a tile count: eight wavefronts with 4
-// or 8 tiles each, up to 64 tiles.
-static SlabKernels lookup_slab(int tiles, int d, int xs, int js) {
-    const int per = (tiles + 7) / 8;
-    const int tpw = (per + 3) / 4 * 4;
-    if (tpw > 8) return SlabKernels{nullptr, nullptr, 0};
-    return lookup_slab_shape(tpw, 8, d, xs, js);
+// Tiles per wavefront of the slab kernel for a tile count and block size
+// (eight or sixteen wavefronts); 0 when no shape holds that many tiles.
+int slab_tpw_for(int tiles, int waves) {
+    const int per = (tiles + waves - 1) / waves;
+    if (waves == 8) return per <= 4 ? 4 : (per <= 8 ? 8 : 0);
+    if (waves == 16) return per <= 1 ? 1 : (per <= 2 ? 2 : (per <= 4 ? 4 : 0));
+    return 0;
 }
 
-int slab_tpw_for(int tiles) {
-    const int per = (tiles + 7) / 8;
-    const int tpw = (per + 3) / 4 * 4;
-    return tpw <= 8 ? tpw : 0;
+static SlabKernels lookup_slab(int tiles, int d, int xs, int js, int waves) {
+    const int tpw = slab_tpw_for(tiles, waves);
+    if (tpw == 0) return SlabKernels{nullptr, nullptr, 0};
+    return lookup_slab_shape(tpw, waves, d, xs, js);
 }
 
 size_t slab_lds_bytes(int tiles, int d, int xs) { return (size_t)((tiles + 1) / 2) * d * xs * 64 * sizeof(bf16x8); }
@@ -59,8 +59,10 @@ size_t slab_jfrag_bytes(int tiles, int js) {
     return stage_frag_offset(tiles) + ((size_t)tiles * ((tiles + 1) / 2) + kSlabRingChunks) * js * 64 * sizeof(bf16x8);
 }
 
-bool slab_variant_exists(int tiles, int d, int xs, int js) {
-    return slab_lds_bytes(tiles, d, xs) <= kSlabMaxLds && lookup_slab(tiles, d, xs, js).single != nullptr;
+bool slab_variant_exists(int tiles, int d, int xs, int js) { return slab_shape_exists(tiles, d, xs, js, 8); }
+
+bool slab_shape_exists(int tiles, int d, int xs, int js, int waves) {
+    return slab_lds_bytes(tiles, d, xs) <= kSlabMaxLds && lookup_slab(tiles, d, xs, js, waves).single != nullptr;
 }
 
 // Decides whether the couplings can be staged as E4M3 bytes: every row must
@@ -159,9 +161,9 @@ static hipError_t slab_prepare(const void *fn, size_t lds) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-hipError_t launch_integrate_slab(int tiles, int d, int xs, int js, const IntegArgs &a, const void *jfrag,
+hipError_t launch_integrate_slab(int tiles, int d, int xs, int js, int waves, const IntegArgs &a, const void *jfrag,
                                  hipStream_t stream) {
-    SlabKernels k = lookup_slab(tiles, d, xs, js);
+    SlabKernels k = lookup_slab(tiles, d, xs, js, waves);
     if (!k.single) return hipErrorInvalidDeviceFunction;
     const size_t lds = slab_lds_bytes(tiles, d, xs);
     hipError_t e = slab_prepare(reinterpret_cast<const void *>(k.single), lds);
@@ -173,19 +175,19 @@ hipError_t launch_integrate_slab(int tiles, int d, int xs, int js, const IntegAr
     return hipGetLastError();
 }
 
-hipError_t slab_occupancy(int tiles, int d, int xs, int js, size_t lds, int *blocks_per_cu) {
+hipError_t slab_occupancy(int tiles, int d, int xs, int js, int waves, size_t lds, int *blocks_per_cu) {
     *blocks_per_cu = 0;
-    SlabKernels k = lookup_slab(tiles, d, xs, js);
+    SlabKernels k = lookup_slab(tiles, d, xs, js, waves);
     if (!k.persistent) return hipErrorInvalidDeviceFunction;
     hipError_t e = slab_prepare(reinterpret_cast<const void *>(k.persistent), lds);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k.persistent, 64 * k.waves, lds);
 }
 
-hipError_t launch_integrate_slab_persistent(int tiles, int d, int xs, int js, size_t lds, int blocks,
+hipError_t launch_integrate_slab_persistent(int tiles, int d, int xs, int js, int waves, size_t lds, int blocks,
                                             const IntegArgs *tasks, const int2 *items, int n_items, int *counter,
                                             const void *const *jfs, const int *ncps, hipStream_t stream) {
-    SlabKernels k = lookup_slab(tiles, d, xs, js);
+    SlabKernels k = lookup_slab(tiles, d, xs, js, waves);
     if (!k.persistent) return hipErrorInvalidDeviceFunction;
     hipError_t e = slab_prepare(reinterpret_cast<const void *>(k.persistent), lds);
     if (e != hipSuccess) return e;

@@ -1,8 +1,8 @@
 // Streamed-J CHYM integrator for large N (gfx950).
 //
-// One block of W wavefronts (eight: two per SIMD, or four: one per SIMD with
-// twice the registers) owns a column slab -- 16 replicas x D components of
-// one problem -- for the whole run.  Row tiles (16 rows) are dealt to the
+// One block of W wavefronts (eight: two per SIMD; sixteen, four per SIMD
+// with half the registers, for few row tiles) owns a column slab -- 16
+// replicas x D components of one problem -- for the whole run.  Row tiles (16 rows) are dealt to the
 // wavefronts round-robin: wavefront w owns tiles w, w+W, ...,
 // whose float32 state lives in its registers in the 16x16 MFMA accumulator
 // layout (lane j + 16 g holds rows 16 I + 4 g + v of replica j).
@@ -129,9 +129,10 @@ __device__ __forceinline__ void slab_write_tile(const float (&xt)[D][4], int I, 
 template <int D, int XS, int JS, int TPW, bool F8, int W>
 __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, const unsigned char *__restrict__ stage,
                                                int ncp, bf16x8 *lb) {
-    // tiles accumulated together (register budget: 256 per lane at two
-    // wavefronts per SIMD, 512 at one)
-    constexpr int GS = W == 8 ? (D >= 3 ? 2 : 4) : (D >= 3 ? 4 : 8);
+    // tiles accumulated together (register budget per lane: 128 at four
+    // wavefronts per SIMD, 256 at two, 512 at one)
+    constexpr int GS0 = W == 16 ? (D >= 3 ? 1 : 2) : (W == 8 ? (D >= 3 ? 2 : 4) : (D >= 3 ? 4 : 8));
+    constexpr int GS = GS0 < TPW ? GS0 : TPW;
     constexpr int NG = TPW / GS;        // groups of owned tiles
     // chunks of J fragments in flight: E4M3 fragments take two registers
     // per tile, bf16 ones four per term
@@ -474,15 +475,29 @@ struct SlabKernels {
     int waves;
 };
 
-// Slab shapes: eight wavefronts with 4 or 8 tiles each.  (One wavefront per
-// SIMD with 16 tiles measured slower at N = 1000, D = 4: a lone wavefront
-// cannot cover the L2 latency of the J stream.)
+// Slab shapes: eight wavefronts with 4 or 8 tiles each, and in the bf16
+// form sixteen wavefronts with 1 or 2 tiles each, or 4 at D <= 2 (measured faster up to
+// about 32 row tiles: more wavefronts cover the latency of the operand reads
+// and of the J stream when each owns few tiles).  One wavefront per SIMD with
+// 16 tiles measured slower at N = 1000, D = 4 (a lone wavefront cannot cover
+// the L2 latency of the J stream), and at N = 200 - 800 too.
 template <int D, int XS, int JS>
 SlabKernels slab_lookup_tpw(int tpw, int waves) {
     if (waves == 8 && tpw == 4)
         return SlabKernels{k_integrate_slab<D, XS, JS, 4, 8>, k_integrate_slab_persistent<D, XS, JS, 4, 8>, 8};
     if (waves == 8 && tpw == 8)
         return SlabKernels{k_integrate_slab<D, XS, JS, 8, 8>, k_integrate_slab_persistent<D, XS, JS, 8, 8>, 8};
+    if constexpr (XS == 1) {
+        if (waves == 16 && tpw == 1)
+            return SlabKernels{k_integrate_slab<D, XS, JS, 1, 16>, k_integrate_slab_persistent<D, XS, JS, 1, 16>, 16};
+        if (waves == 16 && tpw == 2)
+            return SlabKernels{k_integrate_slab<D, XS, JS, 2, 16>, k_integrate_slab_persistent<D, XS, JS, 2, 16>, 16};
+        if constexpr (D <= 2) {  // four tiles of three or four components spill at 128 registers
+            if (waves == 16 && tpw == 4)
+                return SlabKernels{k_integrate_slab<D, XS, JS, 4, 16>, k_integrate_slab_persistent<D, XS, JS, 4, 16>,
+                                   16};
+        }
+    }
     return SlabKernels{nullptr, nullptr, 0};
 }
 

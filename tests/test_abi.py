@@ -170,6 +170,49 @@ def test_plan_table_validation_and_file_roundtrip(tmp_path):
     assert lib.chym_split3_bf16(0x1000, 7, 0x2000, 0x3000, 0x4000, None) == L.CHYM_EINVAL
 
 
+def test_streamed_j_plans(tmp_path):
+    """Streamed-J variants (beyond the register-resident tile limits) take
+    CHYM_KERNEL_SLAB plans whose `waves` is the block size: 16 by default up
+    to 32 row tiles in the bf16 form, 8 beyond and in the float32 form; the
+    other kinds are refused there, and CHYM_KERNEL_SLAB is refused on
+    register-resident variants."""
+    lib = L.load()
+    got = L.ChymPlanEntry()
+    bf, f32, i8 = L.CHYM_PREC_BF16, L.CHYM_PREC_F32, L.CHYM_J_I8
+    for n, d, prec, want in ((400, 4, bf, 16), (512, 2, bf, 16), (800, 4, bf, 8), (1000, 3, bf, 8), (400, 2, f32, 8)):
+        assert lib.chym_plan_get(n, d, prec, i8, ctypes.byref(got)) == L.CHYM_OK
+        assert (got.kernel, got.waves) == (L.CHYM_KERNEL_SLAB, want), (n, d, prec)
+    assert lib.chym_plan_get(100, 3, bf, i8, ctypes.byref(got)) == L.CHYM_OK
+    assert got.kernel == L.CHYM_KERNEL_REGJ
+    assert lib.chym_plan_get(1100, 2, bf, i8, ctypes.byref(got)) == L.CHYM_EUNSUPPORTED  # beyond every integrator
+
+    def entry(n, d, prec, kernel, waves):
+        return L.ChymPlanEntry(n=n, d=d, precision=prec, j_dtype=i8, kernel=kernel, waves=waves, ms=0.0, reserved=0.0)
+
+    e = entry(800, 2, bf, L.CHYM_KERNEL_SLAB, 16)
+    assert lib.chym_plan_set(ctypes.byref(e)) == L.CHYM_OK
+    assert lib.chym_plan_get(800, 2, bf, i8, ctypes.byref(got)) == L.CHYM_OK
+    assert (got.kernel, got.waves) == (L.CHYM_KERNEL_SLAB, 16)
+    path = str(tmp_path / "plan.txt").encode()
+    assert lib.chym_plan_save(path) == L.CHYM_OK
+    e.kernel = L.CHYM_KERNEL_AUTO
+    assert lib.chym_plan_set(ctypes.byref(e)) == L.CHYM_OK
+    assert lib.chym_plan_get(800, 2, bf, i8, ctypes.byref(got)) == L.CHYM_OK and got.waves == 8
+    assert lib.chym_plan_load(path) == L.CHYM_OK
+    assert lib.chym_plan_get(800, 2, bf, i8, ctypes.byref(got)) == L.CHYM_OK and got.waves == 16
+    assert lib.chym_plan_set(ctypes.byref(e)) == L.CHYM_OK  # back to the default
+    for bad, rc in ((entry(800, 4, bf, L.CHYM_KERNEL_LDSJ, 2), L.CHYM_EUNSUPPORTED),   # resident kind on streamed-J
+                    (entry(100, 3, bf, L.CHYM_KERNEL_SLAB, 8), L.CHYM_EUNSUPPORTED),  # streamed-J kind on resident
+                    (entry(800, 4, bf, L.CHYM_KERNEL_SLAB, 4), L.CHYM_EINVAL),        # block size
+                    (entry(800, 4, bf, L.CHYM_KERNEL_SLAB, 16), L.CHYM_EUNSUPPORTED),  # 4 tiles of d = 4 per wave
+                    (entry(400, 2, f32, L.CHYM_KERNEL_SLAB, 16), L.CHYM_EUNSUPPORTED)):  # not built in float32
+        assert lib.chym_plan_set(ctypes.byref(bad)) == rc
+    for line in ("50 4 1 1 5 4 0.0\n", "7 3 1 1 5 8 0.0\n", "25 2 3 1 5 16 0.0\n"):
+        f = tmp_path / "bad.txt"
+        f.write_text(line)
+        assert lib.chym_plan_load(str(f).encode()) == L.CHYM_EINVAL, line
+
+
 def test_coupling_storage_sizes_and_quantizer_validation():
     lib = L.load()
     b = ctypes.c_size_t(0)

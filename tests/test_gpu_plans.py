@@ -126,3 +126,61 @@ def test_autotune_installs_a_candidate(tmp_path):
     api.chym_plan_load(path)
     assert api.chym_plan_get(48, 2, "f32", torch.int8)["kernel"] == best["kernel"]
     api.chym_plan_set(48, 2, "f32", torch.int8, api.CHYM_KERNEL_AUTO)
+
+
+@pytest.mark.parametrize("n,d,kind", [(200, 4, "sk"), (200, 2, "gauss"), (400, 3, "sk"), (520, 2, "sk"),
+                                      (800, 2, "gauss"), (500, 4, "gauss")])
+def test_streamed_j_block_sizes_bit_exact(n, d, kind):
+    """The streamed-J kernel's blocks of 8 and of 16 wavefronts (1, 2 or 4
+    row tiles each) give the same results bit for bit, in single calls and
+    in a batch with ragged replica counts; +-1 couplings take the E4M3 J
+    stream, Gaussian bf16 couplings the bf16 one (sixteen-wavefront blocks
+    hold 1, 2 or, at d <= 2, 4 row tiles per wavefront)."""
+    g = np.random.default_rng(n + d)
+    Jh = synth.sk_pm1(n, 61, n) if kind == "sk" else synth.gaussian_j(n, 61, n).astype(np.float32)
+    J = to_dev(Jh) if kind == "sk" else to_dev(Jh).to(torch.bfloat16)
+    eps = float(np.float32(0.5 / synth.lambda_max(Jh.astype(np.float64))))
+    steps = 120
+    al = to_dev(synth.anneal_schedule(steps, d)[0])
+    specs = [40, 16, 3]
+    x0s = [g.standard_normal((n, r, d)).astype(np.float32) * 1e-2 for r in specs]
+    pumps = [to_dev(g.uniform(0.5, 2.0, r).astype(np.float32)) for r in specs]
+
+    def run(waves):
+        api.chym_plan_set(n, d, "bf16", J.dtype if kind != "sk" else torch.int8, api.CHYM_KERNEL_SLAB, waves)
+        singles = []
+        for x0, p in zip(x0s, pumps):
+            x = to_dev(x0)
+            ws = torch.empty(api.chym_integrate_workspace_size(J, x, precision="bf16") + 256, dtype=torch.uint8,
+                             device="cuda")
+            api.chym_integrate(J, p, x, al, eps=eps, btil=1.0, eta=2e-4, dt=0.01, steps=steps, precision="bf16",
+                               workspace=ws)
+            singles.append(x)
+        tasks = [dict(J=J, pump=p, x=to_dev(x0), alpha=al, steps=steps, precision="bf16", eps=eps, btil=1.0, eta=2e-4,
+                      dt=0.01) for x0, p in zip(x0s, pumps)]
+        b = api.chym_batch_create(tasks)
+        b.launch()
+        torch.cuda.synchronize()
+        b.destroy()
+        return [x.cpu().numpy() for x in singles], [t["x"].cpu().numpy() for t in tasks]
+
+    s8, b8 = run(8)
+    s16, b16 = run(16)
+    api.chym_plan_set(n, d, "bf16", J.dtype if kind != "sk" else torch.int8, api.CHYM_KERNEL_AUTO)
+    for a, b_, c, e in zip(s8, s16, b8, b16):
+        assert np.array_equal(a, b_) and np.array_equal(a, c) and np.array_equal(a, e)
+        assert np.isfinite(a).all()
+
+
+def test_autotune_streamed_j_shape():
+    """The autotuner times the streamed-J block sizes of a variant beyond the
+    register-resident limit and installs the faster."""
+    best, cands = api.chym_plan_autotune(400, 4, "bf16", torch.int8, replicas=2048, steps=40)
+    assert sorted(c["waves"] for c in cands) == [8, 16]
+    assert all(c["kernel"] == api.CHYM_KERNEL_SLAB and c["ms"] > 0 for c in cands)
+    assert best["kernel"] == api.CHYM_KERNEL_SLAB and best["ms"] == min(c["ms"] for c in cands)
+    assert api.chym_plan_get(400, 4, "bf16", torch.int8)["waves"] == best["waves"]
+    best32, cands32 = api.chym_plan_autotune(400, 2, "f32", torch.int8, replicas=1024, steps=20)
+    assert [c["waves"] for c in cands32] == [8]  # sixteen-wavefront blocks are built for the bf16 form only
+    for nn, dd, pp in ((400, 4, "bf16"), (400, 2, "f32")):
+        api.chym_plan_set(nn, dd, pp, torch.int8, api.CHYM_KERNEL_AUTO)
