@@ -44,8 +44,7 @@ PEAK_FP32_VECTOR_UNPACKED_TFLOPS = 78.6
 TRAFFIC_SOURCE = ("profiles/integrate_persistent_sk100_d23_f32.md: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE "
                   "of this kernel on this workload, scaled by the same counters on a copy of known size; "
                   "not measured in this run")
-TRAFFIC = {("k_integrate_persistent<7, 3, 3, 1, false>", 100, 1000, 2000): 4.921e9,
-           ("k_integrate_persistent_lds<7, 3, 3, 1, 2>", 100, 1000, 2000): 1.031e10}
+TRAFFIC = {("k_integrate_persistent_lds<7, 3, 3, 1, 2>", 100, 1000, 2000): 9.70e9}
 
 
 def kernel_name(tiles, d, precision, plan):

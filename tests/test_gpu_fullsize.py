@@ -15,8 +15,11 @@ one float32 ulp (relative 2^-24, random signs) at step 0, T/4, T/2 or
 products, error within ~sqrt(N) = 10 ulp) and the update (a few ulp): at
 most 16 ulp per step; such errors from the T steps add like a random walk,
 each growing at most like a one-ulp perturbation, so the bar is
-max(1e-4, 16 sqrt(T) s).  The sign readout and the integer Ising energies
-of the sampled runs are exact."""
+max(1e-4, 16 sqrt(T) s), clamped at 1e-2: however sensitive a run, its
+final amplitudes must match within 1e-2, so the derived bar never stops
+bounding anything; and at least three quarters of the sampled runs must meet
+1e-4 outright.  The sign readout and the integer
+Ising energies of the sampled runs are exact."""
 import argparse
 
 import numpy as np
@@ -49,7 +52,7 @@ def test_default_workload_sampled_against_oracle():
     sizes = [n * R * d for d in wl["dims"]]
     per_inst = sum(sizes)
     reps = np.array([0, 57, 999, 1000, 1342, 1999])  # pumps 0.5 .. 2.0 (replica // 100 = pump index)
-    worst = 0.0
+    worst, worst_bar, within, total = 0.0, 0.0, 0, 0
     for i in (0, 411, 999):
         outs = {d: o for (ii, d, o) in wl["outs"] if ii == i}
         for di, d in enumerate(wl["dims"]):
@@ -67,12 +70,15 @@ def test_default_workload_sampled_against_oracle():
                 kp = dict(kw, steps=steps - k, start_step=k)
                 xp = oracle.ode_run(wl["Js"][i], wl["pumps"][reps], xk * (1.0 + sgn * 2.0 ** -24), **kp)
                 sens = np.maximum(sens, np.abs(xp - xo).max(axis=(0, 2)))  # per sampled run
-            bar = np.maximum(1e-4, 16.0 * np.sqrt(steps) * sens)
+            bar = np.minimum(np.maximum(1e-4, 16.0 * np.sqrt(steps) * sens), 1e-2)
             err = np.abs(xg - xo).max(axis=(0, 2))
             fmt = {"float_kind": lambda v: f"{v:.1e}"}
             print(f"instance {i} d={d}: |x_gpu - x_oracle| per run {np.array2string(err, formatter=fmt)}, "
                   f"bar {np.array2string(bar, formatter=fmt)}")
             worst = max(worst, float((err / bar).max()))
+            worst_bar = max(worst_bar, float(bar.max()))
+            within += int((err <= 1e-4).sum())
+            total += err.size
             assert np.all(err <= bar), (i, d, err, bar)
             sig = unpack_spins(outs[d]["spins"][reps].cpu().numpy(), n)
             np.testing.assert_array_equal(sig, oracle.readout(xg))
@@ -82,7 +88,9 @@ def test_default_workload_sampled_against_oracle():
             np.testing.assert_allclose(outs[d]["e_hs"][reps].cpu().numpy(), oracle.hs_energy(wl["Js"][i], xg),
                                        rtol=1e-12, atol=1e-9)
             assert not outs[d]["diverged"].cpu().numpy().any()
-    print(f"largest |x_gpu - x_oracle| / bar over the samples: {worst:.2f}")
+    print(f"largest |x_gpu - x_oracle| / bar over the samples: {worst:.2f}; largest bar {worst_bar:.2e}; "
+          f"{within} of {total} sampled runs within 1e-4")
+    assert within >= 0.75 * total, (within, total)
     for p in list(wl["plans"].values()) + [wl["score_plan"]]:
         p.destroy()
 
