@@ -2,10 +2,10 @@
 
 A run of the machine is cheap to start and expensive to finish.  At a
 decision point early in the run (default: after the first 10 % of the
-Euler steps, with features sampled at 8 checkpoints, see ``chym_features``
-in include/chym.h) a small network scores every run; each pump's batch of
-runs keeps its highest-scored fraction, integrates only those to the end,
-and starts fresh runs instead of the others.  Every kept run is still
+Euler steps) a small network scores every run from features of its first
+part (see ``chym_features`` in include/chym.h); each pump's batch of runs
+keeps its highest-scored fraction, integrates only those to the end, and
+starts fresh runs instead of the others.  Every kept run is still
 integrated to the end and judged by its exact Ising energy, so the method's
 answers are unchanged; only the cost per success changes.  Keeping every
 run is the plain method, always a candidate when the policy is chosen.
@@ -14,8 +14,14 @@ Runs of one problem and pump converge to the same hyperspin configuration
 up to a rotation; what tells them apart early is the orientation of the
 first component, the one the anneal keeps.  The features describe it
 (Rayleigh quotient, Ising energy of its signs, its share of the norm, sign
-flips) and are standardized within each pump's batch of runs, since the
-policy ranks runs within such a batch.
+flips) at 7 checkpoints over the first part, and once more for a coarse
+continuation: the decision-point state integrated through the rest of the
+schedule with SURROGATE_STRIDE times the step (every SURROGATE_STRIDE-th
+annealing weight), about 1/SURROGATE_STRIDE of the rest's cost.  From a
+given state the rest of a run is close to deterministic, so the coarse
+continuation mostly ends where the run will; the features are standardized
+within each pump's batch of runs, since the policy ranks runs within such a
+batch.
 
 All arithmetic runs in libchym's kernels: the integrator, the features,
 their standardization, the network's forward, backward and Adam kernels,
@@ -48,8 +54,9 @@ import torch
 from . import _lib as L
 from . import api, stats, synth
 
-N_CKPT = 8
+N_CKPT = 8            # feature slots: N_CKPT - 1 trajectory checkpoints, then the coarse continuation
 N_FEAT = L.CHYM_FEATURES
+SURROGATE_STRIDE = 20  # step multiple of the coarse continuation
 
 
 # ---------------------------------------------------------------- network
@@ -142,8 +149,8 @@ class RestartNet:
 
 
 # ------------------------------------------------------------- simulation
-def checkpoints(steps, frac=0.1, n_ckpt=N_CKPT):
-    """The n_ckpt feature checkpoints (step counts) spread over the first
+def checkpoints(steps, frac=0.1, n_ckpt=N_CKPT - 1):
+    """The n_ckpt trajectory checkpoints (step counts) spread over the first
     `frac` of the run; the last one is the decision point."""
     k_feat = max(n_ckpt, int(round(frac * steps)))
     return [int(round(k_feat * (c + 1) / n_ckpt)) for c in range(n_ckpt)]
@@ -177,10 +184,12 @@ class Problem:
         api.chym_ising_energy(self.J, spins, e)
         return e
 
-    def features(self, pump, x, group, precision, ws, frac=0.1):
+    def features(self, pump, x, group, precision, ws, frac=0.1, stride=SURROGATE_STRIDE):
         """Phase one of a run: integrate x to the decision point, taking the
-        features at the checkpoints; returns them standardized within each
-        pump batch of `group` runs, and the decision step."""
+        features at the trajectory checkpoints, then those of the coarse
+        continuation of a copy of the decision-point state (last slot);
+        returns them standardized within each pump batch of `group` runs,
+        and the decision step."""
         r = x.shape[1]
         feats = torch.zeros((r, N_FEAT), dtype=torch.float32, device=self.dev)
         words = api.chym_sign_words(x)
@@ -189,6 +198,12 @@ class Problem:
             self.integrate(pump, x, k, kc, precision, ws)
             api.chym_features(self.J, x, words, feats, c)
             k = kc
+        xs = x.clone()
+        al = self.alpha[k::stride].contiguous()  # every stride-th annealing weight of the rest
+        if al.shape[0]:
+            api.chym_integrate(self.J, pump, xs, al, steps=al.shape[0], start_step=0, precision=precision,
+                               workspace=ws, **dict(self.prm, dt=self.prm["dt"] * stride))
+        api.chym_features(self.J, xs, words, feats, N_CKPT - 1)
         api.chym_feature_standardize(feats, group, out=feats)
         return feats, k
 
@@ -351,7 +366,7 @@ def validation_score(tts, base):
     return float(np.exp(np.mean(np.log(tts[ok]))))
 
 
-KEEP_GRID = (1.0, 0.85, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2)
+KEEP_GRID = (1.0, 0.7, 0.5, 0.3, 0.2, 0.1, 0.05, 0.02, 0.01)
 
 
 def choose_keep(insts, egs, net, grid=KEEP_GRID):
@@ -512,7 +527,8 @@ def experiment(n_train=50, n_val=10, n_test=20, n=200, d=3, n_ic=1000, n_pumps=2
             for m in ("plain_f32", "bf16", "bf16_learned", "bf16_learned_model")}
     report = dict(
         workload=f"SK +-1 N={n}, D={d}, {n_pumps} pumps, {steps} Euler steps, decision after {frac:.0%} of the steps "
-                 f"(8 feature checkpoints); {n_train} training instances x {n_ic} runs per pump, {n_val} validation "
+                 f"({N_CKPT - 1} feature checkpoints and a continuation at {SURROGATE_STRIDE}x the step); "
+                 f"{n_train} training instances x {n_ic} runs per pump, {n_val} validation "
                  f"instances x {val_ic}; {n_test} held-out instances, each run at its 3 best pumps (pilot of "
                  f"{pilot_ic} runs per pump) from the same {eval_ic} initial states per pump by every method",
         trajectories_train=int(feats.shape[0]), positives_train=float(labels.mean().item()),

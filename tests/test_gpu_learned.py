@@ -124,15 +124,15 @@ def test_mlp_training_learns_a_rule():
 
 
 def test_restart_policy_executed_on_simulated_trajectories():
-    """Train on trajectories the integrator generates, choose the kept
-    fraction on validation instances, and run the policy for real on
-    held-out instances against the plain forms from the same initial
-    states: the kept runs follow exactly the trajectories they have in the
-    plain BF16 run, a restarting policy spends less GPU time per attempt,
-    and BF16 less than FP32.  A gain in time to 99% success is not asserted:
-    at this size the early features rank the runs of a pump batch only
-    weakly (within-batch AUC about 0.5-0.6), and at the full held-out size
-    the measured ratio to BF16 alone has a 95% interval that contains 1."""
+    """Train on trajectories the integrator generates, choose the epoch and
+    the kept fraction on validation instances, and run the policy for real
+    on held-out instances against the plain forms from the same initial
+    states: the chosen policy restarts runs (keeping every run, the plain
+    method, is a candidate, and must not win); the kept runs follow exactly
+    the trajectories they have in the plain BF16 run; the policy solves the
+    same held-out instances as BF16 alone, and on every one of them reaches
+    99 % success in less GPU time than BF16 alone, which in turn takes less
+    than the plain FP32 form per attempt."""
     from paper_2308_02329_amd import learned
 
     rep = learned.experiment(n_train=12, n_val=4, n_test=3, n=200, n_ic=1000, n_pumps=20, steps=20000, epochs=3,
@@ -140,10 +140,11 @@ def test_restart_policy_executed_on_simulated_trajectories():
     print({k: v for k, v in rep.items() if k not in ("per_instance", "loss_history")})
     assert rep["kept_runs_match_plain"]
     assert rep["positives_train"] > 0
+    assert rep["chosen_epoch"] >= 0 and rep["keep_fraction"] < 1.0  # the network is used
+    assert rep["same_instances_solved"] and rep["instances_solved"]["bf16"] >= 1
+    for r in rep["per_instance"]:
+        t = r["tts99_ms"]
+        if np.isfinite(t["bf16"]):
+            assert t["bf16_learned"] < t["bf16"], (r["index"], t)
     c = rep["ms_per_attempt"]
-    if rep["keep_fraction"] < 1.0:
-        # restarting saves GPU time per attempt (the cost model's error is reported, not bounded: the
-        # compacted second phase of a small batch does not fill the chip)
-        assert c["bf16_learned"] < c["bf16"]
-    # the BF16 form's throughput advantage over the plain FP32 form
-    assert c["bf16"] < c["plain_f32"]
+    assert c["bf16_learned"] < c["bf16"] < c["plain_f32"]
