@@ -69,7 +69,8 @@ bool slab_shape_exists(int tiles, int d, int xs, int js, int waves) {
 // be a set of E4M3 values times one power of two (the row scale, chosen as
 // in the FP8 quantizer), checked element by element; FP8 storage always
 // qualifies.  Writes the header flag and the row scales.  Run by one block
-// of 1024 threads: wavefront w takes rows w, w + 16, ...
+// of 1024 threads: wavefront w takes rows w, w + 16, ...  (Batches only: a
+// single problem's staging is always bf16, k_stage_bf16_header.)
 __device__ __forceinline__ void stage_prep_block(const IntegArgs &a, int tiles, unsigned char *__restrict__ stage) {
     __shared__ int s_ok;
     if (threadIdx.x == 0) s_ok = 1;
@@ -113,8 +114,9 @@ __device__ __forceinline__ void stage_prep_block(const IntegArgs &a, int tiles, 
     if (threadIdx.x == 0) *reinterpret_cast<int *>(stage) = (a.j_dtype == CHYM_J_FP8) ? 1 : s_ok;
 }
 
-__global__ __launch_bounds__(1024) void k_stage_prep(IntegArgs a, int tiles, unsigned char *__restrict__ stage) {
-    stage_prep_block(a, tiles, stage);
+// A single problem's staging header: bf16 fragments (flag 0).
+__global__ void k_stage_bf16_header(unsigned char *__restrict__ stage) {
+    if (threadIdx.x == 0) *reinterpret_cast<int *>(stage) = 0;
 }
 
 // The same for the tasks list[0 .. n) of a batch, one block each.
@@ -150,7 +152,7 @@ hipError_t launch_stage_jfrag(const IntegArgs &a, int js, void *out, hipStream_t
     if (js == 3) {
         hipLaunchKernelGGL(k_stage_jfrag<3>, dim3(grid), dim3(256), 0, stream, a, ncp, stage);
     } else {
-        hipLaunchKernelGGL(k_stage_prep, dim3(1), dim3(1024), 0, stream, a, nt, stage);
+        hipLaunchKernelGGL(k_stage_bf16_header, dim3(1), dim3(64), 0, stream, stage);
         hipLaunchKernelGGL(k_stage_jfrag<1>, dim3(grid), dim3(256), 0, stream, a, ncp, stage);
     }
     return hipGetLastError();

@@ -17,11 +17,12 @@
 // kernel, so the two kernels accumulate every G in the same order and give
 // identical results.  J is staged once per problem into the caller's
 // workspace as A fragments in that order and is streamed from L2 every step
-// (at this size it does not fit in LDS).  When every row of J is a set of
-// E4M3 values times one power of two (+-1 couplings in any storage, FP8
-// storage always), J is staged as one byte per coupling and widened to bf16
-// in registers (v_cvt_scalef32_pk_bf16_fp8, exact); this halves the L2
-// traffic, which is what bounds the kernel at N ~ 1000.
+// (at this size it does not fit in LDS).  In batches, when every row of J
+// is a set of E4M3 values times one power of two (+-1 couplings in any
+// storage, FP8 storage always), J is staged as one byte per coupling and
+// widened to bf16 in registers (v_cvt_scalef32_pk_bf16_fp8, exact); this
+// halves the L2 footprint and traffic of the many couplings a batch streams
+// at once.  A single problem's J stays bf16 (k_integrate_slab).
 //
 // Per step: for each group of four owned tiles, accumulate G over all
 // chunks (the J fragments of the next chunk are fetched while the current
@@ -126,7 +127,7 @@ __device__ __forceinline__ void slab_write_tile(const float (&xt)[D][4], int I, 
 // one: J does not change between steps).  Every refill is a load, so a slot's
 // next value is always the register its load writes, and the prefetch crosses
 // group and step boundaries.
-template <int D, int XS, int JS, int TPW, bool F8, int W>
+template <int D, int XS, int JS, int TPW, bool F8, int W, int RDB = 2>
 __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, const unsigned char *__restrict__ stage,
                                                int ncp, bf16x8 *lb) {
     // tiles accumulated together (register budget per lane: 128 at four
@@ -135,8 +136,8 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
     constexpr int GS = GS0 < TPW ? GS0 : TPW;
     constexpr int NG = TPW / GS;        // groups of owned tiles
     // chunks of J fragments in flight: E4M3 fragments take two registers
-    // per tile, bf16 ones four per term
-    constexpr int RD = F8 ? 4 : 2;
+    // per tile, bf16 ones four per term (RDB chunks)
+    constexpr int RD = F8 ? 4 : RDB;
     static_assert(RD <= kSlabRingChunks, "the staging pads kSlabRingChunks chunks past the last tile");
     // PF: the state operand of the next chunk is read from LDS while the
     // current chunk's products run, where its registers fit
@@ -441,11 +442,20 @@ __device__ __forceinline__ void slab_run(const IntegArgs &a, int rep0, const uns
 }
 
 // Column slabs of one problem: block b integrates replicas 16 b .. 16 b + 15.
+// A single problem's J is read by every CU from the same L2 lines, so it is
+// staged as bf16 fragments (no E4M3 path: the conversion per value and
+// product on the vector ALU costs more than the halved L2 bytes save there,
+// measured 3-10% at N = 200 - 1000); with the registers that frees, blocks of
+// eight wavefronts keep four chunks of the bf16 stream in flight (measured
+// 1-5% faster at N = 800 - 1000).  Batches, whose tasks stream many distinct
+// couplings through L2 at once, take the E4M3 path where it applies
+// (k_integrate_slab_persistent).
 template <int D, int XS, int JS, int TPW, int W>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W / 4)))
 void k_integrate_slab(IntegArgs a, const unsigned char *__restrict__ stage, int ncp) {
     extern __shared__ __align__(16) unsigned char smem[];
-    slab_run<D, XS, JS, TPW, W>(a, blockIdx.x * 16, stage, ncp, reinterpret_cast<bf16x8 *>(smem));
+    constexpr int RDB = (W == 8 && XS == 1 && JS == 1) ? 4 : 2;
+    integrate_slab<D, XS, JS, TPW, false, W, RDB>(a, blockIdx.x * 16, stage, ncp, reinterpret_cast<bf16x8 *>(smem));
 }
 
 // Persistent form: blocks pop (task, column slab) items; jfs[task] is the
