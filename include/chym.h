@@ -336,7 +336,12 @@ int chym_solve_batched(const chym_task *tasks, int32_t n_tasks, void *workspace,
  * cross-entropy; parameters in one block of CHYM_MLP_PARAMS values in the
  * order W1 [128][32], b1 [128], W2 [128][128], b2 [128], w3 [128], b3, held
  * as a float32 master copy and a bf16 copy (bf16 bit patterns) that the
- * forward and backward passes read.
+ * forward and backward passes read.  The hidden layers run on the matrix
+ * cores: each one's input (the features, then the first layer's
+ * activations) is rounded to bf16 (nearest even) and its products summed in
+ * float32 with its float32 bias; the output layer is a float32 dot product.
+ * The backward pass takes each rounding as the identity (straight-through):
+ * a layer's weight gradient uses its rounded input.
  */
 #define CHYM_FEATURES 32
 #define CHYM_MLP_PARAMS 20865
@@ -374,7 +379,8 @@ int chym_gather_replicas(int32_t n, int32_t d, int32_t r_src, const float *x_src
 int chym_mlp_scratch_floats(int32_t batch, size_t *floats);
 
 /* Forward pass: logit [batch]; h1, h2 [batch][128] (post-ReLU activations,
- * may be NULL unless a backward pass follows). */
+ * h1 as rounded to bf16 for the second layer; may be NULL unless a backward
+ * pass follows). */
 int chym_mlp_forward(int32_t batch, const float *features, const uint16_t *w_bf16, float *logit, float *h1, float *h2,
                      chym_stream_t stream);
 

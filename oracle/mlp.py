@@ -5,7 +5,11 @@ Network: 32 -> 128 -> 128 -> 1, ReLU, sigmoid output, mean binary
 cross-entropy; parameters in one vector ordered W1 [128][32], b1 [128],
 W2 [128][128], b2 [128], w3 [128], b3.  Written from the definitions
 (matrix products, chain rule); pinned by finite differences and closed forms
-in tests/test_oracle_mlp.py.
+in tests/test_oracle_mlp.py.  forward_bf16 / grad_bf16 are the same network
+with each hidden layer's input rounded to bf16 (the operand precision of the
+matrix cores), differentiated straight through the roundings; pinned by their
+reduction to forward / grad where every rounding is exact and by a case
+rounded by hand.
 
 Features (per replica and checkpoint), about the first component x_{p,1}
 (the one the anneal keeps and the readout reads): its Rayleigh quotient per
@@ -51,19 +55,50 @@ def forward(x, w):
     return z, h1, h2
 
 
+def forward_bf16(x, w):
+    """The network as the matrix cores evaluate it: each hidden layer's input
+    (the features, then the first layer's activations) rounded to bf16, the
+    rest exact.  Returns logit [B], the rounded h1 [B][128] and h2 [B][128]."""
+    p = unpack(w)
+    x = bf16_round(x)
+    h1 = bf16_round(np.maximum(x @ p["W1"].T + p["b1"], 0.0))
+    h2 = np.maximum(h1 @ p["W2"].T + p["b2"], 0.0)
+    z = h2 @ p["w3"] + p["b3"][0]
+    return z, h1, h2
+
+
+def _bce(z, y):
+    return float(np.mean(np.logaddexp(0.0, z) - np.asarray(y, dtype=np.float64) * z))
+
+
 def loss(x, y, w):
     """Mean binary cross-entropy of sigmoid(logit) against labels y."""
-    z, _, _ = forward(x, w)
-    y = np.asarray(y, dtype=np.float64)
-    return float(np.mean(np.logaddexp(0.0, z) - y * z))
+    return _bce(forward(x, w)[0], y)
+
+
+def loss_bf16(x, y, w):
+    """The mean binary cross-entropy of forward_bf16's logits."""
+    return _bce(forward_bf16(x, w)[0], y)
 
 
 def grad(x, y, w):
     """Gradient of the mean BCE by the chain rule."""
-    p = unpack(w)
     x = np.asarray(x, dtype=np.float64)
+    return _chain(x, y, unpack(w), *forward(x, w))
+
+
+def grad_bf16(x, y, w):
+    """The chain rule through forward_bf16 with each rounding taken as the
+    identity (its derivative almost everywhere is zero, so this is the
+    straight-through gradient): the weight gradients of a layer use its
+    rounded input."""
+    return _chain(bf16_round(x), y, unpack(w), *forward_bf16(x, w))
+
+
+def _chain(x, y, p, z, h1, h2):
+    """Gradient of the mean BCE given the layer inputs x, h1 and the
+    activations h2 and logits z of a forward pass."""
     y = np.asarray(y, dtype=np.float64)
-    z, h1, h2 = forward(x, w)
     b = x.shape[0]
     dz = (1.0 / (1.0 + np.exp(-z)) - y) / b
     g = {"w3": h2.T @ dz, "b3": np.array([dz.sum()])}

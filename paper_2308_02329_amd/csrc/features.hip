@@ -15,8 +15,12 @@
 //
 // MLP: 32 -> 128 -> 128 -> 1, ReLU, sigmoid output, binary cross-entropy.
 // Weights are kept as float32 master copies (updated by Adam) and as a bf16
-// copy that the forward and backward passes use; activations and
-// accumulations are float32.
+// copy that the forward and backward passes use.  The two hidden layers run
+// on the matrix cores in bf16 with float32 accumulation: a layer's input
+// (the features, then the first layer's activations) is rounded to bf16
+// (nearest even), its bias added in float32; the output layer is a float32
+// dot product.  The backward pass differentiates that network (the
+// weight gradients use the rounded layer inputs) in float32.
 #include <algorithm>
 
 #include "chym_internal.h"
@@ -292,37 +296,112 @@ static_assert(kParams == CHYM_MLP_PARAMS && kF == CHYM_FEATURES, "parameter bloc
 
 __device__ __forceinline__ float bf(const __bf16 *w, int i) { return (float)w[i]; }
 
-// Forward pass of one sample per thread; the bf16 weights are staged in LDS
-// as float32 once per block.  Writes the logit, and the hidden activations
-// when h1/h2 are given (for the backward pass).
-__global__ __launch_bounds__(128) void k_mlp_forward(int batch, const float *__restrict__ feat,
+typedef __attribute__((ext_vector_type(2))) float mlp_f32x2;
+typedef __attribute__((ext_vector_type(2))) __bf16 mlp_bf16x2;
+typedef __attribute__((ext_vector_type(4))) __bf16 mlp_bf16x4;
+
+__device__ __forceinline__ mlp_bf16x2 mlp_pack(float a, float b) {
+    return __builtin_convertvector((mlp_f32x2){a, b}, mlp_bf16x2);
+}
+
+__device__ __forceinline__ bf16x8 mlp_join(mlp_bf16x2 a, mlp_bf16x2 b, mlp_bf16x2 c, mlp_bf16x2 d) {
+    const mlp_bf16x4 lo = __builtin_shufflevector(a, b, 0, 1, 2, 3);
+    const mlp_bf16x4 hi = __builtin_shufflevector(c, d, 0, 1, 2, 3);
+    return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+__device__ __forceinline__ mlp_bf16x4 mlp_load4(const __bf16 *p) { return *reinterpret_cast<const mlp_bf16x4 *>(p); }
+
+// Forward pass on the matrix cores, one wavefront per 16 samples (the batch
+// tail padded with zero features, its outputs not written).  Both hidden
+// layers are computed transposed, H^T = W X^T, with v_mfma_f32_16x16x32_bf16:
+// the weights are the A operand (16 units x 32 inputs per fragment), the
+// layer input the B operand (32 inputs x 16 samples), and lane (j, g) of a
+// 16 x 16 result holds units 4 g + v of sample j.  The second layer's K
+// chunk c is the rows lane (j, g) already holds in result tiles 2c and 2c+1
+// (slot s: unit 32 c + 16 (s >> 2) + 4 g + (s & 3)), with W2's columns read in
+// that order, so its B operand comes from the lane's own registers.  Writes
+// the logit, and h1 (the rounded first-layer activations, the second layer's
+// input) and h2 when given, [batch][128] each.
+__global__ __launch_bounds__(256) void k_mlp_forward(int batch, const float *__restrict__ feat,
                                                      const __bf16 *__restrict__ wb, float *__restrict__ logit,
                                                      float *__restrict__ h1, float *__restrict__ h2) {
-    extern __shared__ float w[];  // kParams floats
-    for (int i = threadIdx.x; i < kParams; i += blockDim.x) w[i] = bf(wb, i);
-    __syncthreads();
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= batch) return;
-    float in[kF];
+    const int lane = threadIdx.x & 63;
+    const int j = lane & 15, g = lane >> 4;
+    const int s0 = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16;
+    if (s0 >= batch) return;  // wave-uniform
+    const int smp = s0 + j;
+    const bool ok = smp < batch;
+    // layer 1: B operand = features 8 g .. 8 g + 7 of sample j, rounded to bf16
+    bf16x8 bx;
+    {
+        float v[8];
 #pragma unroll
-    for (int i = 0; i < kF; ++i) in[i] = feat[(size_t)s * kF + i];
-    float a1[kH1];
-    for (int o = 0; o < kH1; ++o) {
-        float acc = w[kOffB1 + o];
+        for (int s = 0; s < 8; ++s) v[s] = ok ? feat[(size_t)smp * kF + 8 * g + s] : 0.0f;
+        bx = mlp_join(mlp_pack(v[0], v[1]), mlp_pack(v[2], v[3]), mlp_pack(v[4], v[5]), mlp_pack(v[6], v[7]));
+    }
+    f32x4 a1[8];
 #pragma unroll
-        for (int i = 0; i < kF; ++i) acc = fmaf(w[kOffW1 + o * kF + i], in[i], acc);
-        a1[o] = acc > 0.0f ? acc : 0.0f;
-        if (h1) h1[(size_t)s * kH1 + o] = a1[o];
+    for (int I = 0; I < 8; ++I) {
+        const mlp_bf16x4 b = mlp_load4(wb + kOffB1 + 16 * I + 4 * g);
+        a1[I] = f32x4{(float)b[0], (float)b[1], (float)b[2], (float)b[3]};
+        // A fragment: W1 row 16 I + j, inputs 8 g .. 8 g + 7
+        const bf16x8 aw = *reinterpret_cast<const bf16x8 *>(wb + kOffW1 + (16 * I + j) * kF + 8 * g);
+        a1[I] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx, a1[I], 0, 0, 0);
     }
-    float z = w[kOffB3];
-    for (int o = 0; o < kH2; ++o) {
-        float acc = w[kOffB2 + o];
-        for (int i = 0; i < kH1; ++i) acc = fmaf(w[kOffW2 + o * kH1 + i], a1[i], acc);
-        const float a2 = acc > 0.0f ? acc : 0.0f;
-        if (h2) h2[(size_t)s * kH2 + o] = a2;
-        z = fmaf(w[kOffW3 + o], a2, z);
+    // ReLU, then the rounded activations (the second layer's input)
+    mlp_bf16x2 hp[8][2];
+#pragma unroll
+    for (int I = 0; I < 8; ++I) {
+        float r[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) r[v] = a1[I][v] > 0.0f ? a1[I][v] : 0.0f;
+        hp[I][0] = mlp_pack(r[0], r[1]);
+        hp[I][1] = mlp_pack(r[2], r[3]);
+        if (h1 && ok) {
+            float4 o;
+            o.x = (float)hp[I][0][0];
+            o.y = (float)hp[I][0][1];
+            o.z = (float)hp[I][1][0];
+            o.w = (float)hp[I][1][1];
+            *reinterpret_cast<float4 *>(h1 + (size_t)smp * kH1 + 16 * I + 4 * g) = o;
+        }
     }
-    logit[s] = z;
+    // layer 2
+    f32x4 a2[8];
+#pragma unroll
+    for (int I = 0; I < 8; ++I) {
+        const mlp_bf16x4 b = mlp_load4(wb + kOffB2 + 16 * I + 4 * g);
+        a2[I] = f32x4{(float)b[0], (float)b[1], (float)b[2], (float)b[3]};
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const bf16x8 bh = mlp_join(hp[2 * c][0], hp[2 * c][1], hp[2 * c + 1][0], hp[2 * c + 1][1]);
+#pragma unroll
+        for (int I = 0; I < 8; ++I) {
+            const __bf16 *row = wb + kOffW2 + (16 * I + j) * kH1 + 32 * c + 4 * g;
+            const mlp_bf16x4 lo = mlp_load4(row), hi = mlp_load4(row + 16);
+            const bf16x8 aw = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+            a2[I] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bh, a2[I], 0, 0, 0);
+        }
+    }
+    // ReLU and the output layer: float32 dot with w3 over the lane's units,
+    // then over the four lanes of the sample
+    float part = 0.0f;
+#pragma unroll
+    for (int I = 0; I < 8; ++I) {
+        const mlp_bf16x4 w3 = mlp_load4(wb + kOffW3 + 16 * I + 4 * g);
+        float r[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            r[v] = a2[I][v] > 0.0f ? a2[I][v] : 0.0f;
+            part = fmaf((float)w3[v], r[v], part);
+        }
+        if (h2 && ok) *reinterpret_cast<float4 *>(h2 + (size_t)smp * kH2 + 16 * I + 4 * g) = float4{r[0], r[1], r[2], r[3]};
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    if (g == 0 && ok) logit[smp] = (float)wb[kOffB3] + part;
 }
 
 // Backward pass of the mean binary cross-entropy over the batch, in three
@@ -383,7 +462,8 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(int batch, const float *__res
     }
     for (int i = threadIdx.x; i < kNS * kF; i += blockDim.x) {
         const int a = i / kF, b = i % kF;
-        sx[a][b] = a < ns ? feat[(size_t)(s0 + a) * kF + b] : 0.0f;
+        // the first layer's input as the forward pass rounds it
+        sx[a][b] = a < ns ? (float)(__bf16)feat[(size_t)(s0 + a) * kF + b] : 0.0f;
     }
     for (int i = threadIdx.x; i < kNS; i += blockDim.x) sdz[i] = i < ns ? dzs[s0 + i] : 0.0f;
     __syncthreads();
@@ -449,12 +529,9 @@ int mlp_param_count() { return kParams; }
 hipError_t launch_mlp_forward(int batch, const float *feat, const void *wb, float *logit, float *h1, float *h2,
                               hipStream_t stream) {
     if (batch <= 0) return hipSuccess;
-    const int block = 128;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_forward),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(float) * kParams));
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mlp_forward, dim3((batch + block - 1) / block), dim3(block), sizeof(float) * kParams,
-                       stream, batch, feat, reinterpret_cast<const __bf16 *>(wb), logit, h1, h2);
+    const int waves = (batch + 15) / 16;  // 16 samples per wavefront, 4 wavefronts per block
+    hipLaunchKernelGGL(k_mlp_forward, dim3((waves + 3) / 4), dim3(256), 0, stream, batch, feat,
+                       reinterpret_cast<const __bf16 *>(wb), logit, h1, h2);
     return hipGetLastError();
 }
 

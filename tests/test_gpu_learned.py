@@ -80,18 +80,30 @@ def test_mlp_kernels_match_reference():
     h1 = torch.empty((b, 128), dtype=torch.float32, device="cuda")
     h2 = torch.empty((b, 128), dtype=torch.float32, device="cuda")
     logit = api.chym_mlp_forward(xd, wb, None, h1, h2)
-    z, rh1, rh2 = mlp.forward(x, wr)
-    np.testing.assert_allclose(logit.cpu().numpy(), z, rtol=1e-4, atol=1e-4)
-    np.testing.assert_allclose(h1.cpu().numpy(), rh1, rtol=1e-4, atol=1e-5)
+    z, rh1, rh2 = mlp.forward_bf16(x, wr)
+    # h1 is rounded to bf16 on both sides from sums taken in different orders
+    # (float32 on the matrix cores, float64 here): a sum within rounding error
+    # of a tie may land one bf16 step apart; everything else is equal
+    gh1 = h1.cpu().numpy()
+    step = np.where(rh1 > 0, 2.0 ** (np.floor(np.log2(np.where(rh1 > 0, rh1, 1.0))) - 7), 2.0 ** -133)
+    diff = np.abs(gh1 - rh1)
+    assert np.all(diff <= step) and np.count_nonzero(diff) <= 1e-3 * diff.size
+    # logit: float32 accumulation error, plus the effect of any h1 step apart,
+    # bounded through |w3|^T |W2|
+    p = mlp.unpack(wr)
+    reach = np.abs(p["w3"]) @ np.abs(p["W2"])
+    bound = 1e-4 + 1e-4 * np.abs(z) + diff @ reach
+    assert np.all(np.abs(logit.cpu().numpy() - z) <= bound)
+    np.testing.assert_allclose(h2.cpu().numpy(), rh2, rtol=1e-4, atol=1e-5 + (diff @ np.abs(p["W2"]).T).max())
     scratch = torch.empty(api.chym_mlp_scratch_floats(b), dtype=torch.float32, device="cuda")
     grad = torch.empty(mlp.PARAMS, dtype=torch.float32, device="cuda")
     loss = torch.empty(b, dtype=torch.float32, device="cuda")
     api.chym_mlp_backward(xd, yd, wb, logit, h1, h2, scratch, grad, loss)
-    gref = mlp.grad(x, y, wr)
+    gref = mlp.grad_bf16(x, y, wr)
     gg = grad.cpu().numpy()
     np.testing.assert_allclose(gg, gref, rtol=0, atol=2e-4 * np.abs(gref).max())
     assert np.corrcoef(gg, gref)[0, 1] > 0.99999
-    np.testing.assert_allclose(loss.cpu().numpy().mean(), mlp.loss(x, y, wr), rtol=1e-5)
+    np.testing.assert_allclose(loss.cpu().numpy().mean(), mlp.loss_bf16(x, y, wr), rtol=1e-5)
     # deterministic
     grad2 = torch.empty_like(grad)
     api.chym_mlp_backward(xd, yd, wb, logit, h1, h2, scratch, grad2, loss)
@@ -104,6 +116,28 @@ def test_mlp_kernels_match_reference():
     np.testing.assert_allclose(wd.cpu().numpy(), wn, rtol=1e-5, atol=1e-7)
     np.testing.assert_allclose(m.cpu().numpy(), mn, rtol=1e-6)
     assert not torch.equal(w0, wd)
+
+
+def test_mlp_forward_exact_where_rounding_is_exact():
+    # dyadic weights and features on a coarse grid: the first layer's sums are
+    # exact in float32, so both sides round the same values to bf16 and h1 is
+    # bit-identical; 16 * 3 + 5 samples span full and ragged wavefronts
+    g = np.random.default_rng(11)
+    b = 53
+    p = {"W1": g.integers(-2, 3, (128, 32)) / 2.0, "b1": g.integers(-64, 65, 128) / 64.0,
+         "W2": g.integers(-4, 5, (128, 128)) / 16.0, "b2": g.integers(-8, 9, 128) / 8.0,
+         "w3": g.integers(-4, 5, 128) / 16.0, "b3": np.array([0.25])}
+    w = mlp.pack(p).astype(np.float32)
+    x = (g.integers(-16, 17, (b, 32)) / 4.0).astype(np.float32)
+    wb = api.chym_to_bf16(to_dev(w))
+    h1 = torch.empty((b, 128), dtype=torch.float32, device="cuda")
+    h2 = torch.empty((b, 128), dtype=torch.float32, device="cuda")
+    logit = api.chym_mlp_forward(to_dev(x), wb, None, h1, h2)
+    z, rh1, rh2 = mlp.forward_bf16(x, w)
+    assert not np.array_equal(rh1, mlp.forward(x, w)[1])  # the rounding matters here
+    assert np.array_equal(h1.cpu().numpy(), rh1)
+    np.testing.assert_allclose(h2.cpu().numpy(), rh2, rtol=1e-5, atol=1e-4)
+    np.testing.assert_allclose(logit.cpu().numpy(), z, rtol=1e-5, atol=1e-4)
 
 
 def test_mlp_training_learns_a_rule():

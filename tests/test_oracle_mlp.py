@@ -129,3 +129,46 @@ def test_select_top_reference_against_brute_force():
         for i in chosen:
             for j in set(range(10)) - chosen:
                 assert key[i] > key[j] or (key[i] == key[j] and i < j)
+
+
+def test_bf16_network_reduces_to_exact_one_on_representable_values():
+    # small integers everywhere: every layer input and activation is a bf16
+    # value (integers up to 256), so the rounded network is the exact one
+    g = np.random.default_rng(5)
+    p = {"W1": g.integers(-1, 2, (128, 32)), "b1": g.integers(-2, 3, 128),
+         "W2": g.integers(-1, 2, (128, 128)) / 8.0, "b2": g.standard_normal(128),
+         "w3": g.standard_normal(128) * 0.1, "b3": np.array([0.3])}
+    w = mlp.pack(p)
+    x = g.integers(-3, 4, (9, 32)).astype(float)
+    y = (g.random(9) < 0.5).astype(float)
+    assert np.abs(x @ p["W1"].T + p["b1"]).max() <= 256
+    for a, b in zip(mlp.forward_bf16(x, w), mlp.forward(x, w)):
+        assert np.array_equal(a, b)
+    assert np.array_equal(mlp.grad_bf16(x, y, w), mlp.grad(x, y, w))
+    assert mlp.loss_bf16(x, y, w) == mlp.loss(x, y, w)
+
+
+def test_bf16_network_hand_rounded_case():
+    # one path x_0 -> h1_0 -> h2_0 -> z with unit weights:
+    # x_0 = 1 + 2^-9 rounds to 1 (half an ulp, ties to even);
+    # h1_0 = 1 + 2^-8 + 2^-10 rounds to 1 + 2^-7 (five eighths of an ulp up)
+    p = {name: np.zeros(shp) for name, shp in mlp.SHAPES}
+    p["W1"][0, 0] = 1.0
+    p["b1"][0] = 2.0 ** -8 + 2.0 ** -10
+    p["W2"][0, 0] = 1.0
+    p["w3"][0] = 1.0
+    w = mlp.pack(p)
+    x = np.zeros((1, 32))
+    x[0, 0] = 1 + 2.0 ** -9
+    z, h1, h2 = mlp.forward_bf16(x, w)
+    assert h1[0, 0] == 1 + 2.0 ** -7 and h2[0, 0] == 1 + 2.0 ** -7 and z[0] == 1 + 2.0 ** -7
+    assert mlp.forward(x, w)[0][0] == 1 + 2.0 ** -9 + 2.0 ** -8 + 2.0 ** -10
+    y = np.array([1.0])
+    gr = mlp.unpack(mlp.grad_bf16(x, y, w))
+    dz = 1 / (1 + math.exp(-(1 + 2.0 ** -7))) - 1
+    assert gr["b3"][0] == pytest.approx(dz, rel=1e-15)
+    assert gr["w3"][0] == pytest.approx(dz * (1 + 2.0 ** -7), rel=1e-15)
+    assert gr["W2"][0, 0] == pytest.approx(dz * (1 + 2.0 ** -7), rel=1e-15)  # the rounded h1
+    assert gr["W1"][0, 0] == pytest.approx(dz, rel=1e-15)  # the rounded x: 1, not 1 + 2^-9
+    assert gr["b1"][0] == pytest.approx(dz, rel=1e-15) and gr["b2"][0] == pytest.approx(dz, rel=1e-15)
+    assert np.count_nonzero(mlp.grad_bf16(x, y, w)) == 6
