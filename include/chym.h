@@ -414,7 +414,12 @@ int chym_to_bf16(const float *src, uint16_t *dst, int32_t n, chym_stream_t strea
  *                     register file for each wave);
  *   CHYM_KERNEL_PIPE  J in LDS as for LDSJ1, with the step loop software-
  *                     pipelined: the vector work of one step runs between
- *                     the matrix-core products of the next.
+ *                     the matrix-core products of the next;
+ *   CHYM_KERNEL_LDSJ3 as LDSJ, with registers for three wavefronts per SIMD
+ *                     (built where the step loop fits in 168 registers:
+ *                     up to 10 row tiles at d = 1, 7 at d = 2, 4 at d = 3,
+ *                     3 at d = 4; 8, 5, 3, 3 with float couplings in the
+ *                     float32 form);
  *   CHYM_KERNEL_SLAB  the streamed-J kernel, for the variants beyond the
  *                     register-resident ones (its only kind there): `waves`
  *                     is its block size, 8 (two wavefronts per SIMD) or 16
@@ -435,13 +440,14 @@ int chym_to_bf16(const float *src, uint16_t *dst, int32_t n, chym_stream_t strea
                                sets); built for d = 2, 3 and 2 to 7 row tiles with couplings in one bf16
                                term (any storage in the bf16 form; int8, bf16 or FP8 in the float32 form) */
 #define CHYM_KERNEL_SLAB 5  /* the streamed-J kernel (n beyond the register-resident variants) */
+#define CHYM_KERNEL_LDSJ3 6 /* J in LDS, three wavefronts per SIMD (where built) */
 
 typedef struct chym_plan_entry {
     int32_t n;         /* problem size the entry applies to (any n with the same 16-row tile count) */
     int32_t d;
     int32_t precision; /* CHYM_PREC_* */
     int32_t j_dtype;   /* CHYM_J_* */
-    int32_t kernel;    /* CHYM_KERNEL_REGJ, _LDSJ, _LDSJ1 or _PIPE for register-resident variants,
+    int32_t kernel;    /* CHYM_KERNEL_REGJ, _LDSJ, _LDSJ1, _LDSJ3 or _PIPE for register-resident variants,
                           CHYM_KERNEL_SLAB for streamed-J ones (CHYM_KERNEL_AUTO: remove the entry);
                           a kind not built for the shape is refused with CHYM_EUNSUPPORTED */
     int32_t waves;     /* wavefronts per block: 1..4, or 8 or 16 for CHYM_KERNEL_SLAB */

@@ -47,6 +47,7 @@ CHYM_KERNEL_LDSJ = 2
 CHYM_KERNEL_LDSJ1 = 3
 CHYM_KERNEL_PIPE = 4
 CHYM_KERNEL_SLAB = 5
+CHYM_KERNEL_LDSJ3 = 6
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32

@@ -12,7 +12,7 @@ import ctypes
 import torch
 
 from . import _lib as L
-from ._lib import (CHYM_J_BF16, CHYM_J_ELL, CHYM_J_F32, CHYM_J_FP8, CHYM_J_I8, CHYM_KERNEL_AUTO, CHYM_KERNEL_LDSJ, CHYM_KERNEL_LDSJ1, CHYM_KERNEL_PIPE, CHYM_KERNEL_REGJ, CHYM_KERNEL_SLAB,
+from ._lib import (CHYM_J_BF16, CHYM_J_ELL, CHYM_J_F32, CHYM_J_FP8, CHYM_J_I8, CHYM_KERNEL_AUTO, CHYM_KERNEL_LDSJ, CHYM_KERNEL_LDSJ1, CHYM_KERNEL_PIPE, CHYM_KERNEL_REGJ, CHYM_KERNEL_SLAB, CHYM_KERNEL_LDSJ3,
                    CHYM_PREC_BF16, CHYM_PREC_F32, ChymError, ChymOut, ChymPlanEntry, ChymProblem, ChymRun)
 
 __all__ = ["chym_sign_words", "chym_features", "chym_mlp_forward", "chym_mlp_backward", "chym_mlp_adam",
@@ -22,7 +22,8 @@ __all__ = ["chym_sign_words", "chym_features", "chym_mlp_forward", "chym_mlp_bac
            "chym_batch_workspace_size", "chym_batch_create", "chym_batch_launch", "chym_batch_launch_nograph",
            "chym_batch_destroy", "ChymBatch", "chym_plan_set", "chym_plan_get", "chym_plan_autotune",
            "chym_plan_save", "chym_plan_load", "chym_split3_bf16", "CHYM_KERNEL_REGJ", "CHYM_KERNEL_LDSJ",
-           "CHYM_KERNEL_AUTO", "CHYM_KERNEL_LDSJ1", "CHYM_KERNEL_PIPE", "CHYM_KERNEL_SLAB"]
+           "CHYM_KERNEL_AUTO", "CHYM_KERNEL_LDSJ1", "CHYM_KERNEL_PIPE", "CHYM_KERNEL_SLAB",
+           "CHYM_KERNEL_LDSJ3"]
 
 
 def precision_code(p) -> int:

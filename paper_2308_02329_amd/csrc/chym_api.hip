@@ -260,7 +260,7 @@ int validate_hs(int32_t n, int32_t d, int32_t r, const void *j, int32_t j_dtype,
 typedef std::tuple<int, int, int, int> VariantKey;  // (tiles, d, xs, js)
 
 struct PlanValue {
-    int kind;   // chym::kKernelRegJ / kKernelLdsJ / kKernelLdsJ1 / kKernelPipe / kKernelSlab
+    int kind;   // chym::kKernelRegJ / kKernelLdsJ / kKernelLdsJ1 / kKernelPipe / kKernelLdsJ3 / kKernelSlab
     int waves;  // wavefronts per block
     float ms;
 };
@@ -304,6 +304,7 @@ int kind_of_code(int code) {
         case CHYM_KERNEL_LDSJ: return chym::kKernelLdsJ;
         case CHYM_KERNEL_LDSJ1: return chym::kKernelLdsJ1;
         case CHYM_KERNEL_PIPE: return chym::kKernelPipe;
+        case CHYM_KERNEL_LDSJ3: return chym::kKernelLdsJ3;
         case CHYM_KERNEL_SLAB: return kKernelSlab;
         default: return chym::kKernelRegJ;
     }
@@ -313,13 +314,14 @@ int code_of_kind(int kind) {
         case chym::kKernelLdsJ: return CHYM_KERNEL_LDSJ;
         case chym::kKernelLdsJ1: return CHYM_KERNEL_LDSJ1;
         case chym::kKernelPipe: return CHYM_KERNEL_PIPE;
+        case chym::kKernelLdsJ3: return CHYM_KERNEL_LDSJ3;
         case kKernelSlab: return CHYM_KERNEL_SLAB;
         default: return CHYM_KERNEL_REGJ;
     }
 }
 bool valid_kernel_code(int code) {
     return code == CHYM_KERNEL_REGJ || code == CHYM_KERNEL_LDSJ || code == CHYM_KERNEL_LDSJ1 ||
-           code == CHYM_KERNEL_PIPE || code == CHYM_KERNEL_SLAB;
+           code == CHYM_KERNEL_PIPE || code == CHYM_KERNEL_LDSJ3 || code == CHYM_KERNEL_SLAB;
 }
 
 Variant variant_of_shape(int n, int precision, int j_dtype) {
@@ -1228,6 +1230,7 @@ int chym_plan_autotune(int32_t n, int32_t d, int32_t precision, int32_t j_dtype,
                                    {chym::kKernelLdsJ, 4, 0.f},
                                    {chym::kKernelLdsJ1, 4, 0.f},
                                    {chym::kKernelPipe, 4, 0.f},
+                                   {chym::kKernelLdsJ3, 4, 0.f},
                                    {kKernelSlab, chym::kSlabWaves8, 0.f},
                                    {kKernelSlab, chym::kSlabWaves16, 0.f}};
     PlanValue cands[sizeof(all_cands) / sizeof(all_cands[0])];

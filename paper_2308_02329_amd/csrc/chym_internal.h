@@ -136,6 +136,7 @@ constexpr int kKernelRegJ = 0;
 constexpr int kKernelLdsJ = 1;   // two wavefronts per SIMD
 constexpr int kKernelLdsJ1 = 2;  // one wavefront per SIMD
 constexpr int kKernelPipe = 3;   // one wavefront per SIMD, update and split interleaved with the products
+constexpr int kKernelLdsJ3 = 4;  // three wavefronts per SIMD
 // Whether a persistent kernel of this kind is built for the shape (the
 // pipelined kind exists for some shapes only).
 bool persistent_kind_exists(int tiles, int d, int xs, int js, int kind);

@@ -13,7 +13,7 @@ static KernelFn lookup(int tiles, int d, int xs, int js) {
     CHYM_PICK(3, 3, 1) CHYM_PICK(3, 1, 1) CHYM_PICK(3, 3, 3)
     CHYM_PICK(4, 3, 1) CHYM_PICK(4, 1, 1) CHYM_PICK(4, 3, 3)
 #undef CHYM_PICK
-    return KernelSet{nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr};
+    return KernelSet{nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr};
 }
 
 int resident_tile_limit(int d, int xs, int js) {
@@ -312,15 +312,22 @@ hipError_t launch_integrate_map_persistent(int tiles, int d, int xs, int blocks,
 }
 
 static void (*lds_kernel(const KernelFn &fn, int kind))(const IntegArgs *, const int2 *, int, int *) {
-    return kind == kKernelPipe ? fn.persistent_pipe : kind == kKernelLdsJ1 ? fn.persistent_lds1 : fn.persistent_lds;
+    switch (kind) {
+        case kKernelPipe: return fn.persistent_pipe;
+        case kKernelLdsJ1: return fn.persistent_lds1;
+        case kKernelLdsJ3: return fn.persistent_lds3;
+        default: return fn.persistent_lds;
+    }
 }
 
-static bool uses_lds(int kind) { return kind == kKernelLdsJ || kind == kKernelLdsJ1 || kind == kKernelPipe; }
+static bool uses_lds(int kind) {
+    return kind == kKernelLdsJ || kind == kKernelLdsJ1 || kind == kKernelPipe || kind == kKernelLdsJ3;
+}
 
 bool persistent_kind_exists(int tiles, int d, int xs, int js, int kind) {
     KernelFn fn = lookup(tiles, d, xs, js);
     if (!fn.persistent) return false;
-    return kind == kKernelPipe ? fn.persistent_pipe != nullptr : true;
+    return uses_lds(kind) ? lds_kernel(fn, kind) != nullptr : true;
 }
 
 static hipError_t prepare_lds(const KernelFn &fn, int kind) {

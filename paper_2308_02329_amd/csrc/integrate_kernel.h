@@ -423,8 +423,9 @@ __global__ __launch_bounds__(256) void k_integrate_persistent(const IntegArgs *_
 // (problem, slab of 16 W replicas), stages the problem's J fragments once,
 // and each wavefront integrates its 16 replicas reading J from LDS.  WPE
 // wavefronts per SIMD: 2 caps each at 256 registers so that one wave's
-// matrix-core work can overlap the other's vector work; 1 leaves the full
-// register file to a single wave.
+// matrix-core work can overlap the other's vector work; 3 caps each at 168,
+// for the variants whose step loop still fits (lds3_max_tiles); 1 leaves the
+// full register file to a single wave.
 template <int NT, int D, int XS, int JS, int WPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_integrate_persistent_lds(const IntegArgs *__restrict__ tasks, const int2 *__restrict__ items, int n_items,
@@ -696,6 +697,22 @@ constexpr size_t lds_j_bytes() {
     return (size_t)JS * NT * ((NT + 1) / 2) * 64 * sizeof(bf16x8);
 }
 
+// Largest row-tile count per (d, xs, js) whose three-wavefronts-per-SIMD
+// LDS kernel keeps its step loop free of scratch spills (168 registers;
+// spills in the set-up before the loop are allowed).
+constexpr int lds3_max_tiles(int d, int xs, int js) {
+    if (d == 1) return js == 3 ? 8 : 10;
+    if (d == 2) return js == 3 ? 5 : 7;
+    if (d == 3) return js == 3 ? 3 : 4;
+    return 3;
+}
+
+template <int NT, int D, int XS, int JS>
+constexpr void (*lds3_fn())(const IntegArgs *, const int2 *, int, int *) {
+    if constexpr (NT <= lds3_max_tiles(D, XS, JS)) return k_integrate_persistent_lds<NT, D, XS, JS, 3>;
+    else return nullptr;
+}
+
 struct KernelSet {
     void (*single)(IntegArgs);
     void (*persistent)(const IntegArgs *, const int2 *, int, int *);
@@ -705,6 +722,7 @@ struct KernelSet {
     void (*single_map)(IntegArgs);  // round-trip map form (single coupling term only)
     void (*persistent_map)(const IntegArgs *, const int2 *, int, int *);  // same, many problems
     void (*persistent_pipe)(const IntegArgs *, const int2 *, int, int *);  // pipelined, one wavefront per SIMD
+    void (*persistent_lds3)(const IntegArgs *, const int2 *, int, int *);  // three wavefronts per SIMD
 };
 
 // Largest row-tile count per (d, xs, js) that compiles without scratch
@@ -731,9 +749,9 @@ KernelSet variant_or_null() {
                          lds_j_bytes<NT, JS>(),
                          (JS == 1 && NT <= kMapMaxTiles) ? k_integrate_resident<NT, D, XS, JS, true> : nullptr,
                          (JS == 1 && NT <= kMapMaxTiles) ? k_integrate_persistent<NT, D, XS, JS, true> : nullptr,
-                         pipe_fn<NT, D, XS, JS>()};
+                         pipe_fn<NT, D, XS, JS>(), lds3_fn<NT, D, XS, JS>()};
     else
-        return KernelSet{nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr};
+        return KernelSet{nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr};
 }
 
 // One translation unit per (D, XS, JS) instantiates all tile counts.
@@ -752,7 +770,7 @@ KernelSet lookup_tiles(int tiles) {
         case 10: return variant_or_null<10, D, XS, JS>();
         case 11: return variant_or_null<11, D, XS, JS>();
         case 12: return variant_or_null<12, D, XS, JS>();
-        default: return KernelSet{nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr};
+        default: return KernelSet{nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr};
     }
 }
 

@@ -170,6 +170,28 @@ def test_plan_table_validation_and_file_roundtrip(tmp_path):
     assert lib.chym_split3_bf16(0x1000, 7, 0x2000, 0x3000, 0x4000, None) == L.CHYM_EINVAL
 
 
+def test_three_wave_lds_plans():
+    """CHYM_KERNEL_LDSJ3 (three wavefronts per SIMD) is accepted where its
+    step loop is built (up to 10 / 7 / 4 / 3 row tiles at d = 1..4, 8 / 5 /
+    3 / 3 with float couplings in the float32 form) and refused elsewhere."""
+    lib = L.load()
+    bf, f32, i8, fl = L.CHYM_PREC_BF16, L.CHYM_PREC_F32, L.CHYM_J_I8, L.CHYM_J_F32
+    got = L.ChymPlanEntry()
+    for n, d, prec, jd, ok in ((100, 2, f32, i8, True), (160, 1, f32, i8, True), (40, 4, f32, i8, True),
+                               (64, 3, bf, i8, True), (80, 2, f32, fl, True), (128, 1, f32, fl, True),
+                               (100, 3, f32, i8, False), (112, 2, bf, i8, True), (128, 2, bf, i8, False),
+                               (96, 2, f32, fl, False), (64, 4, bf, i8, False), (176, 1, f32, i8, False)):
+        e = L.ChymPlanEntry(n=n, d=d, precision=prec, j_dtype=jd, kernel=L.CHYM_KERNEL_LDSJ3, waves=4, ms=0.0,
+                            reserved=0.0)
+        rc = lib.chym_plan_set(ctypes.byref(e))
+        assert rc == (L.CHYM_OK if ok else L.CHYM_EUNSUPPORTED), (n, d, prec, jd)
+        if ok:
+            assert lib.chym_plan_get(n, d, prec, jd, ctypes.byref(got)) == L.CHYM_OK
+            assert (got.kernel, got.waves) == (L.CHYM_KERNEL_LDSJ3, 4)
+            e.kernel = L.CHYM_KERNEL_AUTO
+            assert lib.chym_plan_set(ctypes.byref(e)) == L.CHYM_OK
+
+
 def test_streamed_j_plans(tmp_path):
     """Streamed-J variants (beyond the register-resident tile limits) take
     CHYM_KERNEL_SLAB plans whose `waves` is the block size: 16 by default up

@@ -48,6 +48,17 @@ def test_split3_is_exact_and_rne():
 @pytest.mark.parametrize("n,d,prec", [(100, 2, "f32"), (100, 3, "bf16"), (40, 4, "f32"), (150, 1, "f32")])
 @pytest.mark.parametrize("kernel,waves", [(2, 2), (2, 4), (3, 4), (3, 1)])
 def test_lds_plan_matches_register_plan_bit_exact(n, d, prec, kernel, waves):
+    lds_vs_register_plan(n, d, prec, kernel, waves)
+
+
+@pytest.mark.parametrize("n,d,prec", [(100, 2, "f32"), (40, 4, "f32"), (150, 1, "f32"), (60, 3, "bf16"),
+                                      (100, 2, "bf16")])
+@pytest.mark.parametrize("waves", [4, 2])
+def test_three_wave_lds_plan_matches_register_plan_bit_exact(n, d, prec, waves):
+    lds_vs_register_plan(n, d, prec, api.CHYM_KERNEL_LDSJ3, waves)
+
+
+def lds_vs_register_plan(n, d, prec, kernel, waves):
     specs = [(n, d, 70, 150), (n, d, 33, 120), (n, d, 16, 150)]
     cases = [Case(nn, dd, r, s, key=(30, i)) for i, (nn, dd, r, s) in enumerate(specs)]
 
@@ -116,8 +127,8 @@ def test_pipelined_plan_refused_where_not_built():
 
 def test_autotune_installs_a_candidate(tmp_path):
     best, cands = api.chym_plan_autotune(48, 2, "f32", torch.int8, replicas=4096, steps=50)
-    assert len(cands) == 5 and all(c["ms"] > 0 for c in cands)  # the pipelined kind is built for this shape
-    assert api.CHYM_KERNEL_PIPE in [c["kernel"] for c in cands]
+    assert len(cands) == 6 and all(c["ms"] > 0 for c in cands)  # the pipelined and three-wave kinds are built
+    assert {api.CHYM_KERNEL_PIPE, api.CHYM_KERNEL_LDSJ3} <= {c["kernel"] for c in cands}
     assert best["ms"] == min(c["ms"] for c in cands)
     assert api.chym_plan_get(48, 2, "f32", torch.int8)["kernel"] == best["kernel"]
     path = tmp_path / "plans.txt"
