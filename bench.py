@@ -308,7 +308,7 @@ def run_precision(args, torch, api, synth):
                        "n": n, "d": d, "replicas": R, "euler_steps": steps, "precision": "bf16"},
             "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
-                         "kernel": "k_integrate_slab<4, 1, 1, 8, 8> (SK +-1 J, E4M3 stream)", "kernel_ms": ms_sk},
+                         "kernel": "k_integrate_slab<4, 1, 1, 8, 8> (SK +-1 J, bf16 fragments)", "kernel_ms": ms_sk},
             "integrate_ms": res_kind}
 
 
