@@ -1497,8 +1497,9 @@ int chym_plan_load(const char *path) {
             return fail(CHYM_EINVAL, "%s:%d: malformed plan entry", path, lineno);
         }
         const VariantKey k = std::make_tuple(t, d, xs, js);
-        const bool slab_ok = kernel != CHYM_KERNEL_SLAB || chym::slab_shape_exists(t, d, xs, js, waves);
-        if (key_is_slab(k) != (kernel == CHYM_KERNEL_SLAB) || !slab_ok) {
+        const bool built = kernel == CHYM_KERNEL_SLAB ? chym::slab_shape_exists(t, d, xs, js, waves)
+                                                      : chym::persistent_kind_exists(t, d, xs, js, kind_of_code(kernel));
+        if (key_is_slab(k) != (kernel == CHYM_KERNEL_SLAB) || !built) {
             fclose(f);
             return fail(CHYM_EINVAL, "%s:%d: kernel %d does not run %d tiles at d = %d in this form", path, lineno,
                         kernel, t, d);

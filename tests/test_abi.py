@@ -192,6 +192,28 @@ def test_three_wave_lds_plans():
             assert lib.chym_plan_set(ctypes.byref(e)) == L.CHYM_OK
 
 
+def test_plan_file_refuses_kinds_not_built(tmp_path):
+    """A plan file naming a kind that is not built for its variant is
+    refused as a whole (tiles d xs js kernel waves ms)."""
+    lib = L.load()
+    good = tmp_path / "good.txt"
+    good.write_text("7 2 3 1 6 4 1.0\n7 3 3 1 2 4 1.0\n")
+    assert lib.chym_plan_load(str(good).encode()) == L.CHYM_OK
+    got = L.ChymPlanEntry()
+    assert lib.chym_plan_get(100, 2, L.CHYM_PREC_F32, L.CHYM_J_I8, ctypes.byref(got)) == L.CHYM_OK
+    assert got.kernel == L.CHYM_KERNEL_LDSJ3
+    for line in ("7 3 3 1 6 4 1.0\n",    # three wavefronts per SIMD: not built at 7 tiles, d = 3
+                 "7 4 3 1 4 4 1.0\n",    # pipelined: d = 2, 3 only
+                 "6 3 3 3 4 4 1.0\n"):   # pipelined: one coupling term only
+        bad = tmp_path / "bad.txt"
+        bad.write_text(line)
+        assert lib.chym_plan_load(str(bad).encode()) == L.CHYM_EINVAL, line
+    for n, d in ((100, 2), (100, 3)):
+        e = L.ChymPlanEntry(n=n, d=d, precision=L.CHYM_PREC_F32, j_dtype=L.CHYM_J_I8, kernel=L.CHYM_KERNEL_AUTO,
+                            waves=4, ms=0.0, reserved=0.0)
+        assert lib.chym_plan_set(ctypes.byref(e)) == L.CHYM_OK
+
+
 def test_streamed_j_plans(tmp_path):
     """Streamed-J variants (beyond the register-resident tile limits) take
     CHYM_KERNEL_SLAB plans whose `waves` is the block size: 16 by default up
