@@ -146,10 +146,13 @@ const char *chym_last_error(void);
  * problem: a register-resident one (no workspace) up to n = 192 (d = 1),
  * 144/160 (d = 2, float32/bf16 form), 128 (d = 3), 112 (d = 4), or less
  * for float J in the float32 form; and a streamed-J one for larger n, up to
- * n = 1024, which needs a caller workspace (chym_integrate_ws) and requires
- * the bf16 operand of 16 replicas, ceil(n/32) * d * terms KiB, to fit in
- * 160 KiB of LDS (terms = 1 in the bf16 form, 3 in the float32 form).
- * chym_integrate returns CHYM_EUNSUPPORTED where a workspace is needed. */
+ * n = 1024 in both forms, which needs a caller workspace (chym_integrate_ws).
+ * The streamed-J integrator keeps the bf16 operand of 16 replicas,
+ * ceil(n/32) * d * terms KiB (terms = 1 in the bf16 form, 3 in the float32
+ * form), in LDS; where that exceeds 159 KiB (the float32 form beyond n = 832,
+ * 544, 416 for d = 2, 3, 4) it holds one component at a time and reads J d
+ * times per step, with the same results.  chym_integrate returns
+ * CHYM_EUNSUPPORTED where a workspace is needed. */
 int chym_integrate(const chym_problem *prob, const chym_run *run, chym_stream_t stream);
 
 /* Device workspace bytes chym_integrate_ws / chym_solve_ws need for this

@@ -146,10 +146,8 @@ int check_variant(const chym_problem *prob, const chym_run *run) {
     }
     const Variant v = variant_of(prob, run);
     if (v.slab && !chym::slab_variant_exists(v.tiles, prob->d, v.xs, v.js))
-        return fail(CHYM_EUNSUPPORTED,
-                    "n = %d with d = %d in this precision is beyond the integrators (n <= 1024; the operand of "
-                    "16 replicas, %zu bytes, must fit in LDS)",
-                    prob->n, prob->d, chym::slab_lds_bytes(v.tiles, prob->d, v.xs));
+        return fail(CHYM_EUNSUPPORTED, "n = %d with d = %d in this precision is beyond the integrators (n <= 1024)",
+                    prob->n, prob->d);
     return CHYM_OK;
 }
 

@@ -186,7 +186,8 @@ hipError_t launch_score_batched(const ScoreArgs *tasks, const int64_t *first, in
                                 hipStream_t stream);
 
 // Streamed-J slab integrator (large n).  Tiles of 16 rows; kSlabMaxLds
-// bounds the LDS operand area of one column slab.
+// bounds the LDS operand area of one column slab (beyond it the float32 form
+// holds one component at a time and makes d passes over J per step).
 constexpr size_t kSlabMaxLds = 159 * 1024;  // 160 KiB per CU, less room for static LDS
 // Blocks of eight or sixteen wavefronts (kSlabWaves8, kSlabWaves16); the
 // sixteen-wavefront shapes are built for the bf16 form, up to 32 tiles (64

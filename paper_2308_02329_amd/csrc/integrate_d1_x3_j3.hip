@@ -5,5 +5,5 @@
 
 namespace chym {
 KernelSet lookup_resident_1_3_3(int tiles) { return lookup_tiles<1, 3, 3>(tiles); }
-SlabKernels lookup_slab_1_3_3(int tpw, int waves) { return slab_lookup_tpw<1, 3, 3>(tpw, waves); }
+SlabKernels lookup_slab_1_3_3(int tpw, int waves, bool cp) { return slab_lookup_tpw<1, 3, 3>(tpw, waves, cp); }
 }  // namespace chym

@@ -5,5 +5,5 @@
 
 namespace chym {
 KernelSet lookup_resident_2_3_3(int tiles) { return lookup_tiles<2, 3, 3>(tiles); }
-SlabKernels lookup_slab_2_3_3(int tpw, int waves) { return slab_lookup_tpw<2, 3, 3>(tpw, waves); }
+SlabKernels lookup_slab_2_3_3(int tpw, int waves, bool cp) { return slab_lookup_tpw<2, 3, 3>(tpw, waves, cp); }
 }  // namespace chym

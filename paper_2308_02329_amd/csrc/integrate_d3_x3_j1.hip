@@ -5,5 +5,5 @@
 
 namespace chym {
 KernelSet lookup_resident_3_3_1(int tiles) { return lookup_tiles<3, 3, 1>(tiles); }
-SlabKernels lookup_slab_3_3_1(int tpw, int waves) { return slab_lookup_tpw<3, 3, 1>(tpw, waves); }
+SlabKernels lookup_slab_3_3_1(int tpw, int waves, bool cp) { return slab_lookup_tpw<3, 3, 1>(tpw, waves, cp); }
 }  // namespace chym

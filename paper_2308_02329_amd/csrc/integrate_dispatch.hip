@@ -21,9 +21,9 @@ int resident_tile_limit(int d, int xs, int js) {
 }
 
 // ------------------------------------------------------------ slab kernels
-static SlabKernels lookup_slab_shape(int tpw, int waves, int d, int xs, int js) {
+static SlabKernels lookup_slab_shape(int tpw, int waves, int d, int xs, int js, bool cp) {
 #define CHYM_PICK(D, XS, JS) \
-    if (d == D && xs == XS && js == JS) return lookup_slab_##D##_##XS##_##JS(tpw, waves);
+    if (d == D && xs == XS && js == JS) return lookup_slab_##D##_##XS##_##JS(tpw, waves, cp);
     CHYM_PICK(1, 3, 1) CHYM_PICK(1, 1, 1) CHYM_PICK(1, 3, 3)
     CHYM_PICK(2, 3, 1) CHYM_PICK(2, 1, 1) CHYM_PICK(2, 3, 3)
     CHYM_PICK(3, 3, 1) CHYM_PICK(3, 1, 1) CHYM_PICK(3, 3, 3)
@@ -41,13 +41,22 @@ int slab_tpw_for(int tiles, int waves) {
     return 0;
 }
 
+// The float32 form takes component passes where the operand of all d
+// components exceeds the LDS budget (the bf16 form's always fits).
+static bool slab_component_passes(int tiles, int d, int xs) {
+    return xs == 3 && d > 1 && (size_t)((tiles + 1) / 2) * d * xs * 64 * sizeof(bf16x8) > kSlabMaxLds;
+}
+
 static SlabKernels lookup_slab(int tiles, int d, int xs, int js, int waves) {
     const int tpw = slab_tpw_for(tiles, waves);
     if (tpw == 0) return SlabKernels{nullptr, nullptr, 0};
-    return lookup_slab_shape(tpw, waves, d, xs, js);
+    return lookup_slab_shape(tpw, waves, d, xs, js, slab_component_passes(tiles, d, xs));
 }
 
-size_t slab_lds_bytes(int tiles, int d, int xs) { return (size_t)((tiles + 1) / 2) * d * xs * 64 * sizeof(bf16x8); }
+size_t slab_lds_bytes(int tiles, int d, int xs) {
+    const int dp = slab_component_passes(tiles, d, xs) ? 1 : d;
+    return (size_t)((tiles + 1) / 2) * dp * xs * 64 * sizeof(bf16x8);
+}
 
 // The fragments, plus kSlabRingChunks chunks of padding: the streamed-J
 // kernel's prefetch ring refills unconditionally, so around the last tile it

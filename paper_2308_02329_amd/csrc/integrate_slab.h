@@ -29,6 +29,16 @@
 // chunk's matrix-core work runs), then apply the fused Euler update to those
 // tiles in registers; after a barrier every wavefront writes its tiles' new
 // operand terms to LDS, and a second barrier publishes them.
+//
+// Component passes (the float32 form at large N, whose three-term operand of
+// all D components exceeds LDS): LDS holds one component's operand, and a
+// step makes D passes over the J stream, one per component.  The update of a
+// hyperspin needs only its own component's G and the norm of its old state,
+// so the norm-dependent coefficient is formed from the old state at the start
+// of the step, each pass updates its component as soon as its G is complete,
+// and the later passes still write operands of their components' old values.
+// Every accumulator takes the same products in the same order and the update
+// is the same arithmetic, so the results equal those of the one-pass form.
 #pragma once
 
 #include "integrate_kernel.h"
@@ -77,38 +87,43 @@ __device__ __forceinline__ bf16x8 fp8_fragment(uint2 w, float scale) {
     return __builtin_shufflevector(ab, cd, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
-// LDS operand layout: [chunk][component][term][64 lanes] of bf16x8 (1 KB each).
+// LDS operand layout: [chunk][component][term][64 lanes] of bf16x8 (1 KB
+// each); D components, or one in the component-pass form.
 __device__ __forceinline__ int slab_b_index(int c, int mu, int t, int lane, int D, int XS) {
     return ((c * D + mu) * XS + t) * 64 + lane;
 }
 
-// Writes the operand terms of tile I (its four rows of this lane) into the
-// half (I & 1) of chunk I >> 1.
-template <int D, int XS>
-__device__ __forceinline__ void slab_write_tile(const float (&xt)[D][4], int I, int lane, bf16x8 *lb) {
+// Writes the operand terms of one component of tile I (its four rows of this
+// lane, v) into the half (I & 1) of the fragments lb[f0 + 64 q], q < XS.
+template <int XS>
+__device__ __forceinline__ void slab_write_comp(const float (&v)[4], int I, int f0, bf16x8 *lb) {
     typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+    bf16x2 t[XS][2];
 #pragma unroll
-    for (int mu = 0; mu < D; ++mu) {
-        bf16x2 t[XS][2];
-#pragma unroll
-        for (int pr = 0; pr < 2; ++pr) {
-            const float a = xt[mu][2 * pr], b = xt[mu][2 * pr + 1];
-            const bf16x2 h = pack_rne(a, b);
-            t[0][pr] = h;
-            if constexpr (XS == 3) {
-                const float ra = resid_lo(h, a), rb = resid_hi(h, b);
-                const bf16x2 m = pack_rne(ra, rb);
-                const float sa = resid_lo(m, ra), sb = resid_hi(m, rb);
-                t[1][pr] = m;
-                t[2][pr] = pack_rne(sa, sb);
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < XS; ++q) {
-            bf16x4 *dst = reinterpret_cast<bf16x4 *>(lb + slab_b_index(I >> 1, mu, q, lane, D, XS)) + (I & 1);
-            *dst = __builtin_shufflevector(t[q][0], t[q][1], 0, 1, 2, 3);
+    for (int pr = 0; pr < 2; ++pr) {
+        const float a = v[2 * pr], b = v[2 * pr + 1];
+        const bf16x2 h = pack_rne(a, b);
+        t[0][pr] = h;
+        if constexpr (XS == 3) {
+            const float ra = resid_lo(h, a), rb = resid_hi(h, b);
+            const bf16x2 m = pack_rne(ra, rb);
+            const float sa = resid_lo(m, ra), sb = resid_hi(m, rb);
+            t[1][pr] = m;
+            t[2][pr] = pack_rne(sa, sb);
         }
     }
+#pragma unroll
+    for (int q = 0; q < XS; ++q) {
+        bf16x4 *dst = reinterpret_cast<bf16x4 *>(lb + f0 + 64 * q) + (I & 1);
+        *dst = __builtin_shufflevector(t[q][0], t[q][1], 0, 1, 2, 3);
+    }
+}
+
+// Writes the operand terms of every component of tile I into chunk I >> 1.
+template <int D, int XS>
+__device__ __forceinline__ void slab_write_tile(const float (&xt)[D][4], int I, int lane, bf16x8 *lb) {
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) slab_write_comp<XS>(xt[mu], I, slab_b_index(I >> 1, mu, 0, lane, D, XS), lb);
 }
 
 // Integrates the column slab rep0 .. rep0+15 of problem a.  stage: the
@@ -127,7 +142,7 @@ __device__ __forceinline__ void slab_write_tile(const float (&xt)[D][4], int I, 
 // one: J does not change between steps).  Every refill is a load, so a slot's
 // next value is always the register its load writes, and the prefetch crosses
 // group and step boundaries.
-template <int D, int XS, int JS, int TPW, bool F8, int W, int RDB = 2>
+template <int D, int XS, int JS, int TPW, bool F8, int W, int RDB = 2, bool CP = false>
 __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, const unsigned char *__restrict__ stage,
                                                int ncp, bf16x8 *lb) {
     // tiles accumulated together (register budget per lane: 128 at four
@@ -142,6 +157,10 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
     // PF: the state operand of the next chunk is read from LDS while the
     // current chunk's products run, where its registers fit
     constexpr bool PF = XS == 1 ? D >= 3 : D == 2;
+    // CP: component passes; DP components in the LDS operand and the
+    // accumulators of one pass, NPH passes per step
+    constexpr int DP = CP ? 1 : D;
+    constexpr int NPH = CP ? D : 1;
     const int n = a.n;
     const int r = a.r;
     const int nt = (n + 15) / 16;
@@ -181,7 +200,7 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
     };
 
     // zero the operand area (chunks past the last tile read as zero)
-    for (int i = threadIdx.x; i < ncp * D * XS * 64; i += blockDim.x) lb[i] = bf16x8{};
+    for (int i = threadIdx.x; i < ncp * DP * XS * 64; i += blockDim.x) lb[i] = bf16x8{};
     __syncthreads();
 
     float x[TPW][D][4];
@@ -195,7 +214,7 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
 #pragma unroll
             for (int mu = 0; mu < D; ++mu) x[k][mu][v] = ok ? a.x[((size_t)p * r + rep) * D + mu] : 0.0f;
         }
-        if (I < nt) slab_write_tile<D, XS>(x[k], I, lane, lb);
+        if (!CP && I < nt) slab_write_tile<D, XS>(x[k], I, lane, lb);
     }
 
     // the ring holds the first RD chunks of group 0; the scales of group 0
@@ -227,13 +246,38 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
     constexpr int pj[6] = {JS == 1 ? 0 : 2, JS == 1 ? 0 : 1, 0, JS == 1 ? 0 : 1, 0, 0};
     constexpr int px[6] = {JS == 1 ? XS - 1 : 0, JS == 1 ? (XS > 1 ? XS - 2 : 0) : 1, JS == 1 ? 0 : 2, 0, 1, 0};
 
-    bf16x8 bxr[PF ? D : 1][PF ? XS : 1];  // PF: the state operand of the next chunk
+    bf16x8 bxr[PF ? DP : 1][PF ? XS : 1];  // PF: the state operand of the next chunk
     for (int k = 0; k < a.steps; ++k) {
         const float *al = a.alpha + (size_t)(a.start_step + k) * D;
         float ga[D];
 #pragma unroll
         for (int mu = 0; mu < D; ++mu) ga[mu] = dte * al[mu];
+        // CP: the norm-dependent coefficient of every owned hyperspin, from
+        // the old state
+        float ccp[CP ? TPW : 1][4];
+        if constexpr (CP) {
+#pragma unroll
+            for (int kk = 0; kk < TPW; ++kk)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    float S = x[kk][0][v] * x[kk][0][v];
+#pragma unroll
+                    for (int mu = 1; mu < D; ++mu) S = S + x[kk][mu][v] * x[kk][mu][v];
+                    ccp[kk][v] = fmaf(nbd, S, base);
+                }
+        }
 
+#pragma unroll
+        for (int ph = 0; ph < NPH; ++ph) {
+        if constexpr (CP) {
+            __syncthreads();  // every wavefront is done reading the previous operand
+#pragma unroll
+            for (int kk = 0; kk < TPW; ++kk) {
+                const int I = w + W * kk;
+                if (I < nt) slab_write_comp<XS>(x[kk][ph], I, slab_b_index(I >> 1, 0, 0, lane, 1, XS), lb);
+            }
+            __syncthreads();
+        }
 #pragma unroll
         for (int grp = 0; grp < NG; ++grp) {
             if (grp >= ngw) break;  // wave-uniform
@@ -247,19 +291,19 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
                 son[i] = more ? tile_off(grp + 1 < NG ? grp + 1 : 0, i) : tile_off(0, i);
                 if constexpr (F8) scn[i] = more ? scale_of(grp + 1 < NG ? grp + 1 : 0, i) : scale_of(0, i);
             }
-            f32x4 acc[GS][D];
+            f32x4 acc[GS][DP];
 #pragma unroll
             for (int i = 0; i < GS; ++i)
 #pragma unroll
-                for (int mu = 0; mu < D; ++mu) acc[i][mu] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                for (int mu = 0; mu < DP; ++mu) acc[i][mu] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
             if constexpr (PF) {
                 if (grp == 0) {
                     // later groups find chunk 0 in bxr, read during the previous
                     // group's last chunk
 #pragma unroll
-                    for (int mu = 0; mu < D; ++mu)
+                    for (int mu = 0; mu < DP; ++mu)
 #pragma unroll
-                        for (int t = 0; t < XS; ++t) bxr[mu][t] = lb[slab_b_index(0, mu, t, lane, D, XS)];
+                        for (int t = 0; t < XS; ++t) bxr[mu][t] = lb[slab_b_index(0, mu, t, lane, DP, XS)];
                 }
             }
             // chunk c (c % RD == sl): take its J fragments from ring slot sl and
@@ -281,29 +325,29 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
                         }
                     }
                 }
-                bf16x8 bx[D][XS];
+                bf16x8 bx[DP][XS];
                 if constexpr (PF) {
                     // past the last chunk: chunk 0 of the next group
                     const int cb = c + 1 < ncp ? c + 1 : 0;
 #pragma unroll
-                    for (int mu = 0; mu < D; ++mu)
+                    for (int mu = 0; mu < DP; ++mu)
 #pragma unroll
                         for (int t = 0; t < XS; ++t) {
                             bx[mu][t] = bxr[PF ? mu : 0][PF ? t : 0];
-                            bxr[PF ? mu : 0][PF ? t : 0] = lb[slab_b_index(cb, mu, t, lane, D, XS)];
+                            bxr[PF ? mu : 0][PF ? t : 0] = lb[slab_b_index(cb, mu, t, lane, DP, XS)];
                         }
                 } else {
 #pragma unroll
-                    for (int mu = 0; mu < D; ++mu)
+                    for (int mu = 0; mu < DP; ++mu)
 #pragma unroll
-                        for (int t = 0; t < XS; ++t) bx[mu][t] = lb[slab_b_index(c, mu, t, lane, D, XS)];
+                        for (int t = 0; t < XS; ++t) bx[mu][t] = lb[slab_b_index(c, mu, t, lane, DP, XS)];
                 }
 #pragma unroll
                 for (int q = 0; q < NP; ++q)
 #pragma unroll
                     for (int i = 0; i < GS; ++i)
 #pragma unroll
-                        for (int mu = 0; mu < D; ++mu)
+                        for (int mu = 0; mu < DP; ++mu)
                             acc[i][mu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i][pj[q]], bx[mu][px[q]],
                                                                                 acc[i][mu], 0, 0, 0);
             };
@@ -320,6 +364,18 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
             for (int i = 0; i < GS; ++i) {
                 const int kk = GS * grp + i;
                 if (w + W * kk >= nt) continue;
+                if constexpr (CP) {
+                    // component ph only; x^2 formed again rather than kept
+                    // live from the coefficient's sum
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        float xv = x[kk][ph][v];
+                        asm volatile("" : "+v"(xv));
+                        const float y = xv * fmaf(ned, xv * xv, ccp[kk][v]);
+                        x[kk][ph][v] = fmaf(ga[ph], acc[i][0][v], y);
+                    }
+                    continue;
+                }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     float x2[D];
@@ -332,7 +388,7 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
 #pragma unroll
                     for (int mu = 0; mu < D; ++mu) {
                         const float y = x[kk][mu][v] * fmaf(ned, x2[mu], cc);
-                        x[kk][mu][v] = fmaf(ga[mu], acc[i][mu][v], y);
+                        x[kk][mu][v] = fmaf(ga[mu], acc[i][CP ? 0 : mu][v], y);
                     }
                 }
             }
@@ -341,13 +397,16 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
                 for (int i = 0; i < GS; ++i) sc[i] = scn[i];
             }
         }
-        __syncthreads();  // every wavefront is done reading the old operand
-#pragma unroll
-        for (int kk = 0; kk < TPW; ++kk) {
-            const int I = w + W * kk;
-            if (I < nt) slab_write_tile<D, XS>(x[kk], I, lane, lb);
         }
-        __syncthreads();
+        if constexpr (!CP) {
+            __syncthreads();  // every wavefront is done reading the old operand
+#pragma unroll
+            for (int kk = 0; kk < TPW; ++kk) {
+                const int I = w + W * kk;
+                if (I < nt) slab_write_tile<D, XS>(x[kk], I, lane, lb);
+            }
+            __syncthreads();
+        }
     }
 
     // addresses of the final store are formed here, not kept live through the run
@@ -429,16 +488,16 @@ __global__ __launch_bounds__(256) void k_stage_jfrag_batched(const IntegArgs *__
 }
 
 // The E4M3 path exists for single-term couplings; the flag is uniform.
-template <int D, int XS, int JS, int TPW, int W>
+template <int D, int XS, int JS, int TPW, int W, bool CP>
 __device__ __forceinline__ void slab_run(const IntegArgs &a, int rep0, const unsigned char *stage, int ncp,
                                          bf16x8 *lb) {
     if constexpr (JS == 1) {
         if (__builtin_amdgcn_readfirstlane(*reinterpret_cast<const int *>(stage)) != 0) {
-            integrate_slab<D, XS, JS, TPW, true, W>(a, rep0, stage, ncp, lb);
+            integrate_slab<D, XS, JS, TPW, true, W, 2, CP>(a, rep0, stage, ncp, lb);
             return;
         }
     }
-    integrate_slab<D, XS, JS, TPW, false, W>(a, rep0, stage, ncp, lb);
+    integrate_slab<D, XS, JS, TPW, false, W, 2, CP>(a, rep0, stage, ncp, lb);
 }
 
 // Column slabs of one problem: block b integrates replicas 16 b .. 16 b + 15.
@@ -450,17 +509,18 @@ __device__ __forceinline__ void slab_run(const IntegArgs &a, int rep0, const uns
 // 1-5% faster at N = 800 - 1000).  Batches, whose tasks stream many distinct
 // couplings through L2 at once, take the E4M3 path where it applies
 // (k_integrate_slab_persistent).
-template <int D, int XS, int JS, int TPW, int W>
+template <int D, int XS, int JS, int TPW, int W, bool CP = false>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W / 4)))
 void k_integrate_slab(IntegArgs a, const unsigned char *__restrict__ stage, int ncp) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int RDB = (W == 8 && XS == 1 && JS == 1) ? 4 : 2;
-    integrate_slab<D, XS, JS, TPW, false, W, RDB>(a, blockIdx.x * 16, stage, ncp, reinterpret_cast<bf16x8 *>(smem));
+    integrate_slab<D, XS, JS, TPW, false, W, RDB, CP>(a, blockIdx.x * 16, stage, ncp,
+                                                      reinterpret_cast<bf16x8 *>(smem));
 }
 
 // Persistent form: blocks pop (task, column slab) items; jfs[task] is the
 // task's staged J and ncps[task] its chunk count.
-template <int D, int XS, int JS, int TPW, int W>
+template <int D, int XS, int JS, int TPW, int W, bool CP = false>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W / 4)))
 void k_integrate_slab_persistent(const IntegArgs *__restrict__ tasks, const int2 *__restrict__ items, int n_items,
                                  int *__restrict__ counter, const unsigned char *const *__restrict__ jfs,
@@ -475,7 +535,7 @@ void k_integrate_slab_persistent(const IntegArgs *__restrict__ tasks, const int2
         if (it >= n_items) break;
         const int2 wi = items[it];
         const IntegArgs a = tasks[wi.x];
-        slab_run<D, XS, JS, TPW, W>(a, wi.y * 16, jfs[wi.x], ncps[wi.x], reinterpret_cast<bf16x8 *>(smem));
+        slab_run<D, XS, JS, TPW, W, CP>(a, wi.y * 16, jfs[wi.x], ncps[wi.x], reinterpret_cast<bf16x8 *>(smem));
     }
 }
 
@@ -490,9 +550,25 @@ struct SlabKernels {
 // about 32 row tiles: more wavefronts cover the latency of the operand reads
 // and of the J stream when each owns few tiles).  One wavefront per SIMD with
 // 16 tiles measured slower at N = 1000, D = 4 (a lone wavefront cannot cover
-// the L2 latency of the J stream), and at N = 200 - 800 too.
+// the L2 latency of the J stream), and at N = 200 - 800 too.  cp: the
+// component-pass form, built for the float32 form at d >= 2 in blocks of
+// eight wavefronts.
 template <int D, int XS, int JS>
-SlabKernels slab_lookup_tpw(int tpw, int waves) {
+SlabKernels slab_lookup_tpw(int tpw, int waves, bool cp) {
+    if (cp) {
+        // the shapes whose float32 operand exceeds LDS: up to 32 tiles only at d = 4
+        if constexpr (XS == 3 && D >= 2) {
+            if constexpr (D == 4) {
+                if (waves == 8 && tpw == 4)
+                    return SlabKernels{k_integrate_slab<D, XS, JS, 4, 8, true>,
+                                       k_integrate_slab_persistent<D, XS, JS, 4, 8, true>, 8};
+            }
+            if (waves == 8 && tpw == 8)
+                return SlabKernels{k_integrate_slab<D, XS, JS, 8, 8, true>,
+                                   k_integrate_slab_persistent<D, XS, JS, 8, 8, true>, 8};
+        }
+        return SlabKernels{nullptr, nullptr, 0};
+    }
     if (waves == 8 && tpw == 4)
         return SlabKernels{k_integrate_slab<D, XS, JS, 4, 8>, k_integrate_slab_persistent<D, XS, JS, 4, 8>, 8};
     if (waves == 8 && tpw == 8)
@@ -511,7 +587,7 @@ SlabKernels slab_lookup_tpw(int tpw, int waves) {
     return SlabKernels{nullptr, nullptr, 0};
 }
 
-#define CHYM_DECLARE_SLAB(D, XS, JS) SlabKernels lookup_slab_##D##_##XS##_##JS(int tpw, int waves);
+#define CHYM_DECLARE_SLAB(D, XS, JS) SlabKernels lookup_slab_##D##_##XS##_##JS(int tpw, int waves, bool cp);
 CHYM_DECLARE_SLAB(1, 3, 1) CHYM_DECLARE_SLAB(1, 1, 1) CHYM_DECLARE_SLAB(1, 3, 3)
 CHYM_DECLARE_SLAB(2, 3, 1) CHYM_DECLARE_SLAB(2, 1, 1) CHYM_DECLARE_SLAB(2, 3, 3)
 CHYM_DECLARE_SLAB(3, 3, 1) CHYM_DECLARE_SLAB(3, 1, 1) CHYM_DECLARE_SLAB(3, 3, 3)

@@ -376,9 +376,9 @@ def test_ell_pack_layout():
 
 
 def test_streamed_j_size_limits():
-    """Largest n per d and form that validates: the streamed-J operand of 16
-    replicas (d x terms x 1 KB per 32-row chunk) must fit in 159 KB of LDS and
-    the block's eight wavefronts take at most 8 row tiles each."""
+    """Largest n per d and form that validates: 1024 (the block's eight
+    wavefronts take at most 8 row tiles each) in both forms; the float32 form
+    beyond n = 832, 544, 416 (d = 2, 3, 4) takes component passes."""
     lib = L.load()
 
     def ok(n, d, prec):
@@ -387,6 +387,8 @@ def test_streamed_j_size_limits():
         nb = ctypes.c_size_t(0)
         return lib.chym_integrate_workspace_size(ctypes.byref(prob), ctypes.byref(run), ctypes.byref(nb)) == L.CHYM_OK
 
-    for d, f32_max in ((1, 1024), (2, 832), (3, 544), (4, 416)):
-        assert ok(f32_max, d, L.CHYM_PREC_F32) and not ok(f32_max + 1, d, L.CHYM_PREC_F32), d
-        assert ok(1024, d, L.CHYM_PREC_BF16) and not ok(1025, d, L.CHYM_PREC_BF16), d
+    for d in (1, 2, 3, 4):
+        for prec in (L.CHYM_PREC_F32, L.CHYM_PREC_BF16):
+            assert ok(1024, d, prec) and not ok(1025, d, prec), (d, prec)
+        for n in (416, 417, 544, 545, 832, 833):
+            assert ok(n, d, L.CHYM_PREC_F32), (n, d)

@@ -3,7 +3,10 @@ D = 4, 16 pumps x 256 initial states = 4096 runs, 10 000 Euler steps with
 the dimensional anneal, bf16 form, with the three coupling storages of that
 workload (SK +-1 in int8, a Gaussian matrix rounded to bf16, the same
 matrix in FP8 E4M3 with E8M0 row exponents), launched as the bench's
-precision workload launches them (streamed-J kernel, caller workspace).
+precision workload launches them (streamed-J kernel, caller workspace);
+and the float32 form of the same problems (SK +-1 in int8, the Gaussian
+matrix in float32), which at this size takes the streamed-J kernel's
+component passes.
 
 Two kinds of check:
 
@@ -51,15 +54,18 @@ def inputs():
 
 
 def _storages(J):
-    """(name, device couplings, float64 values the device holds, oracle key)."""
+    """(name, device couplings, float64 values the device holds, oracle key,
+    precision form)."""
     ga = J["gauss"]
     fp8_dev = api.chym_quantize_fp8(to_dev(ga))
     codes, expo = fp8.quantize(ga)
     assert np.array_equal(fp8_dev.cpu().numpy(), fp8.pack(codes, expo))  # quantizer bytes at full size
     bf = torch.from_numpy(ga).to(torch.bfloat16)
-    return [("sk_pm1_int8", to_dev(J["sk"]), J["sk"].astype(np.float64), "sk"),
-            ("gauss_bf16", bf.to("cuda:0"), bf.to(torch.float64).numpy(), "gauss"),
-            ("gauss_fp8", fp8_dev, fp8.decode(codes, expo), "gauss")]
+    return [("sk_pm1_int8", to_dev(J["sk"]), J["sk"].astype(np.float64), "sk", "bf16"),
+            ("gauss_bf16", bf.to("cuda:0"), bf.to(torch.float64).numpy(), "gauss", "bf16"),
+            ("gauss_fp8", fp8_dev, fp8.decode(codes, expo), "gauss", "bf16"),
+            ("sk_pm1_int8_f32", to_dev(J["sk"]), J["sk"].astype(np.float64), "sk", "f32"),
+            ("gauss_f32", to_dev(ga.astype(np.float32)), ga.astype(np.float32).astype(np.float64), "gauss", "f32")]
 
 
 def test_precision_workload_full_size_error_report(inputs):
@@ -69,13 +75,14 @@ def test_precision_workload_full_size_error_report(inputs):
     p = {k: float(np.float32(v)) for k, v in gold.PARAMS.items()}
     pump_d, alpha_d = to_dev(pump), to_dev(alpha)
     x = to_dev(x0)
-    ws = torch.empty(api.chym_integrate_workspace_size(to_dev(J["sk"]), x, precision="bf16") + 256,
-                     dtype=torch.uint8, device="cuda:0")
+    storages = _storages(J)
+    nb = max(api.chym_integrate_workspace_size(Jd, x, precision=form) for _, Jd, _, _, form in storages)
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda:0")
     report = {}
-    for name, Jd, Jval, key in _storages(J):
-        print(f"[precision n1000] {name}: integrating {n}x{r}x{d}, {steps} steps", flush=True)
+    for name, Jd, Jval, key, form in storages:
+        print(f"[precision n1000] {name}: integrating {n}x{r}x{d}, {steps} steps, {form} form", flush=True)
         x.copy_(to_dev(x0))
-        api.chym_integrate(Jd, pump_d, x, alpha_d, eps=eps[key], steps=steps, precision="bf16", workspace=ws, **p)
+        api.chym_integrate(Jd, pump_d, x, alpha_d, eps=eps[key], steps=steps, precision=form, workspace=ws, **p)
         spins = torch.empty((r, api.spin_words(n)), dtype=torch.int64, device="cuda:0")
         dv = torch.empty(r, dtype=torch.uint8, device="cuda:0")
         api.chym_readout(x, spins=spins, diverged=dv)
@@ -91,7 +98,11 @@ def test_precision_workload_full_size_error_report(inputs):
         # exact on the GPU's own final states, every run
         assert not dv.cpu().numpy().any()
         np.testing.assert_array_equal(sg, oracle.readout(xg))
-        np.testing.assert_array_equal(eg, oracle.ising_energy(Jval, sg))
+        if Jd.dtype == torch.float32:
+            # float64 sums of float32 values need not be exact: summation order shows at 1e-16
+            np.testing.assert_allclose(eg, oracle.ising_energy(Jval, sg), rtol=1e-12)
+        else:
+            np.testing.assert_array_equal(eg, oracle.ising_energy(Jval, sg))
         sub = np.union1d(np.arange(0, r, 8), idx)  # every 8th run and the compared subset
         np.testing.assert_allclose(ehs.cpu().numpy()[sub], oracle.hs_energy(Jval, xg[:, sub, :]), rtol=1e-12)
 
@@ -120,13 +131,19 @@ def test_precision_workload_full_size_error_report(inputs):
         # the arithmetic.  Each bar is a few times the value first measured
         # (SK int8: readout 0.9999, E_hs median 1.4e-5, max 1.9e-3, 86% same
         # state; Gaussian bf16: 0.998, 3.2e-4, 5.5e-3; FP8: 0.971, 3.4e-3,
-        # 2.3e-2; mean relative Ising-energy change +1.1e-3 at most).
+        # 2.3e-2; mean relative Ising-energy change +1.1e-3 at most).  The
+        # float32 form ended every compared run in the oracle's state (SK int8:
+        # max |dx| 7.3e-4, E_hs median 1.1e-7, max 4.2e-5; Gaussian float32:
+        # 6.2e-4, 6.7e-8, 4.0e-6).
         bars = {"sk_pm1_int8": (0.999, 1e-4, 1e-2, 0.6), "gauss_bf16": (0.99, 2e-3, 3e-2, 0.0),
-                "gauss_fp8": (0.9, 1e-2, 8e-2, 0.0)}[name]
+                "gauss_fp8": (0.9, 1e-2, 8e-2, 0.0), "sk_pm1_int8_f32": (0.9999, 1e-6, 2e-4, 0.95),
+                "gauss_f32": (0.9999, 1e-6, 5e-5, 0.95)}[name]
         row = report[name]
         assert row["readout_agree"] >= bars[0], row
         assert row["hs_rel_median"] <= bars[1] and row["hs_rel_max"] <= bars[2], row
         assert row["same_state"] >= bars[3], row
         assert abs(row["ising_rel_mean"]) <= 5e-3, row
+        if form == "f32":
+            assert row["max_dx"] <= 5e-3, row
     for name, row in report.items():
         print(name, row)

@@ -179,3 +179,56 @@ def test_solve_batched_one_shot_equals_single_calls():
             np.testing.assert_array_equal(sig, oracle.readout(ref))
             np.testing.assert_array_equal(t["e_ising"].cpu().numpy(), oracle.ising_energy(c.J, sig).astype(np.int32))
             np.testing.assert_allclose(t["e_hs"].cpu().numpy(), oracle.hs_energy(c.J, ref), rtol=1e-12)
+
+
+@pytest.mark.parametrize("n,d,kind", [(416, 4, "sk"), (544, 3, "sk"), (832, 2, "sk"), (416, 4, "gauss")])
+def test_component_passes_equal_one_pass_bit_exact(n, d, kind):
+    """Float32 form: n is the largest size whose operand of all d components
+    fits LDS (one pass over J per step); the same problem padded with four
+    uncoupled zero rows takes component passes (d passes per step).  The
+    rows they share agree exactly, for integer couplings and for float ones
+    (three coupling terms)."""
+    small = Case(n, d, 24, 120, key=(46, n, d), kind=kind, sigma=0.05)
+    big = Case(n + 4, d, 24, 120, key=(46, n, d), kind=kind, sigma=0.05)
+    big.J = np.zeros((n + 4, n + 4), dtype=small.J.dtype)
+    big.J[:n, :n] = small.J
+    big.x0 = np.concatenate([small.x0, np.zeros((4, 24, d), np.float32)], axis=0)
+    big.eps = small.eps
+    a = run_gpu(small).cpu().numpy()
+    b = run_gpu(big).cpu().numpy()
+    assert np.array_equal(b[:n], a)
+    assert not b[n:].any()
+
+
+@pytest.mark.parametrize("n,d,r,steps,kind", [(600, 4, 16, 100, "sk"), (900, 2, 16, 80, "gauss"),
+                                              (1000, 3, 13, 60, "sk"), (1024, 4, 16, 40, "sk")])
+def test_component_passes_parity_f32(n, d, r, steps, kind):
+    """Float32 form beyond the one-pass sizes (d passes over J per step)
+    against the oracle's trajectory, ragged replica counts included."""
+    case = Case(n, d, r, steps, key=(47, n, d), kind=kind, sigma=0.05)
+    xg = run_gpu(case).cpu().numpy()
+    xo = oracle.ode_run(case.J, case.pump, case.x0, steps=steps, alpha=case.alpha, **case.params())
+    err = np.abs(xg - xo).max()
+    assert err <= 1e-4, err
+
+
+def test_component_passes_in_a_batch_equal_solo():
+    """Component-pass tasks (int8 couplings, staged as E4M3 bytes in a
+    batch; float couplings, three terms) beside a one-pass streamed-J task
+    and a resident one, across graph replays."""
+    specs = [(700, 4, 20, 60, "sk"), (560, 3, 17, 60, "gauss"), (400, 4, 16, 60, "sk"), (100, 3, 16, 60, "sk")]
+    cases = [Case(n, d, r, s, key=(48, i), kind=k, sigma=0.03) for i, (n, d, r, s, k) in enumerate(specs)]
+    tasks, solo = [], []
+    for c, (n, d, r, s, _) in zip(cases, specs):
+        Jd, pump, x, alpha = c.gpu_inputs()
+        tasks.append(dict(J=Jd, pump=pump, x=x, alpha=alpha, steps=s, precision="f32", **c.params()))
+        solo.append(run_gpu(c).cpu().numpy())
+    b = api.chym_batch_create(tasks)
+    for _ in range(2):
+        for t, c in zip(tasks, cases):
+            t["x"].copy_(to_dev(c.x0))
+        b.launch()
+        torch.cuda.synchronize()
+        for t, ref, sp in zip(tasks, solo, specs):
+            assert np.array_equal(t["x"].cpu().numpy(), ref), sp
+    b.destroy()
