@@ -260,7 +260,9 @@ def timed_events(torch, stream, fn, reps):
 def run_precision(args, torch, api, synth):
     """N = 1000, D = 4, 16 pumps x 256 initial states = 4096 replicas, 10000
     steps, BF16 form, three couplings: SK +-1 (int8, exact), Gaussian rounded
-    to bf16, Gaussian in FP8 (E4M3 + E8M0 row exponents)."""
+    to bf16, Gaussian in FP8 (E4M3 + E8M0 row exponents).  The float32 form of
+    the SK problem (component passes at this size) is timed beside it and
+    reported apart from the line's value."""
     dev = torch.device("cuda:0")
     n, d, steps = 1000, 4, args.euler_steps if args.euler_steps != 5000 else 10000
     R = 4096
@@ -275,8 +277,8 @@ def run_precision(args, torch, api, synth):
     eps["gauss_fp8"] = eps["gauss_bf16"]
     x0 = synth.initial_states_torch(n, R, d, seed=2308023293, device=dev)
     x = torch.empty_like(x0)
-    ws = torch.empty(api.chym_integrate_workspace_size(Js["sk_pm1_int8"], x, precision="bf16") + 256,
-                     dtype=torch.uint8, device=dev)
+    nb = max(api.chym_integrate_workspace_size(Js["sk_pm1_int8"], x, precision=p) for p in ("bf16", "f32"))
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
     res_kind = {}
 
@@ -300,6 +302,15 @@ def run_precision(args, torch, api, synth):
     ms_sk = res_kind["sk_pm1_int8"]
     flops = n * R * d * steps * 2.0 * (n - 1)
     achieved = flops / (ms_sk / 1e3) / 1e12
+
+    def run_f32():
+        api.chym_integrate(Js["sk_pm1_int8"], pumps, x, alpha, eps=float(eps["sk_pm1_int8"]), btil=1.0, eta=2e-4,
+                           dt=args.dt, steps=steps, precision="f32", workspace=ws)
+
+    x.copy_(x0)
+    run_f32()
+    x.copy_(x0)
+    ms_f32 = timed_events(torch, stream, run_f32, 1)
     return {"metric": METRIC, "value": upd / (wall / args.steps), "unit": "spin-component updates/s", "n_gpus": 1,
             "steps": args.steps, "warmup": 1, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
@@ -309,7 +320,11 @@ def run_precision(args, torch, api, synth):
             "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
                          "kernel": "k_integrate_slab<4, 1, 1, 8, 8> (SK +-1 J, bf16 fragments)", "kernel_ms": ms_sk},
-            "integrate_ms": res_kind}
+            "integrate_ms": res_kind,
+            "float32_form": {"couplings": "SK +-1 int8", "kernel": "k_integrate_slab<4, 3, 1, 8, 8, true> "
+                                                                   "(component passes)",
+                             "integrate_ms": ms_f32,
+                             "frac_bf16_peak": flops / (ms_f32 / 1e3) / 1e12 / PEAK_BF16_TFLOPS}}
 
 
 def run_batched(args, torch, api, synth):
