@@ -45,6 +45,12 @@ TRAFFIC_SOURCE = ("profiles/integrate_persistent_sk100_d23_f32.md: rocprofv3 --p
                   "of this kernel on this workload, scaled by the same counters on a copy of known size; "
                   "not measured in this run")
 TRAFFIC = {("k_integrate_persistent_lds<7, 3, 3, 1, 2>", 100, 1000, 2000): 9.70e9}
+# The same for the precision workload's +-1 launch (bf16 form, N = 1000, D = 4,
+# 4096 replicas, 10 000 steps), scaled by its own 65.5 MB state copies.
+PRECISION_TRAFFIC = 1.512e8
+PRECISION_TRAFFIC_SOURCE = ("profiles/hbm_traffic_slab_n1000_d4.md: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE of "
+                            "this kernel on this workload, scaled by the same counters on a copy of known size; "
+                            "not measured in this run")
 
 
 def kernel_name(tiles, d, precision, plan):
@@ -318,7 +324,8 @@ def run_precision(args, torch, api, synth):
                                    f"bf16 form; couplings SK +-1 int8, Gaussian bf16, Gaussian FP8 E4M3+E8M0",
                        "n": n, "d": d, "replicas": R, "euler_steps": steps, "precision": "bf16"},
             "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                         "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                         "frac": achieved / PEAK_BF16_TFLOPS, "traffic": PRECISION_TRAFFIC,
+                         "traffic_source": PRECISION_TRAFFIC_SOURCE,
                          "kernel": "k_integrate_slab<4, 1, 1, 8, 8> (SK +-1 J, bf16 fragments)", "kernel_ms": ms_sk},
             "integrate_ms": res_kind,
             "float32_form": {"couplings": "SK +-1 int8", "kernel": "k_integrate_slab<4, 3, 1, 8, 8, true> "
