@@ -14,6 +14,13 @@
 // the coupling rows and the block's pumps are staged in LDS too when the
 // rows fit a fixed budget (read from global memory otherwise).  A persistent
 // form takes (task, replica block) items of many problems from a counter.
+//
+// Short rows (w <= kEllRegW, e.g. 3-regular graphs) with few units per
+// thread (<= kEllRegUnits): a thread keeps its units' rows, pumps and own
+// state in registers for the whole run, so a step reads from LDS only the
+// neighbours' state (w independent loads per component) instead of the row,
+// then the neighbours, then its own state; the arithmetic and its order are
+// the same, so the results are identical.
 #include "chym_internal.h"
 
 namespace chym {
@@ -21,6 +28,8 @@ namespace chym {
 constexpr size_t kEllMaxLds = 159 * 1024;
 constexpr size_t kEllRowBudget = 32 * 1024;  // LDS for the coupling rows
 constexpr int kEllThreads = 1024;
+constexpr int kEllRegW = 3;      // register path: at most this many couplings per row
+constexpr int kEllRegUnits = 4;  // and this many (row, replica) units per thread
 
 __host__ __device__ inline int ell_rb(int n, int d) {
     for (int rb = 16; rb >= 1; rb >>= 1)
@@ -71,6 +80,71 @@ __device__ __forceinline__ void ell_block(const IntegArgs &a, int rep0, int lrb,
     const float nbd = -(a.dt * a.btil);
     const float ned = -(a.dt * a.eta);
     const float dte = a.dt * a.eps;
+    const int upt = (units + (int)blockDim.x - 1) / (int)blockDim.x;
+    if (e.w <= kEllRegW && upt <= kEllRegUnits) {
+        // register path: unit i of this thread is u = threadIdx.x + i blockDim.x
+        int nq[kEllRegUnits][kEllRegW];
+        float nv[kEllRegUnits][kEllRegW];
+        float xv[kEllRegUnits][D];
+        float base[kEllRegUnits];
+#pragma unroll
+        for (int i = 0; i < kEllRegUnits; ++i) {
+            const int u = (int)threadIdx.x + i * (int)blockDim.x;
+            const bool own = i < upt && u < units;
+            const int *row = own ? (staged ? rl + (size_t)(u >> lrb) * 2 * e.w : e.row(u >> lrb)) : nullptr;
+#pragma unroll
+            for (int kk = 0; kk < kEllRegW; ++kk) {
+                nq[i][kk] = (own && kk < e.w) ? row[kk] : -1;
+                nv[i][kk] = (own && kk < e.w) ? __int_as_float(row[e.w + kk]) : 0.0f;
+            }
+            const int jr = u & (rb - 1);
+            base[i] = (own && rep0 + jr < r) ? fmaf(a.dt, pl[jr] - 1.0f, 1.0f) : 0.0f;
+#pragma unroll
+            for (int mu = 0; mu < D; ++mu) xv[i][mu] = own ? xa[u * D + mu] : 0.0f;
+        }
+        for (int k = 0; k < a.steps; ++k) {
+            const float *al = a.alpha + (size_t)(a.start_step + k) * D;
+            float ga[D];
+#pragma unroll
+            for (int mu = 0; mu < D; ++mu) ga[mu] = dte * al[mu];
+#pragma unroll
+            for (int i = 0; i < kEllRegUnits; ++i) {
+                const int u = (int)threadIdx.x + i * (int)blockDim.x;
+                if (i < upt && u < units) {
+                    const int jr = u & (rb - 1);
+                    float G[D];
+#pragma unroll
+                    for (int mu = 0; mu < D; ++mu) G[mu] = 0.0f;
+#pragma unroll
+                    for (int kk = 0; kk < kEllRegW; ++kk) {
+                        const int q = nq[i][kk];
+                        if ((unsigned)q < (unsigned)n) {
+                            const float *xq = xa + (((size_t)q << lrb) + jr) * D;
+#pragma unroll
+                            for (int mu = 0; mu < D; ++mu) G[mu] = fmaf(nv[i][kk], xq[mu], G[mu]);
+                        }
+                    }
+                    float x2[D];
+#pragma unroll
+                    for (int mu = 0; mu < D; ++mu) x2[mu] = xv[i][mu] * xv[i][mu];
+                    float S = x2[0];
+#pragma unroll
+                    for (int mu = 1; mu < D; ++mu) S = S + x2[mu];
+                    const float cc = fmaf(nbd, S, base[i]);
+#pragma unroll
+                    for (int mu = 0; mu < D; ++mu) {
+                        const float y = xv[i][mu] * fmaf(ned, x2[mu], cc);
+                        xv[i][mu] = fmaf(ga[mu], G[mu], y);
+                        xb[u * D + mu] = xv[i][mu];
+                    }
+                }
+            }
+            __syncthreads();
+            float *t = xa;
+            xa = xb;
+            xb = t;
+        }
+    } else
     for (int k = 0; k < a.steps; ++k) {
         const float *al = a.alpha + (size_t)(a.start_step + k) * D;
         float ga[D];

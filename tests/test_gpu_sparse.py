@@ -67,6 +67,18 @@ def test_sparse_scores_and_solve():
     np.testing.assert_array_equal(res["e_ising_f64"].cpu().numpy(), oracle.ising_energy(case.J, sig))
 
 
+@pytest.mark.parametrize("n,d,r", [(96, 2, 32), (800, 3, 8), (400, 4, 12)])
+def test_sparse_register_path_equals_lds_path(n, d, r):
+    """Rows of width 3 with at most four (row, replica) units per thread take
+    the register path; the same couplings padded to width 4 (a zero coupling,
+    which adds an exact zero) take the LDS path.  Bit-identical, with 2, 4
+    and 4 units per thread."""
+    case = Case(n, d, r, 200, key=(85, n, d), kind="reg3", sigma=0.05)
+    a = run(case, ell_dev(case.J)).cpu().numpy()
+    b = run(case, ell_dev(case.J, width=4)).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
 def test_sparse_padding_precision_forms_and_dense_agreement():
     n, d, r = 96, 2, 32
     case = Case(n, d, r, 300, key=(82,), kind="reg3", sigma=0.05)
