@@ -74,27 +74,35 @@ bool slab_shape_exists(int tiles, int d, int xs, int js, int waves) {
     return slab_lds_bytes(tiles, d, xs) <= kSlabMaxLds && lookup_slab(tiles, d, xs, js, waves).single != nullptr;
 }
 
-// Decides whether the couplings can be staged as E4M3 bytes: every row must
-// be a set of E4M3 values times one power of two (the row scale, chosen as
-// in the FP8 quantizer), checked element by element; FP8 storage always
-// qualifies.  Writes the header flag and the row scales.  Run by one block
-// of 1024 threads: wavefront w takes rows w, w + 16, ...  (Batches only: a
-// single problem's staging is always bf16, k_stage_bf16_header.)
+// Decides the staging format of the couplings, checked element by element:
+// E2M1 codes when every coupling is -1, 0 or +1; else E4M3 bytes when every
+// row is a set of E4M3 values times one power of two (the row scale, chosen
+// as in the FP8 quantizer; FP8 storage always qualifies); else bf16.
+// Writes the header and the row scales.  Run by one block of 1024 threads:
+// wavefront w takes rows w, w + 16, ...  (Batches only: a single problem's
+// staging is always bf16, k_stage_bf16_header.)
 __device__ __forceinline__ void stage_prep_block(const IntegArgs &a, int tiles, unsigned char *__restrict__ stage) {
-    __shared__ int s_ok;
-    if (threadIdx.x == 0) s_ok = 1;
+    __shared__ int s_ok, s_pm1;
+    if (threadIdx.x == 0) {
+        s_ok = 1;
+        s_pm1 = 1;
+    }
     __syncthreads();
     float *scale = reinterpret_cast<float *>(stage + kStageHeader);
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int n = a.n;
-    bool ok = true;
+    bool ok = true, pm1 = true;
     for (int p = w; p < tiles * 16; p += 16) {
         float sc = 1.0f;
         if (p < n) {
             if (a.j_dtype == CHYM_J_FP8) {
                 const uint32_t e = reinterpret_cast<const uint8_t *>(a.j)[(size_t)n * n + p];
                 sc = e == 0xffu ? __builtin_nanf("") : ldexpf(1.0f, (int)e - 127);
+                for (int q = lane; q < n; q += 64) {
+                    const float v = coupling(a.j, a.j_dtype, n, p, q);
+                    if (!(v == 0.0f || v == 1.0f || v == -1.0f)) pm1 = false;
+                }
             } else {
                 float amax = 0.0f;
                 bool fin = true;
@@ -102,6 +110,7 @@ __device__ __forceinline__ void stage_prep_block(const IntegArgs &a, int tiles, 
                     const float v = coupling(a.j, a.j_dtype, n, p, q);
                     fin = fin && __builtin_isfinite(v);
                     amax = fmaxf(amax, fabsf(v));
+                    if (!(v == 0.0f || v == 1.0f || v == -1.0f)) pm1 = false;
                 }
                 for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
                 const int e = e4m3_row_exponent(amax);
@@ -119,13 +128,16 @@ __device__ __forceinline__ void stage_prep_block(const IntegArgs &a, int tiles, 
         if (lane == 0) scale[p] = sc;
     }
     if (!ok) atomicAnd(&s_ok, 0);
+    if (!pm1) atomicAnd(&s_pm1, 0);
     __syncthreads();
-    if (threadIdx.x == 0) *reinterpret_cast<int *>(stage) = (a.j_dtype == CHYM_J_FP8) ? 1 : s_ok;
+    if (threadIdx.x == 0)
+        *reinterpret_cast<int *>(stage) = s_pm1 ? kStageE2M1
+                                                : ((a.j_dtype == CHYM_J_FP8 || s_ok) ? kStageE4M3 : kStageBf16);
 }
 
-// A single problem's staging header: bf16 fragments (flag 0).
+// A single problem's staging header: bf16 fragments.
 __global__ void k_stage_bf16_header(unsigned char *__restrict__ stage) {
-    if (threadIdx.x == 0) *reinterpret_cast<int *>(stage) = 0;
+    if (threadIdx.x == 0) *reinterpret_cast<int *>(stage) = kStageBf16;
 }
 
 // The same for the tasks list[0 .. n) of a batch, one block each.

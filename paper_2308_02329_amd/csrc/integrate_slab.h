@@ -17,12 +17,15 @@
 // kernel, so the two kernels accumulate every G in the same order and give
 // identical results.  J is staged once per problem into the caller's
 // workspace as A fragments in that order and is streamed from L2 every step
-// (at this size it does not fit in LDS).  In batches, when every row of J
-// is a set of E4M3 values times one power of two (+-1 couplings in any
-// storage, FP8 storage always), J is staged as one byte per coupling and
-// widened to bf16 in registers (v_cvt_scalef32_pk_bf16_fp8, exact); this
-// halves the L2 footprint and traffic of the many couplings a batch streams
-// at once.  A single problem's J stays bf16 (k_integrate_slab).
+// (at this size it does not fit in LDS).  In batches, J is staged narrower
+// where that is exact, and widened to bf16 in registers: couplings in
+// {-1, 0, +1} (in any storage) as four-bit E2M1 codes
+// (v_cvt_scalef32_pk_bf16_fp4), otherwise, when every row of J is a set of
+// E4M3 values times one power of two (FP8 storage always), as one E4M3 byte
+// per coupling (v_cvt_scalef32_pk_bf16_fp8).  This cuts the L2 footprint
+// and the HBM traffic of the many distinct couplings a batch streams at once
+// (a quarter, or half, of the bf16 bytes).  A single problem's J stays bf16
+// (k_integrate_slab).
 //
 // Per step: for each group of four owned tiles, accumulate G over all
 // chunks (the J fragments of the next chunk are fetched while the current
@@ -46,11 +49,15 @@
 namespace chym {
 
 // Staged couplings of one problem (caller workspace, 256-byte aligned):
-//   [0, 256)           header: int32, 1 if the fragments are E4M3 bytes
+//   [0, 256)           header: int32 format, kStageBf16, kStageE4M3 or kStageE2M1
 //   [256, 256 + S)     float row scales 2^e_p [tiles * 16] (E4M3 fragments)
-//   [256 + S, ...)     fragments: bf16 [tile][chunk][JS][64 lanes] x 16 B, or
-//                      E4M3 [tile][chunk][64 lanes] x 8 B
+//   [256 + S, ...)     fragments: bf16 [tile][chunk][JS][64 lanes] x 16 B,
+//                      E4M3 [tile][chunk][64 lanes] x 8 B, or
+//                      E2M1 [tile][chunk][64 lanes] x 4 B
 constexpr size_t kStageHeader = 256;
+constexpr int kStageBf16 = 0;
+constexpr int kStageE4M3 = 1;
+constexpr int kStageE2M1 = 2;  // couplings in {-1, 0, +1}
 // the most chunks of J fragments the streamed-J kernel keeps in flight (its
 // prefetch ring); the staging carries that many chunks of padding after the
 // last tile
@@ -74,6 +81,22 @@ __device__ __forceinline__ uint2 load_frag8(__amdgpu_buffer_rsrc_t r, int voff, 
     typedef __attribute__((ext_vector_type(2))) int i2;
     const i2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
     return uint2{(uint32_t)v.x, (uint32_t)v.y};
+}
+
+__device__ __forceinline__ uint32_t load_frag4(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+}
+
+// Eight E2M1 codes (slot s in nibble s: byte s / 2, low nibble first) as
+// bf16; the instruction widens byte b into slots 2b (low nibble), 2b + 1.
+__device__ __forceinline__ bf16x8 fp4_fragment(uint32_t w) {
+    const bf16x2 a = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp4(w, 1.0f, 0);
+    const bf16x2 b = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp4(w, 1.0f, 1);
+    const bf16x2 c = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp4(w, 1.0f, 2);
+    const bf16x2 d = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp4(w, 1.0f, 3);
+    const auto ab = __builtin_shufflevector(a, b, 0, 1, 2, 3);
+    const auto cd = __builtin_shufflevector(c, d, 0, 1, 2, 3);
+    return __builtin_shufflevector(ab, cd, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
 // Eight E4M3 codes (slots 0..7 in byte order) times a power of two, as bf16.
@@ -127,7 +150,7 @@ __device__ __forceinline__ void slab_write_tile(const float (&xt)[D][4], int I, 
 }
 
 // Integrates the column slab rep0 .. rep0+15 of problem a.  stage: the
-// staged couplings (layout above); F8: its fragments are E4M3 bytes; ncp:
+// staged couplings (layout above); FMT: the fragments' format (kStage*); ncp:
 // chunk count of the staging; lb: LDS operand area of ncp * D * XS
 // fragments.  Called by all W wavefronts of the block; contains block
 // barriers.
@@ -142,7 +165,7 @@ __device__ __forceinline__ void slab_write_tile(const float (&xt)[D][4], int I, 
 // one: J does not change between steps).  Every refill is a load, so a slot's
 // next value is always the register its load writes, and the prefetch crosses
 // group and step boundaries.
-template <int D, int XS, int JS, int TPW, bool F8, int W, int RDB = 2, bool CP = false>
+template <int D, int XS, int JS, int TPW, int FMT, int W, int RDB = 2, bool CP = false>
 __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, const unsigned char *__restrict__ stage,
                                                int ncp, bf16x8 *lb) {
     // tiles accumulated together (register budget per lane: 128 at four
@@ -152,7 +175,9 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
     constexpr int NG = TPW / GS;        // groups of owned tiles
     // chunks of J fragments in flight: E4M3 fragments take two registers
     // per tile, bf16 ones four per term (RDB chunks)
-    constexpr int RD = F8 ? 4 : RDB;
+    constexpr bool F8 = FMT == kStageE4M3;
+    constexpr bool F4 = FMT == kStageE2M1;
+    constexpr int RD = FMT != kStageBf16 ? 4 : RDB;
     static_assert(RD <= kSlabRingChunks, "the staging pads kSlabRingChunks chunks past the last tile");
     // PF: the state operand of the next chunk is read from LDS while the
     // current chunk's products run, where its registers fit
@@ -173,8 +198,8 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
     const bool valid = rep < r;
     // J fragments through a buffer resource: per-lane offset lane * bytes,
     // wave-uniform offset of (tile, chunk, term) in scalar registers
-    constexpr int FB = F8 ? 8 : 16;                // bytes per lane per fragment
-    constexpr int CHB = (F8 ? 1 : JS) * 64 * FB;   // bytes per (tile, chunk)
+    constexpr int FB = F8 ? 8 : (F4 ? 4 : 16);                    // bytes per lane per fragment
+    constexpr int CHB = (FMT != kStageBf16 ? 1 : JS) * 64 * FB;   // bytes per (tile, chunk)
     const __amdgpu_buffer_rsrc_t jres = buffer_over(stage + stage_frag_offset(nt), (uint32_t)(nt * ncp * CHB));
     const int jvoff = lane * FB;
     // row scales 2^e_p of the E4M3 fragments (per-lane offset jcol, tile offset uniform)
@@ -218,8 +243,9 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
     }
 
     // the ring holds the first RD chunks of group 0; the scales of group 0
-    bf16x8 ring[F8 ? 1 : RD][GS][JS];
+    bf16x8 ring[FMT != kStageBf16 ? 1 : RD][GS][JS];
     uint2 ring8[F8 ? RD : 1][GS];
+    uint32_t ring4[F4 ? RD : 1][GS];
     float sc[GS];
 #pragma unroll
     for (int i = 0; i < GS; ++i) sc[i] = F8 ? scale_of(0, i) : 1.0f;
@@ -231,6 +257,8 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
             // staging's padding, loaded and never used
             if constexpr (F8) {
                 ring8[sl][i] = load_frag8(jres, jvoff, tile_off(0, i) + sl * CHB);
+            } else if constexpr (F4) {
+                ring4[sl][i] = load_frag4(jres, jvoff, tile_off(0, i) + sl * CHB);
             } else {
 #pragma unroll
                 for (int t = 0; t < JS; ++t) ring[sl][i][t] = load_frag16(jres, jvoff, tile_off(0, i) + sl * CHB + t * 1024);
@@ -317,6 +345,9 @@ __device__ __forceinline__ void integrate_slab(const IntegArgs &a, int rep0, con
                     if constexpr (F8) {
                         af[i][0] = fp8_fragment(ring8[sl][i], sc[i]);
                         ring8[sl][i] = load_frag8(jres, jvoff, nxt);
+                    } else if constexpr (F4) {
+                        af[i][0] = fp4_fragment(ring4[sl][i]);
+                        ring4[sl][i] = load_frag4(jres, jvoff, nxt);
                     } else {
 #pragma unroll
                         for (int t = 0; t < JS; ++t) {
@@ -437,15 +468,29 @@ __device__ __forceinline__ void stage_jfrag_part(const IntegArgs &a, int ncp, un
                                                  int first, int stride) {
     const int nt = (a.n + 15) / 16;
     const int total = nt * ncp * 64;
-    const bool f8 = JS == 1 && *reinterpret_cast<const int *>(stage) != 0;
+    const int fmt = JS == 1 ? *reinterpret_cast<const int *>(stage) : kStageBf16;
     const float *scale = reinterpret_cast<const float *>(stage + kStageHeader);
     bf16x8 *out = reinterpret_cast<bf16x8 *>(stage + stage_frag_offset(nt));
     uint2 *out8 = reinterpret_cast<uint2 *>(stage + stage_frag_offset(nt));
+    uint32_t *out4 = reinterpret_cast<uint32_t *>(stage + stage_frag_offset(nt));
     for (int idx = first; idx < total; idx += stride) {
         const int lane = idx & 63;
         const int c = (idx >> 6) % ncp;
         const int I = (idx >> 6) / ncp;
-        if (f8) {
+        if (fmt == kStageE2M1) {
+            // every coupling is -1, 0 or +1: E2M1 codes 0xA, 0x0, 0x2
+            const int i = lane & 15, g = lane >> 4;
+            const int p = 16 * I + i;
+            uint32_t wd = 0u;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int q = 32 * c + 16 * (s >> 2) + 4 * g + (s & 3);
+                const float v = (p < a.n && q < a.n) ? coupling(a.j, a.j_dtype, a.n, p, q) : 0.0f;
+                const uint32_t code = v > 0.0f ? 0x2u : (v < 0.0f ? 0xAu : 0x0u);
+                wd |= code << (4 * s);
+            }
+            out4[(size_t)(I * ncp + c) * 64 + lane] = wd;
+        } else if (fmt == kStageE4M3) {
             const int i = lane & 15, g = lane >> 4;
             const int p = 16 * I + i;
             const int e = p < a.n ? ilogbf(scale[p]) : 0;
@@ -487,17 +532,22 @@ __global__ __launch_bounds__(256) void k_stage_jfrag_batched(const IntegArgs *__
     stage_jfrag_part<JS>(a, ncps[t], stages[t], (blockIdx.x % bpt) * blockDim.x + threadIdx.x, bpt * blockDim.x);
 }
 
-// The E4M3 path exists for single-term couplings; the flag is uniform.
+// The narrow formats exist for single-term couplings; the header is uniform.
 template <int D, int XS, int JS, int TPW, int W, bool CP>
 __device__ __forceinline__ void slab_run(const IntegArgs &a, int rep0, const unsigned char *stage, int ncp,
                                          bf16x8 *lb) {
     if constexpr (JS == 1) {
-        if (__builtin_amdgcn_readfirstlane(*reinterpret_cast<const int *>(stage)) != 0) {
-            integrate_slab<D, XS, JS, TPW, true, W, 2, CP>(a, rep0, stage, ncp, lb);
+        const int fmt = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int *>(stage));
+        if (fmt == kStageE2M1) {
+            integrate_slab<D, XS, JS, TPW, kStageE2M1, W, 2, CP>(a, rep0, stage, ncp, lb);
+            return;
+        }
+        if (fmt == kStageE4M3) {
+            integrate_slab<D, XS, JS, TPW, kStageE4M3, W, 2, CP>(a, rep0, stage, ncp, lb);
             return;
         }
     }
-    integrate_slab<D, XS, JS, TPW, false, W, 2, CP>(a, rep0, stage, ncp, lb);
+    integrate_slab<D, XS, JS, TPW, kStageBf16, W, 2, CP>(a, rep0, stage, ncp, lb);
 }
 
 // Column slabs of one problem: block b integrates replicas 16 b .. 16 b + 15.
@@ -514,7 +564,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W / 4)))
 void k_integrate_slab(IntegArgs a, const unsigned char *__restrict__ stage, int ncp) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int RDB = (W == 8 && XS == 1 && JS == 1) ? 4 : 2;
-    integrate_slab<D, XS, JS, TPW, false, W, RDB, CP>(a, blockIdx.x * 16, stage, ncp,
+    integrate_slab<D, XS, JS, TPW, kStageBf16, W, RDB, CP>(a, blockIdx.x * 16, stage, ncp,
                                                       reinterpret_cast<bf16x8 *>(smem));
 }
 

@@ -121,18 +121,22 @@ def test_mixed_batch_with_slab_tasks_equals_solo():
 
 def test_batch_stages_every_coupling_storage():
     """Streamed-J and resident tasks with float32 (three coupling terms),
-    bf16, FP8 and int8 couplings in one batch: each task's staging (three
-    bf16 terms, bf16 fragments, E4M3 bytes) happens in the batch's two
-    staging launches, and every task equals its own single call bit for bit,
-    on every replay."""
+    bf16, FP8 and int8 couplings, Gaussian and +-1, in one batch: each
+    task's staging (three bf16 terms; bf16 fragments; E4M3 bytes for FP8
+    storage; E2M1 codes for +-1 couplings in int8, bf16 or FP8 storage)
+    happens in the batch's two staging launches, and every task equals its
+    own single call (always bf16 fragments) bit for bit, on every replay."""
     specs = [  # n, d, r, steps, couplings, form
         (200, 2, 20, 120, "f32", "f32"), (300, 3, 17, 100, "bf16", "bf16"), (250, 2, 33, 100, "fp8", "bf16"),
-        (400, 1, 16, 80, "i8", "f32"), (100, 2, 24, 150, "f32", "f32"), (180, 4, 16, 90, "fp8", "f32")]
+        (400, 1, 16, 80, "i8", "f32"), (100, 2, 24, 150, "f32", "f32"), (180, 4, 16, 90, "fp8", "f32"),
+        (260, 3, 19, 100, "i8", "bf16"), (220, 2, 16, 100, "bf16_pm1", "bf16"), (240, 4, 16, 90, "fp8_pm1", "bf16"),
+        (600, 4, 16, 60, "i8", "f32")]
     tasks, solo, cases = [], [], []
     for i, (n, d, r, s, jd, prec) in enumerate(specs):
-        c = Case(n, d, r, s, key=(46, i), kind="sk" if jd == "i8" else "gauss", sigma=0.03)
+        c = Case(n, d, r, s, key=(46, i), kind="sk" if jd in ("i8", "bf16_pm1", "fp8_pm1") else "gauss", sigma=0.03)
         Jf = to_dev(c.J.astype(np.float32))
-        Jd = {"f32": Jf, "bf16": Jf.to(torch.bfloat16), "fp8": api.chym_quantize_fp8(Jf), "i8": to_dev(c.J)}[jd]
+        Jd = {"f32": Jf, "bf16": Jf.to(torch.bfloat16), "fp8": api.chym_quantize_fp8(Jf), "i8": to_dev(c.J),
+              "bf16_pm1": Jf.to(torch.bfloat16), "fp8_pm1": api.chym_quantize_fp8(Jf)}[jd]
         _, pump, x, alpha = c.gpu_inputs()
         xs = to_dev(c.x0)
         ws = torch.empty(api.chym_integrate_workspace_size(Jd, xs, precision=prec) + 256, dtype=torch.uint8,
