@@ -31,9 +31,14 @@ constexpr int kEllThreads = 1024;
 constexpr int kEllRegW = 3;      // register path: at most this many couplings per row
 constexpr int kEllRegUnits = 4;  // and this many (row, replica) units per thread
 
+// Floats per (row, replica) unit in LDS: d, with d = 3 padded to 4, so that
+// a unit is one 4-, 8- or 16-byte access and the lanes of a wavefront, which
+// read consecutive units of a row, touch consecutive banks.
+__host__ __device__ constexpr int ell_unit_floats(int d) { return d == 3 ? 4 : d; }
+
 __host__ __device__ inline int ell_rb(int n, int d) {
     for (int rb = 16; rb >= 1; rb >>= 1)
-        if (2 * (size_t)n * rb * d * sizeof(float) + kEllRowBudget + 64 <= kEllMaxLds) return rb;
+        if (2 * (size_t)n * rb * ell_unit_floats(d) * sizeof(float) + kEllRowBudget + 64 <= kEllMaxLds) return rb;
     return 0;
 }
 
@@ -46,7 +51,36 @@ __host__ __device__ inline int ell_log2(int rb) {
 }
 
 size_t ell_lds_bytes(int n, int d) {
-    return 2 * (size_t)n * ell_rb(n, d) * d * sizeof(float) + 16 * sizeof(float) + kEllRowBudget;
+    return 2 * (size_t)n * ell_rb(n, d) * ell_unit_floats(d) * sizeof(float) + 16 * sizeof(float) + kEllRowBudget;
+}
+
+// The D values of unit u of an LDS state buffer, as one access.
+template <int D>
+__device__ __forceinline__ void ell_get(const float *buf, size_t u, float (&v)[D]) {
+    if constexpr (D == 1) {
+        v[0] = buf[u];
+    } else if constexpr (D == 2) {
+        const float2 t = reinterpret_cast<const float2 *>(buf)[u];
+        v[0] = t.x;
+        v[1] = t.y;
+    } else {
+        const float4 t = reinterpret_cast<const float4 *>(buf)[u];
+        v[0] = t.x;
+        v[1] = t.y;
+        v[2] = t.z;
+        if constexpr (D == 4) v[3] = t.w;
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void ell_put(float *buf, size_t u, const float (&v)[D]) {
+    if constexpr (D == 1) {
+        buf[u] = v[0];
+    } else if constexpr (D == 2) {
+        reinterpret_cast<float2 *>(buf)[u] = float2{v[0], v[1]};
+    } else {
+        reinterpret_cast<float4 *>(buf)[u] = float4{v[0], v[1], v[2], D == 4 ? v[D - 1] : 0.0f};
+    }
 }
 
 // Integrates replicas rep0 .. rep0 + 2^lrb - 1 of problem a; called by all
@@ -58,8 +92,9 @@ __device__ __forceinline__ void ell_block(const IntegArgs &a, int rep0, int lrb,
     const int rb = 1 << lrb;
     const int units = n << lrb;
     float *xa = sm;
-    float *xb = sm + (size_t)units * D;
-    float *pl = xb + (size_t)units * D;                  // pumps of the block's replicas [16]
+    constexpr int UF = ell_unit_floats(D);
+    float *xb = sm + (size_t)units * UF;
+    float *pl = xb + (size_t)units * UF;                 // pumps of the block's replicas [16]
     int *rl = reinterpret_cast<int *>(pl + 16);          // coupling rows [n][2 w], if they fit
     const EllView e = ell_view(a.j, n);
     const bool staged = (size_t)n * 2 * e.w * sizeof(int) <= kEllRowBudget;
@@ -72,8 +107,10 @@ __device__ __forceinline__ void ell_block(const IntegArgs &a, int rep0, int lrb,
     for (int u = threadIdx.x; u < units; u += blockDim.x) {
         const int p = u >> lrb;
         const int rep = rep0 + (u & (rb - 1));
+        float v[D];
 #pragma unroll
-        for (int mu = 0; mu < D; ++mu) xa[u * D + mu] = rep < r ? a.x[((size_t)p * r + rep) * D + mu] : 0.0f;
+        for (int mu = 0; mu < D; ++mu) v[mu] = rep < r ? a.x[((size_t)p * r + rep) * D + mu] : 0.0f;
+        ell_put<D>(xa, u, v);
     }
     __syncthreads();
 
@@ -99,8 +136,12 @@ __device__ __forceinline__ void ell_block(const IntegArgs &a, int rep0, int lrb,
             }
             const int jr = u & (rb - 1);
             base[i] = (own && rep0 + jr < r) ? fmaf(a.dt, pl[jr] - 1.0f, 1.0f) : 0.0f;
+            if (own) {
+                ell_get<D>(xa, u, xv[i]);
+            } else {
 #pragma unroll
-            for (int mu = 0; mu < D; ++mu) xv[i][mu] = own ? xa[u * D + mu] : 0.0f;
+                for (int mu = 0; mu < D; ++mu) xv[i][mu] = 0.0f;
+            }
         }
         for (int k = 0; k < a.steps; ++k) {
             const float *al = a.alpha + (size_t)(a.start_step + k) * D;
@@ -119,7 +160,8 @@ __device__ __forceinline__ void ell_block(const IntegArgs &a, int rep0, int lrb,
                     for (int kk = 0; kk < kEllRegW; ++kk) {
                         const int q = nq[i][kk];
                         if ((unsigned)q < (unsigned)n) {
-                            const float *xq = xa + (((size_t)q << lrb) + jr) * D;
+                            float xq[D];
+                            ell_get<D>(xa, ((size_t)q << lrb) + jr, xq);
 #pragma unroll
                             for (int mu = 0; mu < D; ++mu) G[mu] = fmaf(nv[i][kk], xq[mu], G[mu]);
                         }
@@ -135,8 +177,8 @@ __device__ __forceinline__ void ell_block(const IntegArgs &a, int rep0, int lrb,
                     for (int mu = 0; mu < D; ++mu) {
                         const float y = xv[i][mu] * fmaf(ned, x2[mu], cc);
                         xv[i][mu] = fmaf(ga[mu], G[mu], y);
-                        xb[u * D + mu] = xv[i][mu];
                     }
+                    ell_put<D>(xb, u, xv[i]);
                 }
             }
             __syncthreads();
@@ -156,16 +198,15 @@ __device__ __forceinline__ void ell_block(const IntegArgs &a, int rep0, int lrb,
             const int rep = rep0 + jr;
             const float base = rep < r ? fmaf(a.dt, pl[jr] - 1.0f, 1.0f) : 0.0f;  // 1 + dt (r_i - 1)
             float xv[D], G[D];
+            ell_get<D>(xa, u, xv);
 #pragma unroll
-            for (int mu = 0; mu < D; ++mu) {
-                xv[mu] = xa[u * D + mu];
-                G[mu] = 0.0f;
-            }
+            for (int mu = 0; mu < D; ++mu) G[mu] = 0.0f;
             for (int kk = 0; kk < e.w; ++kk) {
                 const int q = row[kk];
                 if ((unsigned)q < (unsigned)n) {
                     const float jv = __int_as_float(row[e.w + kk]);
-                    const float *xq = xa + (((size_t)q << lrb) + jr) * D;
+                    float xq[D];
+                    ell_get<D>(xa, ((size_t)q << lrb) + jr, xq);
 #pragma unroll
                     for (int mu = 0; mu < D; ++mu) G[mu] = fmaf(jv, xq[mu], G[mu]);
                 }
@@ -177,11 +218,13 @@ __device__ __forceinline__ void ell_block(const IntegArgs &a, int rep0, int lrb,
 #pragma unroll
             for (int mu = 1; mu < D; ++mu) S = S + x2[mu];
             const float cc = fmaf(nbd, S, base);
+            float xn[D];
 #pragma unroll
             for (int mu = 0; mu < D; ++mu) {
                 const float y = xv[mu] * fmaf(ned, x2[mu], cc);
-                xb[u * D + mu] = fmaf(ga[mu], G[mu], y);
+                xn[mu] = fmaf(ga[mu], G[mu], y);
             }
+            ell_put<D>(xb, u, xn);
         };
         if (staged) {
             for (int u = threadIdx.x; u < units; u += blockDim.x) unit(u, rl + (size_t)(u >> lrb) * 2 * e.w);
@@ -198,8 +241,10 @@ __device__ __forceinline__ void ell_block(const IntegArgs &a, int rep0, int lrb,
         const int p = u >> lrb;
         const int rep = rep0 + (u & (rb - 1));
         if (rep < r) {
+            float v[D];
+            ell_get<D>(xa, u, v);
 #pragma unroll
-            for (int mu = 0; mu < D; ++mu) a.x[((size_t)p * r + rep) * D + mu] = xa[u * D + mu];
+            for (int mu = 0; mu < D; ++mu) a.x[((size_t)p * r + rep) * D + mu] = v[mu];
         }
     }
 }
