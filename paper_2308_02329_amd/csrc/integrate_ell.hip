@@ -36,9 +36,14 @@ constexpr int kEllRegUnits = 4;  // and this many (row, replica) units per threa
 // read consecutive units of a row, touch consecutive banks.
 __host__ __device__ constexpr int ell_unit_floats(int d) { return d == 3 ? 4 : d; }
 
+// Replicas per block: the largest power of two up to 16 whose double-buffered
+// state fits LDS and that leaves at most kEllRegUnits units per thread (so
+// that short rows take the register path at every size).
 __host__ __device__ inline int ell_rb(int n, int d) {
     for (int rb = 16; rb >= 1; rb >>= 1)
-        if (2 * (size_t)n * rb * ell_unit_floats(d) * sizeof(float) + kEllRowBudget + 64 <= kEllMaxLds) return rb;
+        if (2 * (size_t)n * rb * ell_unit_floats(d) * sizeof(float) + kEllRowBudget + 64 <= kEllMaxLds &&
+            (rb == 1 || (size_t)n * rb <= (size_t)kEllRegUnits * kEllThreads))
+            return rb;
     return 0;
 }
 
