@@ -79,6 +79,29 @@ def test_sparse_register_path_equals_lds_path(n, d, r):
     assert np.array_equal(a, b)
 
 
+def test_sparse_register_path_short_rows():
+    """Rows of width 2 (a +-1 ring) and mixed widths 0-3 on the register
+    path (unused slots skipped) against the same couplings padded to width 4
+    (LDS path) and against the oracle."""
+    n, d, r = 150, 3, 20
+    case = Case(n, d, r, 300, key=(86,), kind="reg3", sigma=0.05)
+    g = np.random.default_rng(86)
+    ring = np.zeros((n, n), dtype=np.int8)
+    for p in range(n):
+        q = (p + 1) % n
+        ring[p, q] = ring[q, p] = 1 if g.random() < 0.5 else -1
+    mixed = case.J.copy()
+    mixed[:10, :] = 0  # rows with no couplings
+    mixed[:, :10] = 0
+    for J in (ring, mixed):
+        case.J = J
+        a = run(case, ell_dev(J)).cpu().numpy()
+        b = run(case, ell_dev(J, width=4)).cpu().numpy()
+        assert np.array_equal(a, b)
+        xo = oracle.ode_run(J, case.pump, case.x0, steps=case.steps, alpha=case.alpha, **case.params())
+        assert np.abs(a - xo).max() <= 1e-4
+
+
 def test_sparse_padding_precision_forms_and_dense_agreement():
     n, d, r = 96, 2, 32
     case = Case(n, d, r, 300, key=(82,), kind="reg3", sigma=0.05)
