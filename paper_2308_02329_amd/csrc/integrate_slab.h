@@ -27,11 +27,12 @@
 // (a quarter, or half, of the bf16 bytes).  A single problem's J stays bf16
 // (k_integrate_slab).
 //
-// Per step: for each group of four owned tiles, accumulate G over all
-// chunks (the J fragments of the next chunk are fetched while the current
-// chunk's matrix-core work runs), then apply the fused Euler update to those
-// tiles in registers; after a barrier every wavefront writes its tiles' new
-// operand terms to LDS, and a second barrier publishes them.
+// Per step: for each group of owned tiles (one to eight, by block size and
+// D), accumulate G over all chunks (the J fragments of the next chunk are
+// fetched while the current chunk's matrix-core work runs), then apply the
+// fused Euler update to those tiles in registers; after a barrier every
+// wavefront writes its tiles' new operand terms to LDS, and a second barrier
+// publishes them.
 //
 // Component passes (the float32 form at large N, whose three-term operand of
 // all D components exceeds LDS): LDS holds one component's operand, and a
